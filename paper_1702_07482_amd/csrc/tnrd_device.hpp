@@ -1,0 +1,90 @@
+// Device helpers shared by the stage kernels of libtnrd (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tnrd {
+
+// Half-sample symmetric reflection into [0, n) for -n <= q < 2n:
+// -1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2 (the border extension of K).
+__device__ __forceinline__ int reflect(int q, int n)
+{
+    q = q < 0 ? -q - 1 : q;
+    return q >= n ? 2 * n - 1 - q : q;
+}
+
+// Reflect, then clamp: a safe index for any q (used where the value is
+// discarded anyway, e.g. responses of positions outside the image).
+__device__ __forceinline__ int reflect_clamp(int q, int n)
+{
+    q = reflect(q, n);
+    return q < 0 ? 0 : (q >= n ? n - 1 : q);
+}
+
+// RBF grid constants, precomputed on the host for the Gaussian influence
+// function phi(z) = sum_j w_j exp(-(z - mu_j)^2 / (2 sigma^2)), mu_j = mu0 + j*step.
+struct RbfGrid {
+    float mu0;       // first centre
+    float inv_step;  // 1 / step
+    float neg_half_inv_var;  // -1 / (2 sigma^2)
+    float step;
+    int nrbf;
+    int window;      // 0: all terms; w > 0: the 2w+1 centres nearest to z
+};
+
+// Direct windowed evaluation: one exp per term.
+__device__ __forceinline__ float rbf_phi_direct(float z, const float *__restrict__ w,
+                                                const RbfGrid &g)
+{
+    int lo = 0, hi = g.nrbf - 1;
+    if (g.window > 0) {
+        int j0 = __float2int_rn((z - g.mu0) * g.inv_step);  // saturating; NaN -> 0
+        j0 = min(max(j0, -g.window), g.nrbf - 1 + g.window);
+        lo = max(lo, j0 - g.window);
+        hi = min(hi, j0 + g.window);
+    }
+    float acc = 0.f;
+    for (int j = lo; j <= hi; ++j) {
+        float d = z - (g.mu0 + (float)j * g.step);
+        acc = fmaf(w[j], __expf(d * d * g.neg_half_inv_var), acc);
+    }
+    return acc;
+}
+
+// phi and phi' together (phi'(z) = sum_j w_j * (-(z - mu_j)/sigma^2) * G_j(z)).
+__device__ __forceinline__ void rbf_phi_dphi_direct(float z, const float *__restrict__ w,
+                                                    const RbfGrid &g, float &phi, float &dphi)
+{
+    int lo = 0, hi = g.nrbf - 1;
+    if (g.window > 0) {
+        int j0 = __float2int_rn((z - g.mu0) * g.inv_step);  // saturating; NaN -> 0
+        j0 = min(max(j0, -g.window), g.nrbf - 1 + g.window);
+        lo = max(lo, j0 - g.window);
+        hi = min(hi, j0 + g.window);
+    }
+    float a = 0.f, b = 0.f;
+    for (int j = lo; j <= hi; ++j) {
+        float d = z - (g.mu0 + (float)j * g.step);
+        float G = w[j] * __expf(d * d * g.neg_half_inv_var);
+        a += G;
+        b = fmaf(G, d, b);
+    }
+    phi = a;
+    dphi = b * (2.f * g.neg_half_inv_var);  // -(z - mu)/sigma^2 = 2 * d * (-1/(2 sigma^2))
+}
+
+// Closed-form prox of lambda <u^2 - 2 f^2 log u, 1>:
+//   u = (ut + s) / (2(1+2l)),  s = sqrt(ut^2 + 8(1+2l) l f^2).
+// For ut < 0 the same root is evaluated as c / ((s - ut) 2(1+2l)), c = 8(1+2l) l f^2,
+// which avoids the cancellation in ut + s ((ut + s)(s - ut) = c).
+__device__ __forceinline__ float prox(float ut, float f, float lam)
+{
+    float c1 = 1.f + 2.f * lam;
+    float c = 8.f * c1 * lam * f * f;
+    float s = sqrtf(fmaf(ut, ut, c));
+    float num = ut >= 0.f ? (ut + s) : c / (s - ut);
+    return num / (2.f * c1);
+}
+
+}  // namespace tnrd

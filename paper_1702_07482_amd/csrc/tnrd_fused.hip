@@ -1,0 +1,390 @@
+// Fused forward stage: one kernel per stage computes, for a tile of output
+// pixels,
+//
+//   z_i = K_i u        filter bank as an implicit GEMM on MFMA (v_mfma_f32_16x16x4_f32)
+//   v_i = phi_i(z_i)   Gaussian-RBF influence, windowed, on the vector ALUs
+//   Y   = K^T-GEMM     [taps x pixels] = [taps x filters] . [filters x pixels] on MFMA
+//   x   = col2im(Y)    shift-add of the tap columns (plus the reflected-border fold)
+//   u'  = prox(u - x)
+//
+// without writing the Nk response maps anywhere but registers and LDS.
+//
+// Tile geometry (R = (KS-1)/2): the workgroup owns an output tile of Th x Tw
+// pixels.  K^T needs v on the tile plus an R ring ("E region", Eh x Ew), and
+// z on E needs u on the tile plus a 2R ring (the u tile staged in LDS).  Each
+// wave takes whole E rows; a row is cut into NB blocks of 16 pixels, the N
+// dimension of every MFMA.  Pixels of a block that fall outside the image (or
+// beyond Ew) carry v = 0.
+//
+// GEMM layouts for v_mfma_f32_16x16x4_f32 (lane l, g = l / 16, j = l % 16):
+//   A operand  A[j][g]   (row j, k = g)
+//   B operand  B[g][j]
+//   D          D[4g + r][j] in accumulator register r
+// GEMM1: rows = filters (16 per m-block), k = taps (4 per k-step), cols = pixels.
+//   D gives lane l the responses of pixel j for filters 16 mb + 4 g + r.
+// GEMM2: rows = tap slots, k = filters, cols = pixels.  Its B operand for k-step
+//   (mb, r) is exactly GEMM1's D register r of m-block mb if k-row g of that
+//   step is taken to be filter 16 mb + 4 g + r, so the responses never move.
+//   Tap slot L (0..16*MB2-1) holds tap (a, b) = (L % KS, L / KS), arranged so
+//   that the four lane groups of one D register hold four different a.
+//
+// col2im: lane (g, j) of D register r of slot block mb2 holds Y for source
+// pixel (e, c) and tap (a, b); it belongs to output (e - a, c - b) in tile
+// coordinates.  It is added into P[e][a][c - b + 2R] (one plane per tap row a,
+// one row per source row e).  Within one LDS atomic the 64 lanes hit 64
+// distinct words (different a across groups, different c within a group), and
+// each P row is written by the one wave that owns E row e, in a fixed order,
+// so the result is deterministic.  After a barrier, X(y, x) = sum_a P[y+a][a][x+2R].
+//
+// The border fold (K^T is the exact adjoint of "reflect, then convolve"): an
+// output pixel within R of the image border also receives X at its mirror
+// position in the padded ring, which the tile's P already holds.
+#include "tnrd_device.hpp"
+#include "tnrd_internal.hpp"
+
+namespace tnrd {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int FUSED_THREADS = 256;
+constexpr int FUSED_WAVES = FUSED_THREADS / 64;
+constexpr int RBF_WIN = 6;                // Horner window half-width (13 centres)
+constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
+constexpr int NO_SLOT = -(1 << 20);     // col2im offset of an unused tap slot
+
+// Constants of the windowed Horner evaluation of phi.
+//   s = (z - mu0) / step = j0 + d, j0 the nearest centre, |d| <= 1/2,
+//   G_{j0+m}(z) = exp(-rho (d - m)^2 / 2), rho = (step / sigma)^2
+//              = exp(-rho d^2 / 2) * q^m * exp(-rho m^2 / 2),  q = exp(rho d)
+//   phi(z) = exp(-rho d^2 / 2 - rho W d) * sum_{n=0}^{2W} w_{j0-W+n} c_n q^n,
+//   c_n = exp(-rho (n - W)^2 / 2).
+struct FusedRbf {
+    float mu0_over_step;  // mu0 / step
+    float inv_step;       // 1 / step
+    float rho_log2e;      // rho * log2(e)
+    float jmax;           // Nrbf - 1 + W (largest clamped centre index)
+    float c[RBF_TERMS];
+};
+
+template <int KS>
+struct Geo {
+    static constexpr int R = KS / 2;
+    static constexpr int KK = KS * KS;
+    static constexpr int KS1 = (KK + 3) / 4;                         // GEMM1 k-steps
+    static constexpr int MB2 = (KK % 16 <= 1) ? KK / 16 : (KK + 15) / 16;  // GEMM2 slot blocks
+    static constexpr int VTAP = (KK > 16 * MB2) ? 1 : 0;             // leftover tap on the VALU
+};
+
+struct FusedLds {
+    int ldw;      // u tile row pitch
+    int u_off, u_size;
+    int t_off, t_pitch;   // RBF table
+    int p_off, pw, p_size;
+    int total;
+};
+
+__host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, int tw, int nrbf)
+{
+    const int R = ks / 2;
+    FusedLds l;
+    const int luh = th + 4 * R;
+    l.ldw = tw + 4 * R + 1;
+    l.u_off = 0;
+    l.u_size = luh * l.ldw;
+    l.t_pitch = nrbf + 4 * RBF_WIN + 1;
+    l.t_off = l.u_size;
+    const int eh = th + 2 * R;
+    l.pw = 16 * nb + 2 * R;
+    l.p_off = l.t_off + 16 * nmb * l.t_pitch;
+    l.p_size = eh * ks * l.pw;
+    l.total = l.p_off + l.p_size;
+    return l;
+}
+
+template <int KS, int NMB, int NB>
+__global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
+    const float *__restrict__ u_prev, const float *__restrict__ f, float *__restrict__ u_next,
+    int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
+    const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
+    FusedRbf rb, const float *__restrict__ lam_t)
+{
+    using G = Geo<KS>;
+    constexpr int R = G::R, KK = G::KK, KS1 = G::KS1, MB2 = G::MB2;
+    constexpr int KS2 = 4 * NMB;  // GEMM2 k-steps (4 filters each)
+
+    extern __shared__ float lds[];
+    const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf);
+    float *su = lds + L.u_off;
+    float *stab = lds + L.t_off;
+    float *sp = lds + L.p_off;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+
+    const int img = blockIdx.x / tiles_per_img;
+    const int trem = blockIdx.x - img * tiles_per_img;
+    const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
+    const int ty0 = ty * Th, tx0 = tx * Tw;
+    const size_t plane = (size_t)H * W;
+    const float *un = u_prev + img * plane;
+
+    const int Eh = Th + 2 * R, Ew = Tw + 2 * R;
+    const int luh = Th + 4 * R, luw = Tw + 4 * R;
+
+    // ---- stage the u tile (rows ty0-2R .. ty0+Th+2R-1), reflected at the border
+    for (int i = tid; i < luh * luw; i += FUSED_THREADS) {
+        int ly = i / luw, lx = i - ly * luw;
+        int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
+        su[ly * L.ldw + lx] = un[(size_t)yy * W + xx];
+    }
+    // ---- RBF weight table, zero padded by 2W on both sides of every row
+    for (int i = tid; i < 16 * NMB * L.t_pitch; i += FUSED_THREADS) {
+        int fi = i / L.t_pitch, jj = i - fi * L.t_pitch - 2 * RBF_WIN;
+        stab[i] = (fi < Nk && jj >= 0 && jj < Nrbf) ? rbfw[(size_t)fi * Nrbf + jj] : 0.f;
+    }
+    for (int i = tid; i < L.p_size; i += FUSED_THREADS) sp[i] = 0.f;
+
+    // ---- filter operands in registers
+    float a1[NMB][KS1];
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+        for (int s = 0; s < KS1; ++s) {
+            int fi = 16 * mb + j, t = 4 * s + g;
+            a1[mb][s] = (fi < Nk && t < KK) ? filt[(size_t)fi * KK + t] : 0.f;
+        }
+    float a2[MB2][KS2];
+#pragma unroll
+    for (int mb2 = 0; mb2 < MB2; ++mb2)
+#pragma unroll
+        for (int s = 0; s < KS2; ++s) {
+            int fi = 16 * (s >> 2) + 4 * g + (s & 3);
+            int Ls = 16 * mb2 + 4 * (j & 3) + (j >> 2);  // slot of A row j
+            int ta = Ls % KS, tb = Ls / KS;
+            a2[mb2][s] = (fi < Nk && Ls < KK) ? filt[(size_t)fi * KK + ta * KS + tb] : 0.f;
+        }
+    float av[NMB][4];  // leftover tap (KS-1, KS-1) when 16*MB2 == KK-1
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int fi = 16 * mb + 4 * g + r;
+            av[mb][r] = (G::VTAP && fi < Nk) ? filt[(size_t)fi * KK + KK - 1] : 0.f;
+        }
+    // GEMM1 B-operand offsets: tap t = 4 s + g -> (a, b) = (t / KS, t % KS)
+    int off1[KS1];
+#pragma unroll
+    for (int s = 0; s < KS1; ++s) {
+        int t = 4 * s + g;
+        off1[s] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+    }
+    // col2im target offsets into P: a * pw - b for the slot of each D register
+    int off2[MB2][4];
+#pragma unroll
+    for (int mb2 = 0; mb2 < MB2; ++mb2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int Ls = 16 * mb2 + 4 * r + g;
+            off2[mb2][r] = Ls < KK ? (Ls % KS) * L.pw - (Ls / KS) : NO_SLOT;
+        }
+    __syncthreads();
+
+    const float lam = lam_t[0];
+    for (int e = wave; e < Eh; e += FUSED_WAVES) {
+        const int yi = ty0 - R + e;
+        if (yi < 0 || yi >= H) continue;  // rows outside the image contribute v = 0
+        float *prow = sp + e * KS * L.pw + 2 * R;
+#pragma unroll 1
+        for (int cb = 0; cb < NB; ++cb) {
+            const int c = 16 * cb + j;
+            const int xi = tx0 - R + c;
+            const bool valid = (c < Ew) && (xi >= 0) && (xi < W);
+            const int cc = c < Ew ? c : Ew - 1;
+            const float *ub = su + (e + 2 * R) * L.ldw + cc + 2 * R;
+
+            // GEMM1: z = K u
+            floatx4 acc1[NMB];
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) acc1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS1; ++s) {
+                float bv = ub[-off1[s]];
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+                    acc1[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], bv, acc1[mb], 0, 0, 0);
+            }
+
+            // influence: v = phi(z), lane-local (pixel j, filters 16 mb + 4 g + r)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float z = acc1[mb][r];
+                    float s = fmaf(z, rb.inv_step, -rb.mu0_over_step);
+                    float jr = fminf(fmaxf(rintf(s), -(float)RBF_WIN), rb.jmax);
+                    float d = s - jr;
+                    const float *w = stab + (16 * mb + 4 * g + r) * L.t_pitch + (int)jr + RBF_WIN;
+                    float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
+                    float E = __builtin_amdgcn_exp2f(-rb.rho_log2e * d * fmaf(0.5f, d, (float)RBF_WIN));
+                    float acc = w[2 * RBF_WIN] * rb.c[2 * RBF_WIN];
+#pragma unroll
+                    for (int n = 2 * RBF_WIN - 1; n >= 0; --n) acc = fmaf(acc, q, w[n] * rb.c[n]);
+                    float v = E * acc;
+                    acc1[mb][r] = (valid && fabsf(d) <= 0.5f) ? v : 0.f;
+                }
+
+            // GEMM2: Y = K^T-slots . v
+            floatx4 acc2[MB2];
+#pragma unroll
+            for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int mb2 = 0; mb2 < MB2; ++mb2)
+                        acc2[mb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[mb2][4 * mb + r],
+                                                                         acc1[mb][r], acc2[mb2], 0, 0, 0);
+
+            // col2im into P (row e, planes a, columns c - b + 2R)
+#pragma unroll
+            for (int mb2 = 0; mb2 < MB2; ++mb2)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (off2[mb2][r] != NO_SLOT) atomicAdd(prow + c + off2[mb2][r], acc2[mb2][r]);
+            if (G::VTAP) {
+                float part = 0.f;
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) part = fmaf(av[mb][r], acc1[mb][r], part);
+                part += __shfl_xor(part, 16);
+                part += __shfl_xor(part, 32);
+                if (g == 0) atomicAdd(prow + c + (KS - 1) * L.pw - (KS - 1), part);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- gather X, fold the border ring, prox, store
+    const float *fn = f + img * plane;
+    float *uo = u_next + img * plane;
+    for (int i = tid; i < Th * Tw; i += FUSED_THREADS) {
+        const int y = i / Tw, x = i - (i / Tw) * Tw;
+        const int yi = ty0 + y, xi = tx0 + x;
+        if (yi >= H || xi >= W) continue;
+        int qy[2] = {y, 0}, qx[2] = {x, 0};
+        int nqy = 1, nqx = 1;
+        if (yi < R) qy[nqy++] = -yi - 1 - ty0;
+        else if (yi >= H - R) qy[nqy++] = 2 * H - 1 - yi - ty0;
+        if (xi < R) qx[nqx++] = -xi - 1 - tx0;
+        else if (xi >= W - R) qx[nqx++] = 2 * W - 1 - xi - tx0;
+        float xs = 0.f;
+        for (int iy = 0; iy < nqy; ++iy)
+            for (int ix = 0; ix < nqx; ++ix) {
+                const int col = qx[ix] + 2 * R;
+#pragma unroll
+                for (int a = 0; a < KS; ++a) {
+                    const int e = qy[iy] + a;
+                    if (e >= 0 && e < Eh) xs += sp[(e * KS + a) * L.pw + col];
+                }
+            }
+        const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
+        const size_t p = (size_t)yi * W + xi;
+        uo[p] = prox(uv - xs, fn[p], lam);
+    }
+}
+
+// ------------------------------------------------------------------ host side
+template <int KS, int NMB, int NB>
+static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t stream)
+{
+    const int R = KS / 2;
+    FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf);
+    size_t lds_bytes = (size_t)L.total * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        // raise the dynamic LDS limit to the CU's 160 KB; a failure here shows
+        // up as a launch error below, so the status is cleared
+        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    (void)R;
+    FusedRbf rb;
+    const double step = s.grid.step;
+    const double sigma = 1.0 / sqrt(-2.0 * (double)s.grid.neg_half_inv_var);
+    const double rho = (step / sigma) * (step / sigma);
+    rb.mu0_over_step = (float)(s.grid.mu0 / step);
+    rb.inv_step = (float)(1.0 / step);
+    rb.rho_log2e = (float)(rho * 1.4426950408889634);
+    rb.jmax = (float)(s.grid.nrbf - 1 + RBF_WIN);
+    for (int n = 0; n < RBF_TERMS; ++n) {
+        double m = n - RBF_WIN;
+        rb.c[n] = (float)exp(-rho * m * m / 2.0);
+    }
+    const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
+    const int tiles = tiles_x * tiles_y;
+    dim3 grid(tiles * s.N);
+    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB>), grid, dim3(FUSED_THREADS), lds_bytes, stream,
+                       s.u_prev, s.f, s.u_next, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk,
+                       s.rbfw, s.grid.nrbf, rb, s.lam);
+    return hipGetLastError();
+}
+
+// Default tile: widest row blocking that keeps the width, height about 32.
+static void fused_tile(int ks, int H, int W, int req_h, int req_w, int &th, int &tw, int &nb)
+{
+    const int R = ks / 2;
+    tw = req_w > 0 ? req_w : 32;
+    th = req_h > 0 ? req_h : 32;
+    if (tw > W) tw = W;
+    if (th > H) th = H;
+    nb = (tw + 2 * R + 15) / 16;
+}
+
+template <int KS, int NMB>
+static hipError_t fused_nb(const StageArgs &s, int th, int tw, int nb, hipStream_t stream)
+{
+    switch (nb) {
+    case 2: return launch_fused<KS, NMB, 2>(s, th, tw, stream);
+    case 3: return launch_fused<KS, NMB, 3>(s, th, tw, stream);
+    case 4: return launch_fused<KS, NMB, 4>(s, th, tw, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool fused_supported(int ks, int nk, int nrbf, int window, int prec)
+{
+    if (prec != 0) return false;
+    if (ks != 5 && ks != 7) return false;
+    if (nk < 1 || nk > 48) return false;
+    if (window != RBF_WIN) return false;
+    if (nrbf < 1 || nrbf > 200) return false;
+    return true;
+}
+
+size_t fused_scratch_floats(int, int, int, int, int) { return 0; }
+
+hipError_t fused_stage(const StageArgs &s, hipStream_t stream)
+{
+    int th, tw, nb;
+    fused_tile(s.ks, s.H, s.W, s.tile_h, s.tile_w, th, tw, nb);
+    if (nb < 2) nb = 2;
+    if (nb > 4) return hipErrorInvalidValue;
+    const int nmb = (s.Nk + 15) / 16;
+    if (s.ks == 7) {
+        if (nmb <= 2) return fused_nb<7, 2>(s, th, tw, nb, stream);
+        return fused_nb<7, 3>(s, th, tw, nb, stream);
+    }
+    if (s.ks == 5) {
+        if (nmb <= 2) return fused_nb<5, 2>(s, th, tw, nb, stream);
+        return fused_nb<5, 3>(s, th, tw, nb, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tnrd

@@ -1,0 +1,35 @@
+// Internal interfaces between the host API (tnrd_api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tnrd_device.hpp"
+
+namespace tnrd {
+
+// One forward stage over N equally sized images.
+struct StageArgs {
+    const float *u_prev;  // [N][H][W] u_{t-1}
+    const float *f;       // [N][H][W]
+    float *u_next;        // [N][H][W] u_t
+    int N, H, W;
+    int ks, Nk;
+    const float *filt;    // [Nk][ks*ks] stage t
+    const float *rbfw;    // [Nk][Nrbf] stage t
+    const float *lam;     // &lambda[t]
+    RbfGrid grid;
+    float *scratch;       // implementation scratch (split: Nk response maps)
+    int prec;             // tnrd_prec
+    int tile_h, tile_w;   // 0 = automatic
+};
+
+hipError_t split_stage(const StageArgs &s, hipStream_t stream);
+size_t split_scratch_floats(int N, int H, int W, int Nk);
+
+hipError_t fused_stage(const StageArgs &s, hipStream_t stream);
+bool fused_supported(int ks, int Nk, int nrbf, int window, int prec);
+size_t fused_scratch_floats(int N, int H, int W, int Nk, int prec);
+
+}  // namespace tnrd

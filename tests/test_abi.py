@@ -1,0 +1,112 @@
+"""The C-ABI library loads, exports every entry point its header declares, and
+rejects bad arguments on the host before anything touches a GPU.
+
+No call here reaches a kernel: every call has an argument error (or N = 0),
+which the library reports before it enqueues anything.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1702_07482_amd import tnrd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tnrd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnrd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = tnrd.load()
+    names = _declared()
+    assert {"tnrd_forward", "tnrd_backward", "tnrd_forward_batched"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert {s[0] for s in tnrd.SIGNATURES} == set(names)
+
+
+def _model(T=2, Nk=4, ks=5, Nrbf=63, L=0, step=10.0, sigma=10.0):
+    fake = 0x10000  # never dereferenced: every call below fails its host checks
+    return tnrd.TnrdModel(T, Nk, ks, Nrbf, L, -310.0, step, sigma, fake, fake, fake)
+
+
+FAKE_F = ctypes.c_void_p(0x20000)
+FAKE_U = ctypes.c_void_p(0x30000)
+
+
+def _fwd(m, N=1, H=32, W=32, L=1, f=FAKE_F, u=FAKE_U, ws=None, nb=0, **opt):
+    o = tnrd.default_opts(**opt)
+    lib = tnrd.load()
+    return lib.tnrd_forward(f, N, H, W, L, ctypes.byref(m), u, None, ctypes.byref(o), ws, nb, None)
+
+
+def test_default_opts():
+    o = tnrd.default_opts()
+    assert (o.prec, o.impl, o.rbf_window, o.recompute_every, o.validate) == (0, 0, -1, 1, 0)
+
+
+@pytest.mark.parametrize("kw,bad", [
+    (dict(ks=4), tnrd.TNRD_ERR_ARG),
+    (dict(ks=9), tnrd.TNRD_ERR_UNSUPPORTED),
+    (dict(T=0), tnrd.TNRD_ERR_ARG),
+    (dict(Nk=0), tnrd.TNRD_ERR_ARG),
+    (dict(Nrbf=0), tnrd.TNRD_ERR_ARG),
+    (dict(Nrbf=256), tnrd.TNRD_ERR_ARG),
+    (dict(sigma=0.0), tnrd.TNRD_ERR_ARG),
+    (dict(step=-1.0), tnrd.TNRD_ERR_ARG),
+    (dict(sigma=float("nan")), tnrd.TNRD_ERR_ARG),
+    (dict(L=4), tnrd.TNRD_ERR_ARG),  # model for L = 4, image has L = 1
+])
+def test_model_errors(kw, bad):
+    assert _fwd(_model(**kw)) == bad
+
+
+def test_image_errors():
+    m = _model()
+    assert _fwd(m, f=None) == tnrd.TNRD_ERR_ARG
+    assert _fwd(m, u=None) == tnrd.TNRD_ERR_ARG
+    assert _fwd(m, u=FAKE_F) == tnrd.TNRD_ERR_ARG          # output aliases input
+    assert _fwd(m, N=-1) == tnrd.TNRD_ERR_ARG
+    assert _fwd(m, H=4) == tnrd.TNRD_ERR_ARG                # smaller than the filter
+    assert _fwd(m, W=3) == tnrd.TNRD_ERR_ARG
+    assert _fwd(m, L=0) == tnrd.TNRD_ERR_ARG
+    assert _fwd(m, prec=7) == tnrd.TNRD_ERR_ARG
+    assert _fwd(m, impl=9) == tnrd.TNRD_ERR_ARG
+    lib = tnrd.load()
+    mnull = tnrd.TnrdModel(2, 4, 5, 63, 0, -310.0, 10.0, 10.0, None, 0x1, 0x1)
+    assert _fwd(mnull) == tnrd.TNRD_ERR_ARG
+    assert lib.tnrd_forward(FAKE_F, 1, 32, 32, 1, None, FAKE_U, None, None, None, 0, None) == tnrd.TNRD_ERR_ARG
+
+
+def test_workspace_checks_happen_before_any_launch():
+    m = _model()
+    o = tnrd.default_opts()
+    need = tnrd.tnrd_workspace_bytes(1, 32, 32, m, o, 0)
+    assert need > 0
+    assert _fwd(m) == tnrd.TNRD_ERR_WORKSPACE
+    assert _fwd(m, ws=ctypes.c_void_p(0x40000), nb=need - 1) == tnrd.TNRD_ERR_WORKSPACE
+    assert tnrd.tnrd_workspace_bytes(1, 3, 32, m, o, 0) == 0
+
+
+def test_empty_batch_is_a_no_op():
+    assert _fwd(_model(), N=0) == tnrd.TNRD_OK
+
+
+def test_num_checkpoints():
+    assert tnrd.tnrd_num_checkpoints(8, 1) == 9
+    assert tnrd.tnrd_num_checkpoints(8, 0) == 9
+    assert tnrd.tnrd_num_checkpoints(8, 4) == 3   # u_0, u_4, u_8
+    assert tnrd.tnrd_num_checkpoints(8, 3) == 4   # u_0, u_3, u_6, u_8
+    assert tnrd.tnrd_num_checkpoints(5, 8) == 2   # u_0, u_5
+
+
+def test_status_strings():
+    for st in [0, -1, -2, -3, -4, -5]:
+        assert tnrd.status_str(st) and tnrd.status_str(st) != "unknown status"
+    assert tnrd.status_str(12) == "unknown status"
