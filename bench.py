@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--impl", default="auto", choices=["auto", "fused", "split"])
     ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a kernel of known "
+                         "traffic, to scale HBM counters)")
     ap.add_argument("--cpu-rows", type=int, default=512,
                     help="rows of the 512-wide strip the oracle baseline runs on")
     return ap.parse_args()
@@ -156,6 +159,14 @@ def main():
     if impl_code == tnrd.IMPL_AUTO:
         impl_code = resolve_auto_impl()
     legs = set(args.legs.split(","))
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     fwd = leg_forward(args, impl_code)
     out = {

@@ -95,6 +95,7 @@ typedef struct tnrd_opts {
     int32_t validate;     /* nonzero: check f > 0 and finite on the device first (synchronises
                              `stream`; TNRD_ERR_DOMAIN on failure) */
     int32_t tile_h, tile_w; /* 0 = automatic; otherwise the fused kernel's output tile */
+    int32_t wg_waves;     /* fused kernel: wavefronts per workgroup, 4 or 8; 0 = automatic */
 } tnrd_opts;
 
 /* Fills `o` with the defaults (FP32, AUTO, automatic window, no checkpointing,

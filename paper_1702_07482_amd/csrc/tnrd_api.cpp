@@ -169,6 +169,7 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
     s.prec = o.prec;
     s.tile_h = o.tile_h;
     s.tile_w = o.tile_w;
+    s.waves = o.wg_waves;
     const float *cur = u_start;
     const size_t kk = (size_t)m->ksize * m->ksize;
     for (int t = t_begin; t < t_end; ++t) {

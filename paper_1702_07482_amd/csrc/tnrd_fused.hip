@@ -30,11 +30,12 @@
 //
 // col2im: lane (g, j) of D register r of slot block mb2 holds Y for source
 // pixel (e, c) and tap (a, b); it belongs to output (e - a, c - b) in tile
-// coordinates.  It is added into P[e][a][c - b + 2R] (one plane per tap row a,
-// one row per source row e).  Within one LDS atomic the 64 lanes hit 64
-// distinct words (different a across groups, different c within a group), and
-// each P row is written by the one wave that owns E row e, in a fixed order,
-// so the result is deterministic.  After a barrier, X(y, x) = sum_a P[y+a][a][x+2R].
+// coordinates.  Each wave writes the Y of its E row into a private scratch
+// Ys[c][slot] (plain 16-byte stores of the four D registers), then reduces
+// the row along x into P[e][a][qx + 2R] = sum_b Ys[qx + b][slot(a, b)] with
+// plain loads and stores: every P entry is written once, by the wave that
+// owns E row e, so the result is deterministic and no LDS atomics are needed.
+// After a barrier, X(y, x) = sum_a P[y + a][a][x + 2R].
 //
 // The border fold (K^T is the exact adjoint of "reflect, then convolve"): an
 // output pixel within R of the image border also receives X at its mirror
@@ -46,11 +47,8 @@ namespace tnrd {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int FUSED_THREADS = 256;
-constexpr int FUSED_WAVES = FUSED_THREADS / 64;
 constexpr int RBF_WIN = 6;                // Horner window half-width (13 centres)
 constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
-constexpr int NO_SLOT = -(1 << 20);     // col2im offset of an unused tap slot
 
 // Constants of the windowed Horner evaluation of phi.
 //   s = (z - mu0) / step = j0 + d, j0 the nearest centre, |d| <= 1/2,
@@ -80,10 +78,19 @@ struct FusedLds {
     int u_off, u_size;
     int t_off, t_pitch;   // RBF table
     int p_off, pw, p_size;
+    int y_off, yp, y_size;  // per-wave Y scratch: [16 nb][yp] floats per wave
     int total;
 };
 
-__host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, int tw, int nrbf)
+__host__ __device__ inline int fused_yp(int ks)
+{
+    const int kk = ks * ks;
+    const int mb2 = (kk % 16 <= 1) ? kk / 16 : (kk + 15) / 16;
+    return 16 * mb2 + 4;  // slots of the MFMA blocks + one for the leftover tap, 16 B aligned
+}
+
+__host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, int tw, int nrbf,
+                                              int nw)
 {
     const int R = ks / 2;
     FusedLds l;
@@ -97,12 +104,16 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     l.pw = 16 * nb + 2 * R;
     l.p_off = l.t_off + 16 * nmb * l.t_pitch;
     l.p_size = eh * ks * l.pw;
-    l.total = l.p_off + l.p_size;
+    if (l.p_size < 16 * nmb * ks * ks) l.p_size = 16 * nmb * ks * ks;  // also stages the filters
+    l.yp = fused_yp(ks);
+    l.y_off = (l.p_off + l.p_size + 3) & ~3;
+    l.y_size = nw * 16 * nb * l.yp;
+    l.total = l.y_off + l.y_size;
     return l;
 }
 
-template <int KS, int NMB, int NB>
-__global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
+template <int KS, int NMB, int NB, int NW>
+__global__ void __launch_bounds__(64 * NW) k_fused_stage(
     const float *__restrict__ u_prev, const float *__restrict__ f, float *__restrict__ u_next,
     int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
@@ -111,9 +122,11 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
     using G = Geo<KS>;
     constexpr int R = G::R, KK = G::KK, KS1 = G::KS1, MB2 = G::MB2;
     constexpr int KS2 = 4 * NMB;  // GEMM2 k-steps (4 filters each)
+    constexpr int FUSED_THREADS = 64 * NW;
+    constexpr int FUSED_WAVES = NW;
 
     extern __shared__ float lds[];
-    const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf);
+    const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW);
     float *su = lds + L.u_off;
     float *stab = lds + L.t_off;
     float *sp = lds + L.p_off;
@@ -132,27 +145,73 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
     const int Eh = Th + 2 * R, Ew = Tw + 2 * R;
     const int luh = Th + 4 * R, luw = Tw + 4 * R;
 
-    // ---- stage the u tile (rows ty0-2R .. ty0+Th+2R-1), reflected at the border
-    for (int i = tid; i < luh * luw; i += FUSED_THREADS) {
-        int ly = i / luw, lx = i - ly * luw;
-        int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
-        su[ly * L.ldw + lx] = un[(size_t)yy * W + xx];
+    // ---- prologue: every global load of a thread is issued before the first
+    // use, so the workgroup pays one memory latency, not one per element.
+    // (1) the stage's filters, staged through the P area of LDS
+    {
+        const int nf = Nk * KK;
+        float *sf = sp;
+        for (int base = 0; base < nf; base += 8 * FUSED_THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = filt[min(base + k * FUSED_THREADS + tid, nf - 1)];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (base + k * FUSED_THREADS + tid < nf) sf[base + k * FUSED_THREADS + tid] = v[k];
+        }
     }
-    // ---- RBF weight table, zero padded by 2W on both sides of every row
-    for (int i = tid; i < 16 * NMB * L.t_pitch; i += FUSED_THREADS) {
-        int fi = i / L.t_pitch, jj = i - fi * L.t_pitch - 2 * RBF_WIN;
-        stab[i] = (fi < Nk && jj >= 0 && jj < Nrbf) ? rbfw[(size_t)fi * Nrbf + jj] : 0.f;
+    // (2) the u tile (rows ty0-2R .. ty0+Th+2R-1), reflected at the border
+    {
+        const int n = luh * luw;
+        for (int base = 0; base < n; base += 8 * FUSED_THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int i = min(base + k * FUSED_THREADS + tid, n - 1);
+                int ly = i / luw, lx = i - ly * luw;
+                int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
+                v[k] = un[(size_t)yy * W + xx];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int i = base + k * FUSED_THREADS + tid;
+                if (i < n) {
+                    int ly = i / luw, lx = i - ly * luw;
+                    su[ly * L.ldw + lx] = v[k];
+                }
+            }
+        }
     }
-    for (int i = tid; i < L.p_size; i += FUSED_THREADS) sp[i] = 0.f;
+    // (3) RBF weight table, zero padded by 2W on both sides of every row
+    {
+        const int n = 16 * NMB * L.t_pitch;
+        const int nw = Nk * Nrbf;
+        for (int base = 0; base < n; base += 8 * FUSED_THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int i = base + k * FUSED_THREADS + tid;
+                int fi = i / L.t_pitch, jj = i - fi * L.t_pitch - 2 * RBF_WIN;
+                int src = min(max(fi * Nrbf + jj, 0), nw - 1);
+                float w = rbfw[src];
+                v[k] = (fi < Nk && jj >= 0 && jj < Nrbf) ? w : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (base + k * FUSED_THREADS + tid < n) stab[base + k * FUSED_THREADS + tid] = v[k];
+        }
+    }
+    __syncthreads();
 
-    // ---- filter operands in registers
+    // ---- filter operands in registers (from the staged copy)
+    const float *sf = sp;
     float a1[NMB][KS1];
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
         for (int s = 0; s < KS1; ++s) {
             int fi = 16 * mb + j, t = 4 * s + g;
-            a1[mb][s] = (fi < Nk && t < KK) ? filt[(size_t)fi * KK + t] : 0.f;
+            a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
         }
     float a2[MB2][KS2];
 #pragma unroll
@@ -162,7 +221,7 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
             int fi = 16 * (s >> 2) + 4 * g + (s & 3);
             int Ls = 16 * mb2 + 4 * (j & 3) + (j >> 2);  // slot of A row j
             int ta = Ls % KS, tb = Ls / KS;
-            a2[mb2][s] = (fi < Nk && Ls < KK) ? filt[(size_t)fi * KK + ta * KS + tb] : 0.f;
+            a2[mb2][s] = (fi < Nk && Ls < KK) ? sf[fi * KK + ta * KS + tb] : 0.f;
         }
     float av[NMB][4];  // leftover tap (KS-1, KS-1) when 16*MB2 == KK-1
 #pragma unroll
@@ -170,8 +229,10 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int fi = 16 * mb + 4 * g + r;
-            av[mb][r] = (G::VTAP && fi < Nk) ? filt[(size_t)fi * KK + KK - 1] : 0.f;
+            av[mb][r] = (G::VTAP && fi < Nk) ? sf[fi * KK + KK - 1] : 0.f;
         }
+    __syncthreads();  // the staged filters in the P area are consumed
+
     // GEMM1 B-operand offsets: tap t = 4 s + g -> (a, b) = (t / KS, t % KS)
     int off1[KS1];
 #pragma unroll
@@ -179,22 +240,13 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
         int t = 4 * s + g;
         off1[s] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
     }
-    // col2im target offsets into P: a * pw - b for the slot of each D register
-    int off2[MB2][4];
-#pragma unroll
-    for (int mb2 = 0; mb2 < MB2; ++mb2)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int Ls = 16 * mb2 + 4 * r + g;
-            off2[mb2][r] = Ls < KK ? (Ls % KS) * L.pw - (Ls / KS) : NO_SLOT;
-        }
     __syncthreads();
 
     const float lam = lam_t[0];
+    float *ys = lds + L.y_off + wave * (16 * NB * L.yp);
     for (int e = wave; e < Eh; e += FUSED_WAVES) {
         const int yi = ty0 - R + e;
-        if (yi < 0 || yi >= H) continue;  // rows outside the image contribute v = 0
-        float *prow = sp + e * KS * L.pw + 2 * R;
+        if (yi < 0 || yi >= H) continue;  // rows outside the image contribute v = 0 (never read)
 #pragma unroll 1
         for (int cb = 0; cb < NB; ++cb) {
             const int c = 16 * cb + j;
@@ -247,12 +299,11 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
                         acc2[mb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[mb2][4 * mb + r],
                                                                          acc1[mb][r], acc2[mb2], 0, 0, 0);
 
-            // col2im into P (row e, planes a, columns c - b + 2R)
+            // Y of this block into the wave's scratch: slots 16 mb2 + 4 g + r
+            float *yb = ys + c * L.yp;
 #pragma unroll
             for (int mb2 = 0; mb2 < MB2; ++mb2)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (off2[mb2][r] != NO_SLOT) atomicAdd(prow + c + off2[mb2][r], acc2[mb2][r]);
+                *reinterpret_cast<floatx4 *>(yb + 16 * mb2 + 4 * g) = acc2[mb2];
             if (G::VTAP) {
                 float part = 0.f;
 #pragma unroll
@@ -261,8 +312,24 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
                     for (int r = 0; r < 4; ++r) part = fmaf(av[mb][r], acc1[mb][r], part);
                 part += __shfl_xor(part, 16);
                 part += __shfl_xor(part, 32);
-                if (g == 0) atomicAdd(prow + c + (KS - 1) * L.pw - (KS - 1), part);
+                if (g == 0) yb[16 * MB2] = part;
             }
+        }
+        // x-direction col2im of the row: P[e][a][qx + 2R] = sum_b Ys[qx + b][slot(a, b)]
+        float *prow = sp + e * KS * L.pw;
+        for (int o = lane; o < KS * L.pw; o += 64) {
+            const int a = o / L.pw, colp = o - a * L.pw;
+            const int qx = colp - 2 * R;
+            float acc = 0.f;
+#pragma unroll
+            for (int b = 0; b < KS; ++b) {
+                const int c = qx + b;
+                const int Lt = a + KS * b;  // slot order of tap (a, b)
+                const int slot = Lt < 16 * MB2 ? 16 * (Lt >> 4) + 4 * (Lt & 3) + ((Lt & 15) >> 2)
+                                               : 16 * MB2;
+                if (c >= 0 && c < 16 * NB) acc += ys[c * L.yp + slot];
+            }
+            prow[o] = acc;
         }
     }
     __syncthreads();
@@ -287,7 +354,8 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
 #pragma unroll
                 for (int a = 0; a < KS; ++a) {
                     const int e = qy[iy] + a;
-                    if (e >= 0 && e < Eh) xs += sp[(e * KS + a) * L.pw + col];
+                    const int ye = ty0 - R + e;
+                    if (e >= 0 && e < Eh && ye >= 0 && ye < H) xs += sp[(e * KS + a) * L.pw + col];
                 }
             }
         const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
@@ -297,17 +365,17 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) k_fused_stage(
 }
 
 // ------------------------------------------------------------------ host side
-template <int KS, int NMB, int NB>
+template <int KS, int NMB, int NB, int NW>
 static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t stream)
 {
     const int R = KS / 2;
-    FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf);
+    FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf, NW);
     size_t lds_bytes = (size_t)L.total * sizeof(float);
     static bool attr_set = false;
     if (!attr_set) {
         // raise the dynamic LDS limit to the CU's 160 KB; a failure here shows
         // up as a launch error below, so the status is cleared
-        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB>,
+        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB, NW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         (void)hipGetLastError();
         attr_set = true;
@@ -329,7 +397,7 @@ static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     dim3 grid(tiles * s.N);
-    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB>), grid, dim3(FUSED_THREADS), lds_bytes, stream,
+    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW>), grid, dim3(64 * NW), lds_bytes, stream,
                        s.u_prev, s.f, s.u_next, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk,
                        s.rbfw, s.grid.nrbf, rb, s.lam);
     return hipGetLastError();
@@ -346,15 +414,22 @@ static void fused_tile(int ks, int H, int W, int req_h, int req_w, int &th, int 
     nb = (tw + 2 * R + 15) / 16;
 }
 
-template <int KS, int NMB>
+template <int KS, int NMB, int NW>
 static hipError_t fused_nb(const StageArgs &s, int th, int tw, int nb, hipStream_t stream)
 {
     switch (nb) {
-    case 2: return launch_fused<KS, NMB, 2>(s, th, tw, stream);
-    case 3: return launch_fused<KS, NMB, 3>(s, th, tw, stream);
-    case 4: return launch_fused<KS, NMB, 4>(s, th, tw, stream);
+    case 2: return launch_fused<KS, NMB, 2, NW>(s, th, tw, stream);
+    case 3: return launch_fused<KS, NMB, 3, NW>(s, th, tw, stream);
+    case 4: return launch_fused<KS, NMB, 4, NW>(s, th, tw, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int KS, int NMB>
+static hipError_t fused_nw(const StageArgs &s, int th, int tw, int nb, int nw, hipStream_t stream)
+{
+    if (nw == 4) return fused_nb<KS, NMB, 4>(s, th, tw, nb, stream);
+    return fused_nb<KS, NMB, 8>(s, th, tw, nb, stream);
 }
 
 bool fused_supported(int ks, int nk, int nrbf, int window, int prec)
@@ -375,14 +450,15 @@ hipError_t fused_stage(const StageArgs &s, hipStream_t stream)
     fused_tile(s.ks, s.H, s.W, s.tile_h, s.tile_w, th, tw, nb);
     if (nb < 2) nb = 2;
     if (nb > 4) return hipErrorInvalidValue;
+    const int nw = s.waves == 4 ? 4 : 8;
     const int nmb = (s.Nk + 15) / 16;
     if (s.ks == 7) {
-        if (nmb <= 2) return fused_nb<7, 2>(s, th, tw, nb, stream);
-        return fused_nb<7, 3>(s, th, tw, nb, stream);
+        if (nmb <= 2) return fused_nw<7, 2>(s, th, tw, nb, nw, stream);
+        return fused_nw<7, 3>(s, th, tw, nb, nw, stream);
     }
     if (s.ks == 5) {
-        if (nmb <= 2) return fused_nb<5, 2>(s, th, tw, nb, stream);
-        return fused_nb<5, 3>(s, th, tw, nb, stream);
+        if (nmb <= 2) return fused_nw<5, 2>(s, th, tw, nb, nw, stream);
+        return fused_nw<5, 3>(s, th, tw, nb, nw, stream);
     }
     return hipErrorInvalidValue;
 }

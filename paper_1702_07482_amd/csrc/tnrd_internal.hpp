@@ -23,6 +23,7 @@ struct StageArgs {
     float *scratch;       // implementation scratch (split: Nk response maps)
     int prec;             // tnrd_prec
     int tile_h, tile_w;   // 0 = automatic
+    int waves;            // fused: waves per workgroup (4 or 8; 0 = automatic)
 };
 
 hipError_t split_stage(const StageArgs &s, hipStream_t stream);

@@ -45,7 +45,7 @@ class TnrdOpts(ctypes.Structure):
     _fields_ = [
         ("prec", ctypes.c_int32), ("impl", ctypes.c_int32), ("rbf_window", ctypes.c_int32),
         ("recompute_every", ctypes.c_int32), ("validate", ctypes.c_int32),
-        ("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+        ("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
     ]
 
 
