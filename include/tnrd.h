@@ -88,9 +88,9 @@ typedef struct tnrd_model {
 typedef struct tnrd_opts {
     int32_t prec;         /* tnrd_prec */
     int32_t impl;         /* tnrd_impl */
-    int32_t rbf_window;   /* -1: automatic truncation window (dropped Gaussians < 1e-9 of
-                                 their weight), 0: every RBF term, w > 0: the 2w+1 centres
-                                 nearest to z */
+    int32_t rbf_window;   /* -1: automatic truncation window (every dropped Gaussian term is
+                                 below 1e-6 of its weight; 5 when rbf_step == rbf_sigma),
+                                 0: every RBF term, w > 0: the 2w+1 centres nearest to z */
     int32_t recompute_every; /* backward checkpointing, see tnrd_forward(states) */
     int32_t validate;     /* nonzero: check f > 0 and finite on the device first (synchronises
                              `stream`; TNRD_ERR_DOMAIN on failure) */
@@ -122,7 +122,8 @@ int tnrd_num_checkpoints(int T, int recompute_every);
  * Errors: TNRD_ERR_ARG for NULL f/u_out/m/parameter pointers, N < 0, H or W < ksize,
  * even ksize, T/Nk < 1, Nrbf outside 1..255, rbf_step or rbf_sigma <= 0 or not finite,
  * L < 1 or m->L not in {0, L}, u_out == f; TNRD_ERR_UNSUPPORTED for ksize not in
- * {3,5,7} or a precision the chosen implementation lacks; TNRD_ERR_WORKSPACE. */
+ * {3,5,7}, a precision the chosen implementation lacks, or a tile that does not fit
+ * the fused kernel's local memory; TNRD_ERR_WORKSPACE. */
 int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
                  float *u_out, float *states, const tnrd_opts *o,
                  void *ws, size_t ws_bytes, void *stream);

@@ -76,11 +76,12 @@ int rbf_window_for(const tnrd_model *m, int requested)
     if (requested == 0) return 0;
     int w = requested;
     if (requested < 0) {
-        // smallest w with exp(-rho (w + 1/2)^2 / 2) < 1e-9, rho = (step / sigma)^2:
-        // every dropped centre is at least w + 1/2 spacings from z.
+        // smallest w with exp(-rho (w + 1/2)^2 / 2) < 1e-6, rho = (step / sigma)^2:
+        // every dropped centre is at least w + 1/2 spacings from z, so each
+        // dropped Gaussian is below 1e-6 of its weight (w = 5 for step = sigma).
         double rho = (double)m->rbf_step / m->rbf_sigma;
         rho *= rho;
-        w = (int)ceil(sqrt(2.0 * 20.8 / rho) - 0.5);
+        w = (int)ceil(sqrt(2.0 * 13.82 / rho) - 0.5);
         if (w < 1) w = 1;
     }
     if (2 * w + 1 >= m->Nrbf) return 0;
@@ -237,6 +238,9 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
     int impl = choose_impl(m, oo, window);
     if (impl < 0) return impl;
     if (N == 0) return TNRD_OK;
+    if (impl == TNRD_IMPL_FUSED &&
+        !fused_config_ok(m->ksize, m->Nk, m->Nrbf, H, W, oo.tile_h, oo.tile_w, oo.wg_waves))
+        return TNRD_ERR_UNSUPPORTED;
     size_t need = forward_ws_bytes(N, H, W, m, oo, impl);
     if (!ws || ws_bytes < need) return TNRD_ERR_WORKSPACE;
 

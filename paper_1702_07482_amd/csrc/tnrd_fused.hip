@@ -47,7 +47,7 @@ namespace tnrd {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int RBF_WIN = 6;                // Horner window half-width (13 centres)
+constexpr int RBF_WIN = 5;                // Horner window half-width (11 centres)
 constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
 
 // Constants of the windowed Horner evaluation of phi.
@@ -403,7 +403,8 @@ static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     return hipGetLastError();
 }
 
-// Default tile: widest row blocking that keeps the width, height about 32.
+// Tile used when the caller does not pick one: 32 x 32 output pixels (three
+// 16-pixel blocks per E row for 7x7 filters), clamped to the image.
 static void fused_tile(int ks, int H, int W, int req_h, int req_w, int &th, int &tw, int &nb)
 {
     const int R = ks / 2;
@@ -430,6 +431,18 @@ static hipError_t fused_nw(const StageArgs &s, int th, int tw, int nb, int nw, h
 {
     if (nw == 4) return fused_nb<KS, NMB, 4>(s, th, tw, nb, stream);
     return fused_nb<KS, NMB, 8>(s, th, tw, nb, stream);
+}
+
+bool fused_config_ok(int ks, int nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves)
+{
+    int th, tw, nb;
+    fused_tile(ks, H, W, tile_h, tile_w, th, tw, nb);
+    if (nb < 2) nb = 2;
+    if (nb > 4 || th < ks / 2 || tw < ks / 2) return false;
+    const int nw = waves == 4 ? 4 : 8;
+    const int nmb = (nk + 15) / 16;
+    FusedLds L = fused_lds(ks, nmb <= 2 ? 2 : 3, nb, th, tw, nrbf, nw);
+    return (size_t)L.total * sizeof(float) <= 160 * 1024;
 }
 
 bool fused_supported(int ks, int nk, int nrbf, int window, int prec)

@@ -31,6 +31,7 @@ size_t split_scratch_floats(int N, int H, int W, int Nk);
 
 hipError_t fused_stage(const StageArgs &s, hipStream_t stream);
 bool fused_supported(int ks, int Nk, int nrbf, int window, int prec);
+bool fused_config_ok(int ks, int Nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves);
 size_t fused_scratch_floats(int N, int H, int W, int Nk, int prec);
 
 }  // namespace tnrd
