@@ -117,6 +117,62 @@ def leg_forward(args, impl_code):
     }
 
 
+def leg_fwd_bwd(args):
+    """16 x 180 x 180, forward keeping the states + hand-written backward."""
+    import torch
+    from paper_1702_07482_amd import synth, tnrd
+
+    N, H, W, T = 16, 180, 180, 8
+    m = synth.config_model(3)
+    pairs = [synth.make_pair(H, W, 1, config_id=3, index=i) for i in range(N)]
+    f = np.stack([p[1] for p in pairs])
+    ugt = np.stack([p[0] for p in pairs])
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd = torch.from_numpy(f).cuda().contiguous()
+    ud = torch.from_numpy(ugt).cuda().contiguous()
+    o = tnrd.default_opts()
+    mm = dm.abi()
+    nbf = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 0)
+    nbb = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 1)
+    if nbf == 0 or nbb == 0:
+        raise RuntimeError("unsupported configuration")
+    wsf = torch.empty(nbf, dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(nbb, dtype=torch.uint8, device="cuda")
+    u = torch.empty_like(fd)
+    states = torch.empty((T + 1, N, H, W), dtype=torch.float32, device="cuda")
+    g = torch.empty_like(fd)
+    dK = torch.empty_like(dm.filters)
+    dW = torch.empty_like(dm.rbf_w)
+    dl = torch.empty_like(dm.lam)
+
+    def step():
+        st = tnrd.tnrd_forward(fd, N, H, W, 1, mm, u, states, o, wsf, nbf)
+        if st != 0:
+            raise RuntimeError(tnrd.status_str(st))
+        torch.sub(u, ud, out=g)
+        g.mul_(2.0 / g.numel())
+        st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, o, wsb, nbb)
+        if st != 0:
+            raise RuntimeError(tnrd.status_str(st))
+
+    steps = max(3, args.steps // 5)
+    for _ in range(max(2, args.warmup // 5)):
+        step()
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"value": N * H * W * T / 1e6 / (ms / 1e3), "unit": "megapixel-stages/s",
+            "ms_per_step": ms, "steps": steps,
+            "workload": "forward (states kept) + backward, 16 x 180 x 180 FP32, L=1, 8 stages x "
+                        "48 7x7 filters, loss mean((u_T - u_gt)^2); gradients for all filters, "
+                        "RBF weights and lambda"}
+
+
 def resolve_auto_impl():
     """The implementation IMPL_AUTO runs for the headline workload."""
     import torch
@@ -184,6 +240,8 @@ def main():
         "roofline": fwd["roofline"],
         "min_ms_per_step": fwd["min_ms"],
     }
+    if "fwd_bwd" in legs:
+        out["fwd_bwd"] = leg_fwd_bwd(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fwd["f"], fwd["m"], args.cpu_rows)
     print(json.dumps(out), flush=True)

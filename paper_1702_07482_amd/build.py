@@ -18,7 +18,8 @@ LIB = os.path.join(PKG, "libtnrd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["tnrd_api.cpp", "tnrd_backward.cpp", "tnrd_split.hip", "tnrd_fused.hip"]
+SOURCES = ["tnrd_api.cpp", "tnrd_split.hip", "tnrd_fused.hip", "tnrd_backward.hip",
+           "tnrd_batched.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-x", "hip",

@@ -159,6 +159,8 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
                float *const *dst, float *scratch, hipStream_t stream)
 {
     StageArgs s;
+    s.u_cur = nullptr;
+    s.g_cur = nullptr;
     s.f = f;
     s.N = N;
     s.H = H;
@@ -239,7 +241,7 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
     if (impl < 0) return impl;
     if (N == 0) return TNRD_OK;
     if (impl == TNRD_IMPL_FUSED &&
-        !fused_config_ok(m->ksize, m->Nk, m->Nrbf, H, W, oo.tile_h, oo.tile_w, oo.wg_waves))
+        !fused_config_ok(m->ksize, m->Nk, m->Nrbf, H, W, oo.tile_h, oo.tile_w, oo.wg_waves, 0))
         return TNRD_ERR_UNSUPPORTED;
     size_t need = forward_ws_bytes(N, H, W, m, oo, impl);
     if (!ws || ws_bytes < need) return TNRD_ERR_WORKSPACE;

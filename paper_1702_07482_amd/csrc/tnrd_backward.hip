@@ -1,0 +1,693 @@
+// Backward pass of the T-stage filter (gradients for training, Sec. 3.2).
+//
+// Per stage t (from T down to 1), with g = dl/du_t and the states u_{t-1}, u_t:
+//
+//   y   = du_t/d(ut_t) = u_t^2 / ((1+2l) u_t^2 + 2 l f^2)        (eq. derv2 via the prox output)
+//   x_l = du_t/dl      = 2 (f^2 - u_t^2) / s,  s = (1+2l) u_t + 2 l f^2 / u_t   (eq. derv4)
+//   e   = y g
+//   z_i = K_i u_{t-1},  a_i = K_i e
+//   dl^t   = sum_p g x_l
+//   dW_ij  = - sum_p a_i G_j(z_i)
+//   dK_i   = - sum_p ( phi_i(z_i) ebar[p - d] + phi_i'(z_i) a_i ubar[p - d] )   (d = tap offset)
+//   g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)                  (transposed eq. derv1-1)
+//
+// Three kernels per stage, then one deterministic reduction:
+//   k_fused_stage<.., MODE_BWD_INPUT>  g_{t-1}  (tnrd_fused.hip)
+//   k_bwd_params   dK and dl partial sums per tile; exports z, a per pixel
+//   k_bwd_dw       dW partial sums from the exported z, a
+//   k_reduce_partials  fixed-order sums of the partials into the outputs
+//
+// k_bwd_params runs the filter-bank GEMM transposed (rows = 16 pixels,
+// columns = 16 filters), so its accumulator register r of lane (g, j) holds
+// pixel 4g + r and filter j.  That register is exactly the B operand of the
+// dK^T GEMM (rows = taps, k = pixels) for k-step r if k-row g of that step is
+// pixel 4g + r: v and phi'a go from the influence function straight into the
+// weight-gradient contraction without passing through LDS.
+//
+// k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms with one lane per
+// filter (each lane owns its row, each wave its histogram), so no two lanes
+// ever update the same word and no atomics are needed.
+#include <math.h>
+
+#include <vector>
+
+#include "tnrd.h"
+#include "tnrd_api_internal.hpp"
+#include "tnrd_device.hpp"
+#include "tnrd_fused_common.hpp"
+#include "tnrd_internal.hpp"
+
+namespace tnrd {
+
+constexpr int BP_TH = 32;   // k_bwd_params tile height
+constexpr int BP_NBW = 2;   // 16-pixel blocks per tile row (tile width 32)
+constexpr int BP_NW = 4;    // waves per workgroup
+constexpr int DW_NW = 8;    // k_bwd_dw waves per workgroup
+
+struct BwdParamsIO {
+    const float *u_prev;  // u_{t-1}
+    const float *u_cur;   // u_t
+    const float *f;
+    const float *g_cur;   // dl/du_t
+    float *zexp;          // [N*H*W][Nk] z = K u_{t-1}
+    float *aexp;          // [N*H*W][Nk] a = K e
+    float *dk_part;       // [tiles][Nk*KK]
+    float *dl_part;       // [tiles]
+};
+
+struct BpLds {
+    int ldw, tile_size, u_off, e_off, t_off, t_pitch, red_off, red_size, dl_off, total;
+};
+
+__host__ __device__ inline BpLds bp_lds(int ks, int nmb, int th, int tw, int nrbf, int nw)
+{
+    const int R = ks / 2;
+    BpLds l;
+    l.ldw = tw + 2 * R + 1;
+    l.tile_size = (th + 2 * R) * l.ldw;
+    l.u_off = 0;
+    l.e_off = l.tile_size;
+    l.t_pitch = nrbf + 4 * RBF_WIN + 1;
+    l.t_off = 2 * l.tile_size;
+    l.red_off = l.t_off + 16 * nmb * l.t_pitch;
+    l.red_size = 16 * nmb * ks * ks;
+    l.dl_off = l.red_off + l.red_size;
+    l.total = l.dl_off + nw;
+    return l;
+}
+
+// Horner evaluation of phi(z) and phi'(z) from the LDS weight table row.
+__device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__restrict__ row,
+                                                    const FusedRbf &rb, float &phi, float &dphi)
+{
+    float s = fmaf(z, rb.inv_step, -rb.mu0_over_step);
+    float jr = fminf(fmaxf(rintf(s), -(float)RBF_WIN), rb.jmax);
+    float d = s - jr;
+    const float *w = row + (int)jr + RBF_WIN;
+    float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
+    float E = __builtin_amdgcn_exp2f(-rb.rho_log2e * d * fmaf(0.5f, d, (float)RBF_WIN));
+    float acc = w[2 * RBF_WIN] * rb.c[2 * RBF_WIN];
+    float accd = 0.f;
+#pragma unroll
+    for (int n = 2 * RBF_WIN - 1; n >= 0; --n) {
+        accd = fmaf(accd, q, acc);
+        acc = fmaf(acc, q, w[n] * rb.c[n]);
+    }
+    const bool in = fabsf(d) <= 0.5f;
+    phi = in ? E * acc : 0.f;
+    dphi = in ? rb.rho_over_step * E * fmaf(q, accd, -(d + (float)RBF_WIN) * acc) : 0.f;
+}
+
+template <int KS, int NMB, int NBW, int NW>
+__global__ void __launch_bounds__(64 * NW) k_bwd_params(
+    BwdParamsIO io, int H, int W, int Th, int tiles_x, int tiles_per_img,
+    const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf, FusedRbf rb,
+    const float *__restrict__ lam_t)
+{
+    using G = Geo<KS>;
+    constexpr int R = G::R, KK = G::KK, KS1 = G::KS1, MB2 = G::MB2;
+    constexpr int THREADS = 64 * NW;
+    constexpr int Tw = 16 * NBW;
+
+    extern __shared__ float lds[];
+    const BpLds L = bp_lds(KS, NMB, Th, Tw, Nrbf, NW);
+    float *su = lds + L.u_off;
+    float *se = lds + L.e_off;
+    float *stab = lds + L.t_off;
+    float *red = lds + L.red_off;
+    float *sdl = lds + L.dl_off;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int img = blockIdx.x / tiles_per_img;
+    const int trem = blockIdx.x - img * tiles_per_img;
+    const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
+    const int ty0 = ty * Th, tx0 = tx * Tw;
+    const size_t plane = (size_t)H * W;
+    const float lam = lam_t[0];
+    const float c1 = 1.f + 2.f * lam, c2 = 2.f * lam;
+
+    // ---- prologue: filters (via red), u_{t-1} and e tiles with an R ring, weight table
+    {
+        const int nf = Nk * KK;
+        for (int base = 0; base < nf; base += 8 * THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = filt[min(base + k * THREADS + tid, nf - 1)];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (base + k * THREADS + tid < nf) red[base + k * THREADS + tid] = v[k];
+        }
+    }
+    float dl_acc = 0.f;
+    {
+        const float *un = io.u_prev + img * plane;
+        const float *uc = io.u_cur + img * plane;
+        const float *fn = io.f + img * plane;
+        const float *gn = io.g_cur + img * plane;
+        const int luh = Th + 2 * R, luw = Tw + 2 * R;
+        const int n = luh * luw;
+        for (int base = 0; base < n; base += 4 * THREADS) {
+            float uu[4], uv[4], ff[4], gg[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int i = min(base + k * THREADS + tid, n - 1);
+                int ly = i / luw, lx = i - ly * luw;
+                int yy = reflect_clamp(ty0 - R + ly, H), xx = reflect_clamp(tx0 - R + lx, W);
+                size_t q = (size_t)yy * W + xx;
+                uu[k] = un[q];
+                uv[k] = uc[q];
+                ff[k] = fn[q];
+                gg[k] = gn[q];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int i = base + k * THREADS + tid;
+                if (i < n) {
+                    int ly = i / luw, lx = i - ly * luw;
+                    float u2 = uv[k] * uv[k], f2 = ff[k] * ff[k];
+                    float den = fmaf(c1, u2, c2 * f2);  // u s
+                    su[ly * L.ldw + lx] = uu[k];
+                    se[ly * L.ldw + lx] = u2 / den * gg[k];
+                    // dl/dlambda over the tile's own pixels: g * 2 (f - u)(f + u) / s
+                    // (the factored difference keeps its precision when u ~ f)
+                    int yi = ty0 - R + ly, xi = tx0 - R + lx;
+                    bool own = ly >= R && ly < R + Th && lx >= R && lx < R + Tw && yi < H && xi < W;
+                    if (own)
+                        dl_acc = fmaf(gg[k], 2.f * (ff[k] - uv[k]) * (ff[k] + uv[k]) * uv[k] / den, dl_acc);
+                }
+            }
+        }
+    }
+    {
+        const int n = 16 * NMB * L.t_pitch;
+        const int nw = Nk * Nrbf;
+        for (int base = 0; base < n; base += 8 * THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int i = base + k * THREADS + tid;
+                int fi = i / L.t_pitch, jj = i - fi * L.t_pitch - 2 * RBF_WIN;
+                float w = rbfw[min(max(fi * Nrbf + jj, 0), nw - 1)];
+                v[k] = (fi < Nk && jj >= 0 && jj < Nrbf) ? w : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (base + k * THREADS + tid < n) stab[base + k * THREADS + tid] = v[k];
+        }
+    }
+    __syncthreads();
+
+    // filter bank as the B operand of the transposed GEMM: B[k=g][n=j] = k_{16 nb + j}[tap 4 s + g]
+    float bf[NMB][KS1];
+#pragma unroll
+    for (int nb = 0; nb < NMB; ++nb)
+#pragma unroll
+        for (int s = 0; s < KS1; ++s) {
+            int fi = 16 * nb + j, t = 4 * s + g;
+            bf[nb][s] = (fi < Nk && t < KK) ? red[fi * KK + t] : 0.f;
+        }
+    int off1[KS1];
+#pragma unroll
+    for (int s = 0; s < KS1; ++s) {
+        int t = 4 * s + g;
+        off1[s] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+    }
+    // dK^T GEMM rows: tap 16 mt + j
+    int offt[MB2];
+    bool tapok[MB2];
+#pragma unroll
+    for (int mt = 0; mt < MB2; ++mt) {
+        int t = 16 * mt + j;
+        tapok[mt] = t < KK;
+        offt[mt] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+    }
+    const int offv = ((KK - 1) / KS) * L.ldw + (KK - 1) % KS;  // leftover tap (VALU)
+
+    floatx4 dkt[MB2][NMB];
+#pragma unroll
+    for (int mt = 0; mt < MB2; ++mt)
+#pragma unroll
+        for (int nb = 0; nb < NMB; ++nb) dkt[mt][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float acc48[NMB];
+#pragma unroll
+    for (int nb = 0; nb < NMB; ++nb) acc48[nb] = 0.f;
+
+    for (int y = wave; y < Th; y += NW) {
+        const int yi = ty0 + y;
+        if (yi >= H) break;
+#pragma unroll 1
+        for (int cb = 0; cb < NBW; ++cb) {
+            // transposed GEMM1: rows = pixels j of the block, columns = filters
+            const float *ubase = su + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
+            const float *ebase = se + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
+            floatx4 accz[NMB], acca[NMB];
+#pragma unroll
+            for (int nb = 0; nb < NMB; ++nb) {
+                accz[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                acca[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int s = 0; s < KS1; ++s) {
+                float bu = ubase[-off1[s]], be = ebase[-off1[s]];
+#pragma unroll
+                for (int nb = 0; nb < NMB; ++nb) {
+                    accz[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bu, bf[nb][s], accz[nb], 0, 0, 0);
+                    acca[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(be, bf[nb][s], acca[nb], 0, 0, 0);
+                }
+            }
+            // influence, export, and the two dK operands (v, h) in place
+#pragma unroll
+            for (int nb = 0; nb < NMB; ++nb) {
+                const float *row = stab + (16 * nb + j) * L.t_pitch;
+                const int fi = 16 * nb + j;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int x = 16 * cb + 4 * g + r, xi = tx0 + x;
+                    const bool valid = xi < W;
+                    float z = accz[nb][r], a = acca[nb][r];
+                    float ph, dph;
+                    rbf_phi_dphi_horner(z, row, rb, ph, dph);
+                    if (valid && fi < Nk) {
+                        size_t pix = img * plane + (size_t)yi * W + xi;
+                        io.zexp[pix * Nk + fi] = z;
+                        io.aexp[pix * Nk + fi] = a;
+                    }
+                    accz[nb][r] = valid ? ph : 0.f;
+                    acca[nb][r] = valid ? dph * a : 0.f;
+                }
+            }
+            // dK^T GEMM: k-step r, k-row g = pixel 4 g + r
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = 16 * cb + 4 * g + r;
+                const int b2 = (y + 2 * R) * L.ldw + x + 2 * R;
+#pragma unroll
+                for (int mt = 0; mt < MB2; ++mt) {
+                    float ae = tapok[mt] ? se[b2 - offt[mt]] : 0.f;
+                    float au = tapok[mt] ? su[b2 - offt[mt]] : 0.f;
+#pragma unroll
+                    for (int nb = 0; nb < NMB; ++nb) {
+                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, accz[nb][r], dkt[mt][nb], 0, 0, 0);
+                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(au, acca[nb][r], dkt[mt][nb], 0, 0, 0);
+                    }
+                }
+                if (G::VTAP) {
+                    float ev = se[b2 - offv], uvv = su[b2 - offv];
+#pragma unroll
+                    for (int nb = 0; nb < NMB; ++nb)
+                        acc48[nb] = fmaf(accz[nb][r], ev, fmaf(acca[nb][r], uvv, acc48[nb]));
+                }
+            }
+        }
+    }
+
+    // ---- tile reduction of dK (waves in order) and dl
+    if (G::VTAP) {
+#pragma unroll
+        for (int nb = 0; nb < NMB; ++nb) {
+            acc48[nb] += __shfl_xor(acc48[nb], 16);
+            acc48[nb] += __shfl_xor(acc48[nb], 32);
+        }
+    }
+    __syncthreads();  // red (filter staging) is free again
+    for (int w = 0; w < NW; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int mt = 0; mt < MB2; ++mt)
+#pragma unroll
+                for (int nb = 0; nb < NMB; ++nb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        int t = 16 * mt + 4 * g + r, fi = 16 * nb + j;
+                        if (t < KK && !(G::VTAP && t == KK - 1)) {
+                            float *dst = red + fi * KK + t;
+                            *dst = (w == 0 ? 0.f : *dst) + dkt[mt][nb][r];
+                        }
+                    }
+            if (G::VTAP && g == 0) {
+#pragma unroll
+                for (int nb = 0; nb < NMB; ++nb) {
+                    float *dst = red + (16 * nb + j) * KK + KK - 1;
+                    *dst = (w == 0 ? 0.f : *dst) + acc48[nb];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // dl: wave sums, then the waves in order
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dl_acc += __shfl_xor(dl_acc, o);
+    if (lane == 0) sdl[wave] = dl_acc;
+    __syncthreads();
+    float *dkp = io.dk_part + (size_t)blockIdx.x * Nk * KK;
+    for (int i = tid; i < Nk * KK; i += THREADS) dkp[i] = red[i];
+    if (tid == 0) {
+        float sum = 0.f;
+        for (int w = 0; w < NW; ++w) sum += sdl[w];
+        io.dl_part[blockIdx.x] = sum;
+    }
+}
+
+// dW partial sums: lane = filter, each wave its own histogram of
+// Nk rows x (Nrbf + 4W + 1) bins (bin b stored at b + 2W).
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_bwd_dw(
+    const float *__restrict__ zexp, const float *__restrict__ aexp, long long P, long long per_wg,
+    int Nk, int Nrbf, FusedRbf rb, float *__restrict__ dw_part)
+{
+    extern __shared__ float lds[];
+    const int hb = Nrbf + 4 * RBF_WIN + 1;
+    const int hsize = Nk * hb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < NW * hsize; i += 64 * NW) lds[i] = 0.f;
+    __syncthreads();
+    float *hist = lds + wave * hsize + lane * hb + 2 * RBF_WIN;
+    const long long p0 = (long long)blockIdx.x * per_wg;
+    const long long p1 = min(P, p0 + per_wg);
+    if (lane < Nk) {
+        for (long long p = p0 + wave; p < p1; p += NW) {
+            const float z = zexp[p * Nk + lane], a = aexp[p * Nk + lane];
+            float s = fmaf(z, rb.inv_step, -rb.mu0_over_step);
+            float jr = fminf(fmaxf(rintf(s), -(float)RBF_WIN), rb.jmax);
+            float d = s - jr;
+            if (fabsf(d) > 0.5f) continue;  // beyond every centre by more than W spacings
+            // G_{jr+m} = E0 q^m c_m,  E0 = exp(-rho d^2/2),  q = exp(rho d)
+            float E0 = __builtin_amdgcn_exp2f(-0.5f * rb.rho_log2e * d * d);
+            float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
+            float qi = __builtin_amdgcn_exp2f(-rb.rho_log2e * d);
+            float *hrow = hist + (int)jr;
+            float up = a * E0, dn = a * E0;
+            hrow[0] += up * rb.c[RBF_WIN];
+#pragma unroll
+            for (int m = 1; m <= RBF_WIN; ++m) {
+                up *= q;
+                dn *= qi;
+                hrow[m] += up * rb.c[RBF_WIN + m];
+                hrow[-m] += dn * rb.c[RBF_WIN - m];
+            }
+        }
+    }
+    __syncthreads();
+    float *dst = dw_part + (size_t)blockIdx.x * Nk * Nrbf;
+    for (int i = tid; i < Nk * Nrbf; i += 64 * NW) {
+        int fi = i / Nrbf, jj = i - fi * Nrbf;
+        float sum = 0.f;
+        for (int w = 0; w < NW; ++w) sum += lds[w * hsize + fi * hb + 2 * RBF_WIN + jj];
+        dst[i] = sum;
+    }
+}
+
+// out[e] = scale * sum_k part[k * nelem + e].  A block owns 16 consecutive
+// elements; its 16 rows of threads sum interleaved subsets of k (row r takes
+// k = r, r + 16, ...) and the 16 row sums are then added in row order, so
+// the result does not depend on scheduling.
+constexpr int RED_E = 16, RED_R = 16;
+__global__ void __launch_bounds__(RED_E * RED_R) k_reduce_partials(
+    const float *__restrict__ part, int nparts, int nelem, float scale, float *__restrict__ out)
+{
+    __shared__ float rows[RED_R][RED_E];
+    const int te = threadIdx.x % RED_E, tr = threadIdx.x / RED_E;
+    const int e = blockIdx.x * RED_E + te;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    if (e < nelem) {
+        int k = tr;
+        for (; k + 3 * RED_R < nparts; k += 4 * RED_R) {
+            s0 += part[(size_t)k * nelem + e];
+            s1 += part[(size_t)(k + RED_R) * nelem + e];
+            s2 += part[(size_t)(k + 2 * RED_R) * nelem + e];
+            s3 += part[(size_t)(k + 3 * RED_R) * nelem + e];
+        }
+        for (; k < nparts; k += RED_R) s0 += part[(size_t)k * nelem + e];
+    }
+    rows[tr][te] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (tr == 0 && e < nelem) {
+        float s = 0.f;
+        for (int r = 0; r < RED_R; ++r) s += rows[r][te];
+        out[e] = scale * s;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+namespace {
+
+struct BwdGeom {
+    int tiles_x, tiles_y, tiles;   // k_bwd_params tiles (per image) and total
+    int dw_grid;
+    long long dw_per_wg;
+    size_t img;                    // N*H*W
+};
+
+BwdGeom bwd_geom(int N, int H, int W)
+{
+    BwdGeom gm;
+    const int tw = 16 * BP_NBW;
+    gm.tiles_x = (W + tw - 1) / tw;
+    gm.tiles_y = (H + BP_TH - 1) / BP_TH;
+    gm.tiles = gm.tiles_x * gm.tiles_y * N;
+    gm.img = (size_t)N * H * W;
+    long long P = (long long)gm.img;
+    long long grid = (P + 255) / 256;
+    if (grid > 1024) grid = 1024;
+    if (grid < 1) grid = 1;
+    gm.dw_per_wg = (P + grid - 1) / grid;
+    gm.dw_grid = (int)((P + gm.dw_per_wg - 1) / gm.dw_per_wg);
+    return gm;
+}
+
+constexpr size_t AL = 256;
+size_t al(size_t x) { return (x + AL - 1) / AL * AL; }
+
+struct BwdWs {
+    float *g[2], *zexp, *aexp, *dk_part, *dl_part, *dw_part, *seg;
+    size_t bytes;
+};
+
+BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s)
+{
+    BwdGeom gm = bwd_geom(N, H, W);
+    const size_t kk = (size_t)m->ksize * m->ksize;
+    BwdWs w;
+    size_t off = AL;  // flags
+    auto take = [&](size_t floats) {
+        float *p = base ? (float *)(base + off) : nullptr;
+        off += al(floats * sizeof(float));
+        return p;
+    };
+    w.g[0] = take(gm.img);
+    w.g[1] = take(gm.img);
+    w.zexp = take(gm.img * m->Nk);
+    w.aexp = take(gm.img * m->Nk);
+    w.dk_part = take((size_t)gm.tiles * m->Nk * kk);
+    w.dl_part = take((size_t)gm.tiles);
+    w.dw_part = take((size_t)gm.dw_grid * m->Nk * m->Nrbf);
+    w.seg = s > 1 ? take(gm.img * (size_t)(s + 1)) : nullptr;
+    w.bytes = off;
+    return w;
+}
+
+template <int KS, int NMB>
+hipError_t launch_bwd_params(const BwdParamsIO &io, int N, int H, int W, const float *filt, int Nk,
+                             const float *rbfw, const RbfGrid &grid, const float *lam,
+                             hipStream_t stream)
+{
+    BpLds L = bp_lds(KS, NMB, BP_TH, 16 * BP_NBW, grid.nrbf, BP_NW);
+    size_t lds_bytes = (size_t)L.total * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    BwdGeom gm = bwd_geom(N, H, W);
+    const int per_img = gm.tiles_x * gm.tiles_y;
+    FusedRbf rb = make_fused_rbf(grid);
+    hipLaunchKernelGGL((k_bwd_params<KS, NMB, BP_NBW, BP_NW>), dim3(gm.tiles), dim3(64 * BP_NW),
+                       lds_bytes, stream, io, H, W, BP_TH, gm.tiles_x, per_img, filt, Nk, rbfw,
+                       grid.nrbf, rb, lam);
+    return hipGetLastError();
+}
+
+hipError_t bwd_params(const BwdParamsIO &io, int N, int H, int W, int ks, const float *filt,
+                      int Nk, const float *rbfw, const RbfGrid &grid, const float *lam,
+                      hipStream_t stream)
+{
+    const int nmb = (Nk + 15) / 16;
+    if (ks == 7)
+        return nmb <= 2 ? launch_bwd_params<7, 2>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params<7, 3>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream);
+    if (ks == 5)
+        return nmb <= 2 ? launch_bwd_params<5, 2>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params<5, 3>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t bwd_dw(const float *zexp, const float *aexp, int N, int H, int W, int Nk,
+                  const RbfGrid &grid, float *dw_part, hipStream_t stream)
+{
+    BwdGeom gm = bwd_geom(N, H, W);
+    const size_t lds_bytes = (size_t)DW_NW * Nk * (grid.nrbf + 4 * RBF_WIN + 1) * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_bwd_dw<DW_NW>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    FusedRbf rb = make_fused_rbf(grid);
+    hipLaunchKernelGGL((k_bwd_dw<DW_NW>), dim3(gm.dw_grid), dim3(64 * DW_NW), lds_bytes, stream,
+                       zexp, aexp, (long long)gm.img, gm.dw_per_wg, Nk, grid.nrbf, rb, dw_part);
+    return hipGetLastError();
+}
+
+hipError_t reduce_partials(const float *part, int nparts, int nelem, float scale, float *out,
+                           hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3((nelem + RED_E - 1) / RED_E), dim3(RED_E * RED_R), 0,
+                       stream, part, nparts, nelem, scale, out);
+    return hipGetLastError();
+}
+
+bool bwd_lds_ok(const tnrd_model *m)
+{
+    const int nmb = (m->Nk + 15) / 16 <= 2 ? 2 : 3;
+    BpLds L = bp_lds(m->ksize, nmb, BP_TH, 16 * BP_NBW, m->Nrbf, BP_NW);
+    size_t dw = (size_t)DW_NW * m->Nk * (m->Nrbf + 4 * RBF_WIN + 1) * sizeof(float);
+    return (size_t)L.total * sizeof(float) <= 160 * 1024 && dw <= 160 * 1024;
+}
+
+}  // namespace
+
+size_t backward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int window)
+{
+    if (!fused_supported(m->ksize, m->Nk, m->Nrbf, window, o.prec) || !bwd_lds_ok(m)) return 0;
+    const int s = o.recompute_every < 1 ? 1 : o.recompute_every;
+    return bwd_ws_layout(nullptr, N, H, W, m, s).bytes;
+}
+
+}  // namespace tnrd
+
+using namespace tnrd;
+
+extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                             const float *states, const float *grad_uT, float *grad_filters,
+                             float *grad_rbf_w, float *grad_lambda, float *grad_u0,
+                             const tnrd_opts *o, void *ws, size_t ws_bytes, void *stream_)
+{
+    tnrd_opts oo;
+    resolve_opts(o, &oo);
+    int st = check_image_args(f, N, H, W, L, m, grad_uT);
+    if (st != TNRD_OK) return st;
+    if (!states || !grad_filters || !grad_rbf_w || !grad_lambda) return TNRD_ERR_ARG;
+    if (oo.prec < TNRD_PREC_FP32 || oo.prec > TNRD_PREC_FP16) return TNRD_ERR_ARG;
+    const int window = rbf_window_for(m, oo.rbf_window);
+    if (!fused_supported(m->ksize, m->Nk, m->Nrbf, window, oo.prec) || !bwd_lds_ok(m))
+        return TNRD_ERR_UNSUPPORTED;
+    // the input-gradient kernel uses its own tile; the forward tile options
+    // only steer the recomputation of checkpointed states
+    if (!fused_config_ok(m->ksize, m->Nk, m->Nrbf, H, W, 0, 0, 0, 1))
+        return TNRD_ERR_UNSUPPORTED;
+    const int T = m->T;
+    const int s = oo.recompute_every < 1 ? 1 : oo.recompute_every;
+    const size_t need = bwd_ws_layout(nullptr, N, H, W, m, s).bytes;
+    if (N > 0 && (!ws || ws_bytes < need)) return TNRD_ERR_WORKSPACE;
+    hipStream_t stream = (hipStream_t)stream_;
+    const size_t kk = (size_t)m->ksize * m->ksize;
+    if (N == 0) {
+        // empty batch: every gradient is zero
+        if (hipMemsetAsync(grad_filters, 0, (size_t)T * m->Nk * kk * sizeof(float), stream) != hipSuccess ||
+            hipMemsetAsync(grad_rbf_w, 0, (size_t)T * m->Nk * m->Nrbf * sizeof(float), stream) != hipSuccess ||
+            hipMemsetAsync(grad_lambda, 0, (size_t)T * sizeof(float), stream) != hipSuccess)
+            return TNRD_ERR_HIP;
+        return TNRD_OK;
+    }
+    BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s);
+    BwdGeom gm = bwd_geom(N, H, W);
+    const size_t img = gm.img;
+    if (oo.validate) {
+        st = run_domain_check(f, img, (int *)ws, stream);
+        if (st != TNRD_OK) return st;
+    }
+
+    // u_t for every t of the current checkpoint segment: stored states, or
+    // recomputed from the segment's first checkpoint into w.seg.
+    const int nck = tnrd_num_checkpoints(T, s);
+    std::vector<const float *> ut(T + 1, nullptr);
+    StageArgs ia;  // input-gradient stage arguments
+    ia.N = N;
+    ia.H = H;
+    ia.W = W;
+    ia.ks = m->ksize;
+    ia.Nk = m->Nk;
+    ia.f = f;
+    ia.grid = make_grid(m, window);
+    ia.scratch = nullptr;
+    ia.prec = oo.prec;
+    ia.tile_h = 0;
+    ia.tile_w = 0;
+    ia.waves = 0;
+
+    const float *g_cur = grad_uT;
+    int ping = 0;
+    int seg_hi = T;  // segment [seg_lo, seg_hi]
+    while (seg_hi > 0) {
+        const int seg_lo = ((seg_hi - 1) / s) * s;
+        // states of the segment
+        ut[seg_lo] = states + (size_t)(seg_lo / s) * img;
+        ut[seg_hi] = states + (size_t)(seg_hi == T ? nck - 1 : seg_hi / s) * img;
+        if (seg_hi - seg_lo > 1) {
+            // recompute u_{seg_lo+1} .. u_{seg_hi-1} with the forward kernel
+            std::vector<float *> dst(seg_hi - seg_lo - 1);
+            for (int t = seg_lo + 1; t < seg_hi; ++t) {
+                dst[t - seg_lo - 1] = w.seg + (size_t)(t - seg_lo) * img;
+                ut[t] = dst[t - seg_lo - 1];
+            }
+            st = run_stages(f, N, H, W, m, oo, TNRD_IMPL_FUSED, window, seg_lo, seg_hi - 1,
+                            ut[seg_lo], dst.data(), nullptr, stream);
+            if (st != TNRD_OK) return st;
+        }
+        for (int t = seg_hi; t > seg_lo; --t) {
+            const int ts = t - 1;  // 0-based stage index
+            const float *filt = m->filters + (size_t)ts * m->Nk * kk;
+            const float *rbfw = m->rbf_w + (size_t)ts * m->Nk * m->Nrbf;
+            const float *lam = m->lambda + ts;
+            BwdParamsIO io;
+            io.u_prev = ut[t - 1];
+            io.u_cur = ut[t];
+            io.f = f;
+            io.g_cur = g_cur;
+            io.zexp = w.zexp;
+            io.aexp = w.aexp;
+            io.dk_part = w.dk_part;
+            io.dl_part = w.dl_part;
+            if (bwd_params(io, N, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) != hipSuccess)
+                return TNRD_ERR_HIP;
+            if (bwd_dw(w.zexp, w.aexp, N, H, W, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
+                return TNRD_ERR_HIP;
+            if (reduce_partials(w.dk_part, gm.tiles, (int)(m->Nk * kk), -1.f,
+                                grad_filters + (size_t)ts * m->Nk * kk, stream) != hipSuccess ||
+                reduce_partials(w.dw_part, gm.dw_grid, m->Nk * m->Nrbf, -1.f,
+                                grad_rbf_w + (size_t)ts * m->Nk * m->Nrbf, stream) != hipSuccess ||
+                reduce_partials(w.dl_part, gm.tiles, 1, 1.f, grad_lambda + ts, stream) != hipSuccess)
+                return TNRD_ERR_HIP;
+            if (t > 1 || grad_u0) {
+                float *g_next = (t == 1) ? grad_u0 : w.g[ping];
+                ia.u_prev = ut[t - 1];
+                ia.u_cur = ut[t];
+                ia.g_cur = g_cur;
+                ia.u_next = g_next;
+                ia.filt = filt;
+                ia.rbfw = rbfw;
+                ia.lam = lam;
+                if (fused_stage_input_grad(ia, stream) != hipSuccess) return TNRD_ERR_HIP;
+                g_cur = g_next;
+                ping ^= 1;
+            }
+        }
+        seg_hi = seg_lo;
+    }
+    return TNRD_OK;
+}

@@ -41,41 +41,15 @@
 // output pixel within R of the image border also receives X at its mirror
 // position in the padded ring, which the tile's P already holds.
 #include "tnrd_device.hpp"
+#include "tnrd_fused_common.hpp"
 #include "tnrd_internal.hpp"
 
 namespace tnrd {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-constexpr int RBF_WIN = 5;                // Horner window half-width (11 centres)
-constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
-
-// Constants of the windowed Horner evaluation of phi.
-//   s = (z - mu0) / step = j0 + d, j0 the nearest centre, |d| <= 1/2,
-//   G_{j0+m}(z) = exp(-rho (d - m)^2 / 2), rho = (step / sigma)^2
-//              = exp(-rho d^2 / 2) * q^m * exp(-rho m^2 / 2),  q = exp(rho d)
-//   phi(z) = exp(-rho d^2 / 2 - rho W d) * sum_{n=0}^{2W} w_{j0-W+n} c_n q^n,
-//   c_n = exp(-rho (n - W)^2 / 2).
-struct FusedRbf {
-    float mu0_over_step;  // mu0 / step
-    float inv_step;       // 1 / step
-    float rho_log2e;      // rho * log2(e)
-    float jmax;           // Nrbf - 1 + W (largest clamped centre index)
-    float c[RBF_TERMS];
-};
-
-template <int KS>
-struct Geo {
-    static constexpr int R = KS / 2;
-    static constexpr int KK = KS * KS;
-    static constexpr int KS1 = (KK + 3) / 4;                         // GEMM1 k-steps
-    static constexpr int MB2 = (KK % 16 <= 1) ? KK / 16 : (KK + 15) / 16;  // GEMM2 slot blocks
-    static constexpr int VTAP = (KK > 16 * MB2) ? 1 : 0;             // leftover tap on the VALU
-};
-
 struct FusedLds {
     int ldw;      // u tile row pitch
     int u_off, u_size;
+    int e_off;    // input-gradient mode: e tile, same shape as the u tile
     int t_off, t_pitch;   // RBF table
     int p_off, pw, p_size;
     int y_off, yp, y_size;  // per-wave Y scratch: [16 nb][yp] floats per wave
@@ -90,7 +64,7 @@ __host__ __device__ inline int fused_yp(int ks)
 }
 
 __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, int tw, int nrbf,
-                                              int nw)
+                                              int nw, int mode = MODE_FWD)
 {
     const int R = ks / 2;
     FusedLds l;
@@ -98,8 +72,9 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     l.ldw = tw + 4 * R + 1;
     l.u_off = 0;
     l.u_size = luh * l.ldw;
+    l.e_off = l.u_off + l.u_size;
     l.t_pitch = nrbf + 4 * RBF_WIN + 1;
-    l.t_off = l.u_size;
+    l.t_off = l.e_off + (mode == MODE_BWD_INPUT ? l.u_size : 0);
     const int eh = th + 2 * R;
     l.pw = 16 * nb + 2 * R;
     l.p_off = l.t_off + 16 * nmb * l.t_pitch;
@@ -112,13 +87,15 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     return l;
 }
 
-template <int KS, int NMB, int NB, int NW>
+template <int KS, int NMB, int NB, int NW, int MODE>
 __global__ void __launch_bounds__(64 * NW) k_fused_stage(
-    const float *__restrict__ u_prev, const float *__restrict__ f, float *__restrict__ u_next,
-    int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
+    FusedIO io, int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
     FusedRbf rb, const float *__restrict__ lam_t)
 {
+    constexpr bool BWD = MODE == MODE_BWD_INPUT;
+    const float *__restrict__ u_prev = io.u_prev;
+    const float *__restrict__ f = io.f;
     using G = Geo<KS>;
     constexpr int R = G::R, KK = G::KK, KS1 = G::KS1, MB2 = G::MB2;
     constexpr int KS2 = 4 * NMB;  // GEMM2 k-steps (4 filters each)
@@ -126,8 +103,9 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     constexpr int FUSED_WAVES = NW;
 
     extern __shared__ float lds[];
-    const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW);
+    const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW, MODE);
     float *su = lds + L.u_off;
+    float *se = lds + L.e_off;
     float *stab = lds + L.t_off;
     float *sp = lds + L.p_off;
 
@@ -178,6 +156,40 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
                 if (i < n) {
                     int ly = i / luw, lx = i - ly * luw;
                     su[ly * L.ldw + lx] = v[k];
+                }
+            }
+        }
+    }
+    // (2b) input-gradient mode: e = y * g_t over the same region, where
+    // y = du_t/d(ut_t) = u_t^2 / ((1+2l) u_t^2 + 2 l f^2) is the prox derivative
+    // written with the prox output (equal to the closed form of eq. derv2).
+    if (BWD) {
+        const float lam0 = lam_t[0];
+        const float c1 = 1.f + 2.f * lam0, c2 = 2.f * lam0;
+        const float *ucn = io.u_cur + img * plane;
+        const float *gcn = io.g_cur + img * plane;
+        const float *fcn = f + img * plane;
+        const int n = luh * luw;
+        for (int base = 0; base < n; base += 4 * FUSED_THREADS) {
+            float uu[4], ff[4], gg[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int i = min(base + k * FUSED_THREADS + tid, n - 1);
+                int ly = i / luw, lx = i - ly * luw;
+                int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
+                size_t q = (size_t)yy * W + xx;
+                uu[k] = ucn[q];
+                ff[k] = fcn[q];
+                gg[k] = gcn[q];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int i = base + k * FUSED_THREADS + tid;
+                if (i < n) {
+                    int ly = i / luw, lx = i - ly * luw;
+                    float u2 = uu[k] * uu[k];
+                    float y = u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
+                    se[ly * L.ldw + lx] = y * gg[k];
                 }
             }
         }
@@ -254,17 +266,25 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
             const bool valid = (c < Ew) && (xi >= 0) && (xi < W);
             const int cc = c < Ew ? c : Ew - 1;
             const float *ub = su + (e + 2 * R) * L.ldw + cc + 2 * R;
+            const float *eb = se + (e + 2 * R) * L.ldw + cc + 2 * R;
 
-            // GEMM1: z = K u
-            floatx4 acc1[NMB];
+            // GEMM1: z = K u  (and a = K e in input-gradient mode)
+            floatx4 acc1[NMB], acca[NMB];
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb) acc1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int mb = 0; mb < NMB; ++mb) {
+                acc1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                acca[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
             for (int s = 0; s < KS1; ++s) {
                 float bv = ub[-off1[s]];
+                float be = BWD ? eb[-off1[s]] : 0.f;
 #pragma unroll
-                for (int mb = 0; mb < NMB; ++mb)
+                for (int mb = 0; mb < NMB; ++mb) {
                     acc1[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], bv, acc1[mb], 0, 0, 0);
+                    if (BWD)
+                        acca[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], be, acca[mb], 0, 0, 0);
+                }
             }
 
             // influence: v = phi(z), lane-local (pixel j, filters 16 mb + 4 g + r)
@@ -280,9 +300,20 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
                     float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
                     float E = __builtin_amdgcn_exp2f(-rb.rho_log2e * d * fmaf(0.5f, d, (float)RBF_WIN));
                     float acc = w[2 * RBF_WIN] * rb.c[2 * RBF_WIN];
+                    float accd = 0.f;  // derivative of the Horner polynomial
 #pragma unroll
-                    for (int n = 2 * RBF_WIN - 1; n >= 0; --n) acc = fmaf(acc, q, w[n] * rb.c[n]);
-                    float v = E * acc;
+                    for (int n = 2 * RBF_WIN - 1; n >= 0; --n) {
+                        if (BWD) accd = fmaf(accd, q, acc);
+                        acc = fmaf(acc, q, w[n] * rb.c[n]);
+                    }
+                    float v;
+                    if (BWD) {
+                        // phi'(z) = (rho/step) E (q P'(q) - (d + W) P(q)), times a
+                        float dphi = rb.rho_over_step * E * fmaf(q, accd, -(d + (float)RBF_WIN) * acc);
+                        v = dphi * acca[mb][r];
+                    } else {
+                        v = E * acc;
+                    }
                     acc1[mb][r] = (valid && fabsf(d) <= 0.5f) ? v : 0.f;
                 }
 
@@ -336,7 +367,7 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
 
     // ---- gather X, fold the border ring, prox, store
     const float *fn = f + img * plane;
-    float *uo = u_next + img * plane;
+    float *uo = io.out + img * plane;
     for (int i = tid; i < Th * Tw; i += FUSED_THREADS) {
         const int y = i / Tw, x = i - (i / Tw) * Tw;
         const int yi = ty0 + y, xi = tx0 + x;
@@ -358,90 +389,130 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
                     if (e >= 0 && e < Eh && ye >= 0 && ye < H) xs += sp[(e * KS + a) * L.pw + col];
                 }
             }
-        const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
         const size_t p = (size_t)yi * W + xi;
-        uo[p] = prox(uv - xs, fn[p], lam);
+        if (BWD) {
+            // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1)
+            uo[p] = se[(y + 2 * R) * L.ldw + x + 2 * R] - xs;
+        } else {
+            const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
+            uo[p] = prox(uv - xs, fn[p], lam);
+        }
     }
 }
 
 // ------------------------------------------------------------------ host side
-template <int KS, int NMB, int NB, int NW>
+FusedRbf make_fused_rbf(const RbfGrid &grid)
+{
+    FusedRbf rb;
+    const double step = grid.step;
+    const double sigma = 1.0 / sqrt(-2.0 * (double)grid.neg_half_inv_var);
+    const double rho = (step / sigma) * (step / sigma);
+    rb.mu0_over_step = (float)(grid.mu0 / step);
+    rb.inv_step = (float)(1.0 / step);
+    rb.rho_log2e = (float)(rho * 1.4426950408889634);
+    rb.jmax = (float)(grid.nrbf - 1 + RBF_WIN);
+    rb.rho_over_step = (float)(rho / step);
+    for (int n = 0; n < RBF_TERMS; ++n) {
+        double m = n - RBF_WIN;
+        rb.c[n] = (float)exp(-rho * m * m / 2.0);
+    }
+    return rb;
+}
+
+template <int KS, int NMB, int NB, int NW, int MODE>
 static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t stream)
 {
-    const int R = KS / 2;
-    FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf, NW);
+    FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf, NW, MODE);
     size_t lds_bytes = (size_t)L.total * sizeof(float);
     static bool attr_set = false;
     if (!attr_set) {
         // raise the dynamic LDS limit to the CU's 160 KB; a failure here shows
         // up as a launch error below, so the status is cleared
-        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB, NW>,
+        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB, NW, MODE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         (void)hipGetLastError();
         attr_set = true;
     }
     if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
-    (void)R;
-    FusedRbf rb;
-    const double step = s.grid.step;
-    const double sigma = 1.0 / sqrt(-2.0 * (double)s.grid.neg_half_inv_var);
-    const double rho = (step / sigma) * (step / sigma);
-    rb.mu0_over_step = (float)(s.grid.mu0 / step);
-    rb.inv_step = (float)(1.0 / step);
-    rb.rho_log2e = (float)(rho * 1.4426950408889634);
-    rb.jmax = (float)(s.grid.nrbf - 1 + RBF_WIN);
-    for (int n = 0; n < RBF_TERMS; ++n) {
-        double m = n - RBF_WIN;
-        rb.c[n] = (float)exp(-rho * m * m / 2.0);
-    }
+    FusedRbf rb = make_fused_rbf(s.grid);
+    FusedIO io;
+    io.u_prev = s.u_prev;
+    io.f = s.f;
+    io.out = s.u_next;
+    io.u_cur = s.u_cur;
+    io.g_cur = s.g_cur;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     dim3 grid(tiles * s.N);
-    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW>), grid, dim3(64 * NW), lds_bytes, stream,
-                       s.u_prev, s.f, s.u_next, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk,
-                       s.rbfw, s.grid.nrbf, rb, s.lam);
+    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW, MODE>), grid, dim3(64 * NW), lds_bytes,
+                       stream, io, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk, s.rbfw,
+                       s.grid.nrbf, rb, s.lam);
     return hipGetLastError();
 }
 
-// Tile used when the caller does not pick one: 32 x 32 output pixels (three
-// 16-pixel blocks per E row for 7x7 filters), clamped to the image.
-static void fused_tile(int ks, int H, int W, int req_h, int req_w, int &th, int &tw, int &nb)
+// Tile used when the caller does not pick one: 32 x 32 output pixels for the
+// forward (three 16-pixel blocks per E row for 7x7 filters), 32 x 26 for the
+// input-gradient mode (two blocks per E row, which leaves LDS room for the e
+// tile), clamped to the image.
+static void fused_tile(int ks, int H, int W, int req_h, int req_w, int mode, int &th, int &tw,
+                       int &nb)
 {
     const int R = ks / 2;
-    tw = req_w > 0 ? req_w : 32;
+    tw = req_w > 0 ? req_w : (mode == MODE_FWD ? 32 : 32 - 2 * R);
     th = req_h > 0 ? req_h : 32;
     if (tw > W) tw = W;
     if (th > H) th = H;
     nb = (tw + 2 * R + 15) / 16;
 }
 
-template <int KS, int NMB, int NW>
+template <int KS, int NMB, int NW, int MODE>
 static hipError_t fused_nb(const StageArgs &s, int th, int tw, int nb, hipStream_t stream)
 {
     switch (nb) {
-    case 2: return launch_fused<KS, NMB, 2, NW>(s, th, tw, stream);
-    case 3: return launch_fused<KS, NMB, 3, NW>(s, th, tw, stream);
-    case 4: return launch_fused<KS, NMB, 4, NW>(s, th, tw, stream);
+    case 2: return launch_fused<KS, NMB, 2, NW, MODE>(s, th, tw, stream);
+    case 3: return launch_fused<KS, NMB, 3, NW, MODE>(s, th, tw, stream);
+    case 4: return launch_fused<KS, NMB, 4, NW, MODE>(s, th, tw, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int KS, int NMB>
+template <int KS, int NMB, int MODE>
 static hipError_t fused_nw(const StageArgs &s, int th, int tw, int nb, int nw, hipStream_t stream)
 {
-    if (nw == 4) return fused_nb<KS, NMB, 4>(s, th, tw, nb, stream);
-    return fused_nb<KS, NMB, 8>(s, th, tw, nb, stream);
+    if (nw == 4) return fused_nb<KS, NMB, 4, MODE>(s, th, tw, nb, stream);
+    return fused_nb<KS, NMB, 8, MODE>(s, th, tw, nb, stream);
 }
 
-bool fused_config_ok(int ks, int nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves)
+template <int MODE>
+static hipError_t fused_dispatch(const StageArgs &s, hipStream_t stream)
 {
     int th, tw, nb;
-    fused_tile(ks, H, W, tile_h, tile_w, th, tw, nb);
+    fused_tile(s.ks, s.H, s.W, s.tile_h, s.tile_w, MODE, th, tw, nb);
+    if (nb < 2) nb = 2;
+    if (nb > 4) return hipErrorInvalidValue;
+    const int nw = s.waves == 4 ? 4 : 8;
+    const int nmb = (s.Nk + 15) / 16;
+    if (s.ks == 7) {
+        if (nmb <= 2) return fused_nw<7, 2, MODE>(s, th, tw, nb, nw, stream);
+        return fused_nw<7, 3, MODE>(s, th, tw, nb, nw, stream);
+    }
+    if (s.ks == 5) {
+        if (nmb <= 2) return fused_nw<5, 2, MODE>(s, th, tw, nb, nw, stream);
+        return fused_nw<5, 3, MODE>(s, th, tw, nb, nw, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool fused_config_ok(int ks, int nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves,
+                     int mode)
+{
+    int th, tw, nb;
+    fused_tile(ks, H, W, tile_h, tile_w, mode, th, tw, nb);
     if (nb < 2) nb = 2;
     if (nb > 4 || th < ks / 2 || tw < ks / 2) return false;
     const int nw = waves == 4 ? 4 : 8;
     const int nmb = (nk + 15) / 16;
-    FusedLds L = fused_lds(ks, nmb <= 2 ? 2 : 3, nb, th, tw, nrbf, nw);
+    FusedLds L = fused_lds(ks, nmb <= 2 ? 2 : 3, nb, th, tw, nrbf, nw, mode);
     return (size_t)L.total * sizeof(float) <= 160 * 1024;
 }
 
@@ -459,21 +530,12 @@ size_t fused_scratch_floats(int, int, int, int, int) { return 0; }
 
 hipError_t fused_stage(const StageArgs &s, hipStream_t stream)
 {
-    int th, tw, nb;
-    fused_tile(s.ks, s.H, s.W, s.tile_h, s.tile_w, th, tw, nb);
-    if (nb < 2) nb = 2;
-    if (nb > 4) return hipErrorInvalidValue;
-    const int nw = s.waves == 4 ? 4 : 8;
-    const int nmb = (s.Nk + 15) / 16;
-    if (s.ks == 7) {
-        if (nmb <= 2) return fused_nw<7, 2>(s, th, tw, nb, nw, stream);
-        return fused_nw<7, 3>(s, th, tw, nb, nw, stream);
-    }
-    if (s.ks == 5) {
-        if (nmb <= 2) return fused_nw<5, 2>(s, th, tw, nb, nw, stream);
-        return fused_nw<5, 3>(s, th, tw, nb, nw, stream);
-    }
-    return hipErrorInvalidValue;
+    return fused_dispatch<MODE_FWD>(s, stream);
+}
+
+hipError_t fused_stage_input_grad(const StageArgs &s, hipStream_t stream)
+{
+    return fused_dispatch<MODE_BWD_INPUT>(s, stream);
 }
 
 }  // namespace tnrd

@@ -13,7 +13,9 @@ namespace tnrd {
 struct StageArgs {
     const float *u_prev;  // [N][H][W] u_{t-1}
     const float *f;       // [N][H][W]
-    float *u_next;        // [N][H][W] u_t
+    float *u_next;        // [N][H][W] u_t (input-gradient mode: g_{t-1})
+    const float *u_cur;   // input-gradient mode: u_t
+    const float *g_cur;   // input-gradient mode: g_t
     int N, H, W;
     int ks, Nk;
     const float *filt;    // [Nk][ks*ks] stage t
@@ -30,8 +32,10 @@ hipError_t split_stage(const StageArgs &s, hipStream_t stream);
 size_t split_scratch_floats(int N, int H, int W, int Nk);
 
 hipError_t fused_stage(const StageArgs &s, hipStream_t stream);
+hipError_t fused_stage_input_grad(const StageArgs &s, hipStream_t stream);
 bool fused_supported(int ks, int Nk, int nrbf, int window, int prec);
-bool fused_config_ok(int ks, int Nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves);
+bool fused_config_ok(int ks, int Nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves,
+                     int mode);
 size_t fused_scratch_floats(int N, int H, int W, int Nk, int prec);
 
 }  // namespace tnrd

@@ -1,0 +1,153 @@
+"""GPU backward (tnrd_backward, via the C ABI) against the FP64 oracle.
+
+Bar: ||a - b||_inf / ||b||_inf <= 1e-4 for every gradient tensor (dK, dW,
+dlambda, dl/du_0), FP32 GPU against FP64.  The loss gradient handed to both
+sides is computed by the oracle (u_T^oracle - u_gt), so no oracle input comes
+from the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1702_07482_amd import synth, tnrd
+from paper_1702_07482_amd.autograd import tnrd_apply
+from tests.helpers import crop_window, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _gpu_grads(f, m, gT, L=1, **opt):
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(**opt)
+    fd = _dev(f)
+    _, states = tnrd.forward(fd, dm, L=L, want_states=True, opts=o)
+    dK, dW, dl, g0 = tnrd.backward(fd, dm, states, _dev(gT), L=L, opts=o, want_u0=True)
+    torch.cuda.synchronize()
+    return dK.cpu().numpy(), dW.cpu().numpy(), dl.cpu().numpy(), g0.cpu().numpy()
+
+
+def _check(got, ref, tol=TOL):
+    names = ["dK", "dW", "dlam", "g0"]
+    errs = {n: rel_inf(a, b) for n, a, b in zip(names, got, ref)}
+    print("rel errors", errs, flush=True)
+    for n in names:
+        assert errs[n] <= tol, (n, errs)
+
+
+def _case(cfg, shape, N, L=1, index=0):
+    pairs = [synth.make_pair(*shape, L, config_id=cfg, index=index + n) for n in range(N)]
+    u = np.stack([p[0] for p in pairs])
+    f = np.stack([p[1] for p in pairs])
+    return u, f
+
+
+@pytest.mark.parametrize("shape,N", [((48, 40), 1), ((37, 53), 2)])
+def test_backward_c1_model(shape, N):
+    """24 5x5 filters, 5 stages: every gradient against the oracle."""
+    print(f"[bwd c1 shape={shape} N={N}]", flush=True)
+    m = synth.config_model(1)
+    u, f = _case(1, shape, N)
+    uT, st = oracle.forward(f, m, want_states=True)
+    gT = uT - u
+    ref = oracle.backward(f, m, st, gT)
+    _check(_gpu_grads(f, m, gT), ref)
+
+
+@pytest.mark.parametrize("shape,N", [((40, 36), 2), ((7, 9), 1)])
+def test_backward_c3_model_small(shape, N):
+    """48 7x7 filters, 8 stages on small and minimum-size images."""
+    print(f"[bwd c3 model shape={shape} N={N}]", flush=True)
+    m = synth.config_model(3)
+    u, f = _case(3, shape, N, index=20)
+    uT, st = oracle.forward(f, m, want_states=True)
+    gT = (uT - u) * (2.0 / u.size)  # gradient of mean((u_T - u_gt)^2)
+    ref = oracle.backward(f, m, st, gT)
+    _check(_gpu_grads(f, m, gT), ref)
+
+
+def test_recompute_is_bit_identical():
+    """Checkpointing every 3rd state and recomputing the rest gives the same bits."""
+    m = synth.config_model(3)
+    u, f = _case(3, (45, 50), 2, index=30)
+    gT = np.random.default_rng(0).standard_normal(f.shape)
+    a = _gpu_grads(f, m, gT, recompute_every=1)
+    b = _gpu_grads(f, m, gT, recompute_every=3)
+    c = _gpu_grads(f, m, gT, recompute_every=8)
+    for x, y, z in zip(a, b, c):
+        np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(x, z)
+
+
+def test_backward_is_deterministic():
+    m = synth.config_model(1)
+    u, f = _case(1, (64, 70), 2, index=40)
+    gT = np.random.default_rng(1).standard_normal(f.shape)
+    a = _gpu_grads(f, m, gT)
+    b = _gpu_grads(f, m, gT)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_zero_weight_gradients_closed_form():
+    """Zero RBF weights: dK = 0 and dlambda = 0 exactly in the math (tiny here),
+    and dl/du_0 = gT / prod_t (1 + 4 lambda^t)."""
+    m = synth.config_model(1)
+    m["rbf_w"][:] = 0
+    u, f = _case(1, (33, 31), 1, index=50)
+    gT = np.random.default_rng(2).standard_normal(f.shape).astype(np.float32)
+    dK, dW, dl, g0 = _gpu_grads(f, m, gT)
+    assert np.abs(dK).max() <= 1e-3 * np.abs(gT).max()
+    scale = np.prod(1.0 + 4.0 * m["lam"].astype(np.float64))
+    np.testing.assert_allclose(g0, gT / scale, rtol=1e-5, atol=1e-7)
+    assert np.abs(dl).max() <= 1e-3 * np.abs(gT).sum()
+
+
+def test_c3_full_size_localized_gradient():
+    """16 x 180 x 180 (the fwd+bwd workload), loss gradient supported on one
+    pixel: every parameter gradient comes from that pixel's receptive field,
+    which the oracle covers with a crop of radius T * (k - 1)."""
+    m = synth.config_model(3)
+    u, f = _case(3, (180, 180), 16, index=60)
+    radius = m["T"] * (m["ks"] - 1)
+    for (n, y, x) in [(0, 90, 91), (11, 2, 177)]:
+        print(f"[bwd c3 full localized n={n} y={y} x={x}]", flush=True)
+        gT = np.zeros(f.shape, dtype=np.float32)
+        gT[n, y, x] = 1.0
+        got = _gpu_grads(f, m, gT)
+        y0, y1 = crop_window(y, 180, radius)
+        x0, x1 = crop_window(x, 180, radius)
+        fc = f[n, y0:y1, x0:x1]
+        gc = gT[n, y0:y1, x0:x1]
+        _, st = oracle.forward(fc, m, want_states=True)
+        dK, dW, dl, g0c = oracle.backward(fc, m, st, gc)
+        g0 = np.zeros(f.shape)
+        g0[n, y0:y1, x0:x1] = g0c
+        _check(got, (dK, dW, dl, g0))
+
+
+def test_autograd_function_matches_backward():
+    """TNRDFunction: loss.backward() fills filters/rbf_w/lam grads equal to the
+    C-ABI backward with dl/du_T = 2 (u_T - u_gt) / n."""
+    m = synth.config_model(1)
+    u, f = _case(1, (40, 44), 2, index=70)
+    filt = _dev(m["filters"]).requires_grad_(True)
+    w = _dev(m["rbf_w"]).requires_grad_(True)
+    lam = _dev(m["lam"]).requires_grad_(True)
+    fd, ud = _dev(f), _dev(u)
+    uT = tnrd_apply(fd, filt, w, lam)
+    loss = ((uT - ud) ** 2).mean()
+    loss.backward()
+    gT = (2.0 / u.size) * (uT.detach() - ud)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    _, states = tnrd.forward(fd, dm, want_states=True)
+    dK, dW, dl = tnrd.backward(fd, dm, states, gT.contiguous())
+    torch.testing.assert_close(filt.grad, dK, rtol=0, atol=0)
+    torch.testing.assert_close(w.grad, dW, rtol=0, atol=0)
+    torch.testing.assert_close(lam.grad, dl, rtol=0, atol=0)
