@@ -8,7 +8,7 @@ inputs resident in HBM.  Metric: megapixel-stages per second
 
 Extra legs reported on the same JSON line (each its own workload):
   fwd_bwd  16 x 180 x 180, forward with saved states + hand-written backward
-  batched  64 uneven images in one persistent launch replayed from a HIP graph
+  batched  64 uneven images, one launch per stage over all tiles, replayed from a HIP graph
   mixed    8 x 2048 x 2048 with BF16/FP16 filter-bank operands
 
 The CPU baseline times the FP64 oracle (tests' reference, not a product path)
@@ -173,6 +173,41 @@ def leg_fwd_bwd(args):
                         "RBF weights and lambda"}
 
 
+def leg_batched(args):
+    """64 uneven images, L in {1,2,4,8}, one launch per stage over all tiles, from a HIP graph."""
+    import torch
+    from paper_1702_07482_amd import autotune, synth, tnrd
+
+    sizes, looks = synth.c4_batch(64)
+    T = 8
+    models = {L: synth.config_model(4, look=L) for L in sorted(set(looks))}
+    dms = [tnrd.DeviceModel.from_numpy(models[L], L=L) for L in sorted(models)]
+    fs = [torch.from_numpy(synth.make_pair(h, w, L, config_id=4, index=100 + i)[1]).cuda()
+          for i, ((h, w), L) in enumerate(zip(sizes, looks))]
+    th, tw, nw = autotune.tune_batched(fs, looks, dms)
+    o = tnrd.default_opts(tile_h=th, tile_w=tw, wg_waves=nw, use_graph=1)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs, ws = tnrd.forward_batched(fs, looks, dms, opts=o)  # records the graph
+        for _ in range(2):
+            tnrd.forward_batched(fs, looks, dms, opts=o, outs=outs, ws=ws)
+        stream.synchronize()
+        steps = max(3, args.steps // 5)
+        a, b = _events()
+        a.record(stream)
+        for _ in range(steps):
+            tnrd.forward_batched(fs, looks, dms, opts=o, outs=outs, ws=ws)
+        b.record(stream)
+        stream.synchronize()
+    ms = a.elapsed_time(b) / steps
+    mp = sum(h * w for h, w in sizes) / 1e6
+    return {"value": mp * T / (ms / 1e3), "unit": "megapixel-stages/s", "ms_per_step": ms,
+            "steps": steps, "megapixels": mp, "tile": [th, tw, nw],
+            "workload": "batched forward, 64 images of 256x256/384x512/512x512/1024x768, "
+                        "L in {1,2,4,8} (one model per L), 8 stages x 48 7x7, FP32, one "
+                        "launch per stage over all tiles, replayed from a HIP graph"}
+
+
 def resolve_auto_impl():
     """The implementation IMPL_AUTO runs for the headline workload."""
     import torch
@@ -242,6 +277,8 @@ def main():
     }
     if "fwd_bwd" in legs:
         out["fwd_bwd"] = leg_fwd_bwd(args)
+    if "batched" in legs:
+        out["batched"] = leg_batched(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fwd["f"], fwd["m"], args.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -96,6 +96,8 @@ typedef struct tnrd_opts {
                              `stream`; TNRD_ERR_DOMAIN on failure) */
     int32_t tile_h, tile_w; /* 0 = automatic; otherwise the fused kernel's output tile */
     int32_t wg_waves;     /* fused kernel: wavefronts per workgroup, 4 or 8; 0 = automatic */
+    int32_t use_graph;    /* tnrd_forward_batched: 1 (default) records the launch sequence in a HIP
+                             graph once per batch signature and replays it; 0 launches directly */
 } tnrd_opts;
 
 /* Fills `o` with the defaults (FP32, AUTO, automatic window, no checkpointing,
@@ -155,14 +157,19 @@ typedef struct tnrd_image {
     int32_t L;       /* looks; selects the model whose L matches (or one with L == 0) */
 } tnrd_image;
 
-/* Batched forward over B images of different sizes and look numbers in one
- * persistent launch per call (per-L models, Sec. 4.5: one trained model per
- * noise level).  `imgs` and `models` are HOST arrays; the models must share T,
- * Nk, ksize, Nrbf and the RBF grid.  Workspace from
- * tnrd_batched_workspace_bytes.  The launch sequence is recorded once into a
- * HIP graph per (stream, batch shape) and replayed on later calls with the same
- * shapes, models and workspace.  Errors as tnrd_forward, plus TNRD_ERR_ARG for
- * an image whose L matches no model. */
+/* Batched forward over B images of different sizes and look numbers (per-L
+ * models: the paper trains one model per noise level, Sec. 4.5).  Each stage
+ * is one launch over the tiles of every image.  `imgs` and `models` are HOST
+ * arrays; the models must share T, Nk, ksize, Nrbf and the RBF grid; an image
+ * uses the model whose L equals its own, else one with L == 0.  Workspace from
+ * tnrd_batched_workspace_bytes.  With opts->use_graph (default) and a non-null
+ * stream, the descriptor upload and the T launches are recorded once into a HIP
+ * graph per (stream, workspace, batch signature: pointers, sizes, looks,
+ * models, tiles) and replayed on later calls; the pinned copy of the
+ * descriptors stays alive as long as the graph.  Tiles: opts->tile_h/tile_w
+ * (default 32 x 32; both must be >= ksize - 1) and opts->wg_waves.  Errors as
+ * tnrd_forward, plus TNRD_ERR_ARG for an image whose L matches no model or
+ * models that disagree in shape. */
 size_t tnrd_batched_workspace_bytes(int B, const tnrd_image *imgs, int n_models,
                                     const tnrd_model *models, const tnrd_opts *o);
 int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models, const tnrd_model *models,

@@ -201,6 +201,7 @@ void tnrd_default_opts(tnrd_opts *o)
     o->rbf_window = -1;
     o->recompute_every = 1;
     o->validate = 0;
+    o->use_graph = 1;
 }
 
 int tnrd_num_checkpoints(int T, int recompute_every)

@@ -1,15 +1,302 @@
-// Batched forward over uneven images (in progress).
-#include "tnrd.h"
+// tnrd_forward_batched: a batch of images with different sizes and look
+// numbers, one launch per stage over every (image, tile) item, with the
+// per-image model chosen by L.  The descriptor upload and the T stage launches
+// are recorded once per batch signature into a HIP graph and replayed on
+// later calls.
+#include <hip/hip_runtime.h>
 
-extern "C" {
-size_t tnrd_batched_workspace_bytes(int, const tnrd_image *, int, const tnrd_model *,
-                                    const tnrd_opts *)
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "tnrd.h"
+#include "tnrd_api_internal.hpp"
+#include "tnrd_internal.hpp"
+
+using namespace tnrd;
+
+namespace {
+
+constexpr size_t AL = 256;
+size_t al(size_t x) { return (x + AL - 1) / AL * AL; }
+
+struct BatchPlan {
+    int th, tw, nw;
+    int ntiles;                  // items per stage
+    size_t off_imgs, off_models, off_items, off_tmp, desc_bytes, total;
+    std::vector<size_t> tmp_off; // per image, from the workspace base
+};
+
+int resolve_model(const tnrd_image &im, int n_models, const tnrd_model *models)
 {
-    return 0;
+    int any = -1;
+    for (int k = 0; k < n_models; ++k) {
+        if (models[k].L == im.L) return k;
+        if (models[k].L == 0 && any < 0) any = k;
+    }
+    return any;
 }
-int tnrd_forward_batched(int, const tnrd_image *, int, const tnrd_model *, const tnrd_opts *,
-                         void *, size_t, void *)
+
+int check_batch(int B, const tnrd_image *imgs, int n_models, const tnrd_model *models,
+                const tnrd_opts &o, BatchPlan &plan, std::vector<int> &model_of)
 {
-    return TNRD_ERR_UNSUPPORTED;
+    if (B < 0 || n_models < 1 || !models) return TNRD_ERR_ARG;
+    if (B > 0 && !imgs) return TNRD_ERR_ARG;
+    for (int k = 0; k < n_models; ++k) {
+        int st = check_model(&models[k]);
+        if (st != TNRD_OK) return st;
+        const tnrd_model &a = models[0], &b = models[k];
+        if (a.T != b.T || a.Nk != b.Nk || a.ksize != b.ksize || a.Nrbf != b.Nrbf ||
+            a.rbf_mu0 != b.rbf_mu0 || a.rbf_step != b.rbf_step || a.rbf_sigma != b.rbf_sigma)
+            return TNRD_ERR_ARG;
+    }
+    const tnrd_model &m = models[0];
+    if (o.prec != TNRD_PREC_FP32) return o.prec > TNRD_PREC_FP16 || o.prec < 0 ? TNRD_ERR_ARG
+                                                                                : TNRD_ERR_UNSUPPORTED;
+    const int window = rbf_window_for(&m, o.rbf_window);
+    if (!fused_supported(m.ksize, m.Nk, m.Nrbf, window, o.prec)) return TNRD_ERR_UNSUPPORTED;
+    plan.th = o.tile_h > 0 ? o.tile_h : 32;
+    plan.tw = o.tile_w > 0 ? o.tile_w : 32;
+    plan.nw = o.wg_waves == 4 ? 4 : 8;
+    if (!batched_config_ok(m.ksize, m.Nk, m.Nrbf, plan.th, plan.tw, plan.nw))
+        return TNRD_ERR_UNSUPPORTED;
+    model_of.assign(B, -1);
+    plan.ntiles = 0;
+    size_t tmp_total = 0;
+    plan.tmp_off.assign(B, 0);
+    for (int b = 0; b < B; ++b) {
+        const tnrd_image &im = imgs[b];
+        if (!im.f || !im.u_out || im.f == im.u_out) return TNRD_ERR_ARG;
+        if (im.H < m.ksize || im.W < m.ksize || im.L < 1) return TNRD_ERR_ARG;
+        if ((size_t)im.H * im.W > ((size_t)1 << 31)) return TNRD_ERR_ARG;
+        model_of[b] = resolve_model(im, n_models, models);
+        if (model_of[b] < 0) return TNRD_ERR_ARG;
+        const int tx = (im.W + plan.tw - 1) / plan.tw, ty = (im.H + plan.th - 1) / plan.th;
+        plan.ntiles += tx * ty;
+    }
+    size_t off = AL;  // domain-check flag
+    plan.off_imgs = off;
+    off += al((size_t)B * sizeof(BatchImage));
+    plan.off_models = off;
+    off += al((size_t)n_models * sizeof(BatchModel));
+    plan.off_items = off;
+    off += al((size_t)plan.ntiles * sizeof(BatchItem));
+    plan.desc_bytes = off - plan.off_imgs;
+    plan.off_tmp = off;
+    for (int b = 0; b < B; ++b) {
+        plan.tmp_off[b] = off;
+        off += al((size_t)imgs[b].H * imgs[b].W * sizeof(float));
+        tmp_total += (size_t)imgs[b].H * imgs[b].W;
+    }
+    (void)tmp_total;
+    plan.total = off;
+    return TNRD_OK;
 }
+
+// Host images of the device descriptors (imgs | models | items), laid out as
+// in the workspace starting at off_imgs.
+void build_descriptors(int B, const tnrd_image *imgs, int n_models, const tnrd_model *models,
+                       const BatchPlan &plan, const std::vector<int> &model_of, char *ws,
+                       unsigned char *host)
+{
+    memset(host, 0, plan.desc_bytes);
+    BatchImage *di = (BatchImage *)(host + (plan.off_imgs - plan.off_imgs));
+    BatchModel *dm = (BatchModel *)(host + (plan.off_models - plan.off_imgs));
+    BatchItem *dt = (BatchItem *)(host + (plan.off_items - plan.off_imgs));
+    int flag = 0;
+    for (int b = 0; b < B; ++b) {
+        const tnrd_image &im = imgs[b];
+        const int tx = (im.W + plan.tw - 1) / plan.tw, ty = (im.H + plan.th - 1) / plan.th;
+        di[b].f = im.f;
+        di[b].u_out = im.u_out;
+        di[b].u_tmp = (float *)(ws + plan.tmp_off[b]);
+        di[b].H = im.H;
+        di[b].W = im.W;
+        di[b].tiles_x = tx;
+        di[b].tiles = tx * ty;
+        di[b].model = model_of[b];
+        for (int k = 0; k < tx * ty; ++k) dt[flag + k] = BatchItem{b, k};
+        flag += tx * ty;
+    }
+    for (int k = 0; k < n_models; ++k) {
+        dm[k].filt = models[k].filters;
+        dm[k].rbfw = models[k].rbf_w;
+        dm[k].lam = models[k].lambda;
+    }
+}
+
+BatchArgs make_args(const BatchPlan &plan, const tnrd_model &m, int window, char *ws)
+{
+    BatchArgs a;
+    a.imgs = (const BatchImage *)(ws + plan.off_imgs);
+    a.models = (const BatchModel *)(ws + plan.off_models);
+    a.items = (const BatchItem *)(ws + plan.off_items);
+    a.items_per_stage = plan.ntiles;
+    a.T = m.T;
+    a.Th = plan.th;
+    a.Tw = plan.tw;
+    a.Nk = m.Nk;
+    a.Nrbf = m.Nrbf;
+    a.rb = make_fused_rbf(make_grid(&m, window));
+    return a;
+}
+
+// ---- graph cache: one recorded graph per (stream, workspace, batch signature)
+struct GraphEntry {
+    hipStream_t stream;
+    std::vector<unsigned long long> sig;
+    hipGraphExec_t exec;
+    unsigned char *host_desc;  // pinned source of the recorded descriptor upload
+};
+std::mutex g_mu;
+std::vector<GraphEntry> g_cache;
+constexpr size_t G_CACHE_MAX = 8;
+
+std::vector<unsigned long long> signature(int B, const tnrd_image *imgs, int n_models,
+                                          const tnrd_model *models, const tnrd_opts &o,
+                                          void *ws, size_t ws_bytes)
+{
+    std::vector<unsigned long long> s;
+    auto P = [&](const void *p) { s.push_back((unsigned long long)(uintptr_t)p); };
+    auto I = [&](long long v) { s.push_back((unsigned long long)v); };
+    P(ws);
+    I((long long)ws_bytes);
+    I(B);
+    I(n_models);
+    I(o.tile_h);
+    I(o.tile_w);
+    I(o.wg_waves);
+    I(o.rbf_window);
+    for (int b = 0; b < B; ++b) {
+        P(imgs[b].f);
+        P(imgs[b].u_out);
+        I(imgs[b].H);
+        I(imgs[b].W);
+        I(imgs[b].L);
+    }
+    for (int k = 0; k < n_models; ++k) {
+        const tnrd_model &m = models[k];
+        P(m.filters);
+        P(m.rbf_w);
+        P(m.lambda);
+        I(m.T);
+        I(m.Nk);
+        I(m.ksize);
+        I(m.Nrbf);
+        I(m.L);
+        float fl[3] = {m.rbf_mu0, m.rbf_step, m.rbf_sigma};
+        unsigned int u[3];
+        memcpy(u, fl, sizeof(u));
+        I(u[0]);
+        I(u[1]);
+        I(u[2]);
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" size_t tnrd_batched_workspace_bytes(int B, const tnrd_image *imgs, int n_models,
+                                               const tnrd_model *models, const tnrd_opts *o)
+{
+    tnrd_opts oo;
+    resolve_opts(o, &oo);
+    BatchPlan plan;
+    std::vector<int> model_of;
+    if (check_batch(B, imgs, n_models, models, oo, plan, model_of) != TNRD_OK) return 0;
+    return plan.total;
+}
+
+extern "C" int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models,
+                                    const tnrd_model *models, const tnrd_opts *o, void *ws,
+                                    size_t ws_bytes, void *stream_)
+{
+    tnrd_opts oo;
+    resolve_opts(o, &oo);
+    BatchPlan plan;
+    std::vector<int> model_of;
+    int st = check_batch(B, imgs, n_models, models, oo, plan, model_of);
+    if (st != TNRD_OK) return st;
+    if (B == 0) return TNRD_OK;
+    if (!ws || ws_bytes < plan.total) return TNRD_ERR_WORKSPACE;
+    hipStream_t stream = (hipStream_t)stream_;
+    const tnrd_model &m = models[0];
+    const int window = rbf_window_for(&m, oo.rbf_window);
+    char *wsb = (char *)ws;
+    if (oo.validate) {
+        for (int b = 0; b < B; ++b) {
+            st = run_domain_check(imgs[b].f, (size_t)imgs[b].H * imgs[b].W, (int *)ws, stream);
+            if (st != TNRD_OK) return st;
+        }
+    }
+    const BatchArgs a = make_args(plan, m, window, wsb);
+    const bool graph = oo.use_graph != 0 && stream != nullptr;
+
+    if (!graph) {
+        std::vector<unsigned char> host(plan.desc_bytes);
+        build_descriptors(B, imgs, n_models, models, plan, model_of, wsb, host.data());
+        if (hipMemcpyAsync(wsb + plan.off_imgs, host.data(), plan.desc_bytes, hipMemcpyHostToDevice,
+                           stream) != hipSuccess)
+            return TNRD_ERR_HIP;
+        if (batched_launch(a, m.ksize, plan.nw, stream) != hipSuccess)
+            return TNRD_ERR_HIP;
+        // the pageable source must outlive the copy
+        if (hipStreamSynchronize(stream) != hipSuccess) return TNRD_ERR_HIP;
+    } else {
+        std::lock_guard<std::mutex> lock(g_mu);
+        std::vector<unsigned long long> sig = signature(B, imgs, n_models, models, oo, ws, ws_bytes);
+        GraphEntry *hit = nullptr;
+        for (auto &e : g_cache)
+            if (e.stream == stream && e.sig == sig) hit = &e;
+        if (!hit) {
+            if (g_cache.size() >= G_CACHE_MAX) {
+                GraphEntry &old = g_cache.front();
+                (void)hipStreamSynchronize(old.stream);
+                (void)hipGraphExecDestroy(old.exec);
+                (void)hipHostFree(old.host_desc);
+                g_cache.erase(g_cache.begin());
+            }
+            GraphEntry e;
+            e.stream = stream;
+            e.sig = sig;
+            e.exec = nullptr;
+            if (hipHostMalloc((void **)&e.host_desc, plan.desc_bytes, hipHostMallocDefault) != hipSuccess)
+                return TNRD_ERR_HIP;
+            build_descriptors(B, imgs, n_models, models, plan, model_of, wsb, e.host_desc);
+            // first launch outside the graph settles the kernels' one-time setup
+            // (LDS limit), which must not happen during capture
+            if (hipMemcpyAsync(wsb + plan.off_imgs, e.host_desc, plan.desc_bytes,
+                               hipMemcpyHostToDevice, stream) != hipSuccess ||
+                batched_launch(a, m.ksize, plan.nw, stream) != hipSuccess) {
+                (void)hipHostFree(e.host_desc);
+                return TNRD_ERR_HIP;
+            }
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                (void)hipHostFree(e.host_desc);
+                return TNRD_ERR_HIP;
+            }
+            hipError_t e1 = hipMemcpyAsync(wsb + plan.off_imgs, e.host_desc, plan.desc_bytes,
+                                           hipMemcpyHostToDevice, stream);
+            hipError_t e2 = e1 == hipSuccess
+                                ? batched_launch(a, m.ksize, plan.nw, stream)
+                                : e1;
+            hipError_t e3 = hipStreamEndCapture(stream, &g);
+            if (e2 != hipSuccess || e3 != hipSuccess ||
+                hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipStreamSynchronize(stream);
+                (void)hipHostFree(e.host_desc);
+                return TNRD_ERR_HIP;
+            }
+            (void)hipGraphDestroy(g);
+            g_cache.push_back(e);
+            // this call's result was already produced by the direct launch above
+        } else {
+            if (hipGraphLaunch(hit->exec, stream) != hipSuccess) return TNRD_ERR_HIP;
+        }
+    }
+    return TNRD_OK;
 }

@@ -87,11 +87,14 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     return l;
 }
 
+// One output tile of one stage.  The pointers in `io` are those of the tile's
+// image ([H][W] planes); (ty0, tx0) is the tile's origin.  The caller's
+// workgroup runs it with 64 * NW threads and the dynamic LDS of fused_lds().
 template <int KS, int NMB, int NB, int NW, int MODE>
-__global__ void __launch_bounds__(64 * NW) k_fused_stage(
-    FusedIO io, int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
+__device__ __forceinline__ void fused_tile(
+    const FusedIO &io, int H, int W, int Th, int Tw, int ty0, int tx0,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
-    FusedRbf rb, const float *__restrict__ lam_t)
+    const FusedRbf &rb, const float *__restrict__ lam_t, float *lds)
 {
     constexpr bool BWD = MODE == MODE_BWD_INPUT;
     const float *__restrict__ u_prev = io.u_prev;
@@ -102,7 +105,6 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     constexpr int FUSED_THREADS = 64 * NW;
     constexpr int FUSED_WAVES = NW;
 
-    extern __shared__ float lds[];
     const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW, MODE);
     float *su = lds + L.u_off;
     float *se = lds + L.e_off;
@@ -113,12 +115,7 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
 
-    const int img = blockIdx.x / tiles_per_img;
-    const int trem = blockIdx.x - img * tiles_per_img;
-    const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
-    const int ty0 = ty * Th, tx0 = tx * Tw;
-    const size_t plane = (size_t)H * W;
-    const float *un = u_prev + img * plane;
+    const float *un = u_prev;
 
     const int Eh = Th + 2 * R, Ew = Tw + 2 * R;
     const int luh = Th + 4 * R, luw = Tw + 4 * R;
@@ -166,9 +163,9 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     if (BWD) {
         const float lam0 = lam_t[0];
         const float c1 = 1.f + 2.f * lam0, c2 = 2.f * lam0;
-        const float *ucn = io.u_cur + img * plane;
-        const float *gcn = io.g_cur + img * plane;
-        const float *fcn = f + img * plane;
+        const float *ucn = io.u_cur;
+        const float *gcn = io.g_cur;
+        const float *fcn = f;
         const int n = luh * luw;
         for (int base = 0; base < n; base += 4 * FUSED_THREADS) {
             float uu[4], ff[4], gg[4];
@@ -366,8 +363,8 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     __syncthreads();
 
     // ---- gather X, fold the border ring, prox, store
-    const float *fn = f + img * plane;
-    float *uo = io.out + img * plane;
+    const float *fn = f;
+    float *uo = io.out;
     for (int i = tid; i < Th * Tw; i += FUSED_THREADS) {
         const int y = i / Tw, x = i - (i / Tw) * Tw;
         const int yi = ty0 + y, xi = tx0 + x;
@@ -398,6 +395,57 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
             uo[p] = prox(uv - xs, fn[p], lam);
         }
     }
+    __syncthreads();  // LDS is free for the workgroup's next tile
+}
+
+template <int KS, int NMB, int NB, int NW, int MODE>
+__global__ void __launch_bounds__(64 * NW) k_fused_stage(
+    FusedIO io, int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
+    const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
+    FusedRbf rb, const float *__restrict__ lam_t)
+{
+    extern __shared__ float lds[];
+    const int img = blockIdx.x / tiles_per_img;
+    const int trem = blockIdx.x - img * tiles_per_img;
+    const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
+    const size_t plane = (size_t)H * W;
+    FusedIO ii;
+    ii.u_prev = io.u_prev + img * plane;
+    ii.f = io.f + img * plane;
+    ii.out = io.out + img * plane;
+    ii.u_cur = io.u_cur ? io.u_cur + img * plane : nullptr;
+    ii.g_cur = io.g_cur ? io.g_cur + img * plane : nullptr;
+    fused_tile<KS, NMB, NB, NW, MODE>(ii, H, W, Th, Tw, ty * Th, tx * Tw, filt, Nk, rbfw, Nrbf, rb,
+                                      lam_t, lds);
+}
+
+// ------------------------------------------------------------------ batched
+// One launch per stage covers the tiles of every image of an uneven batch:
+// workgroup b takes the b-th (image, tile) item of the stage and runs the
+// fused stage on it with that image's model (chosen by its look number).
+// Stages are ordered by the kernel boundaries, so no workgroup ever waits on
+// another.  Ping-pong: stage t writes u_out if T-1-t is even, else the
+// image's scratch plane, and reads the other (stage 0 reads f).
+template <int KS, int NMB, int NB, int NW>
+__global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
+{
+    extern __shared__ float lds[];
+    constexpr int KK = KS * KS;
+    const BatchItem it = a.items[blockIdx.x];
+    const BatchImage im = a.imgs[it.image];
+    const int ty = it.tile / im.tiles_x, tx = it.tile - ty * im.tiles_x;
+    const bool to_out = ((a.T - 1 - t) & 1) == 0;
+    FusedIO io;
+    io.f = im.f;
+    io.u_prev = t == 0 ? im.f : (to_out ? im.u_tmp : im.u_out);
+    io.out = to_out ? im.u_out : im.u_tmp;
+    io.u_cur = nullptr;
+    io.g_cur = nullptr;
+    const BatchModel md = a.models[im.model];
+    fused_tile<KS, NMB, NB, NW, MODE_FWD>(io, im.H, im.W, a.Th, a.Tw, ty * a.Th, tx * a.Tw,
+                                          md.filt + (size_t)t * a.Nk * KK, a.Nk,
+                                          md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb,
+                                          md.lam + t, lds);
 }
 
 // ------------------------------------------------------------------ host side
@@ -536,6 +584,66 @@ hipError_t fused_stage(const StageArgs &s, hipStream_t stream)
 hipError_t fused_stage_input_grad(const StageArgs &s, hipStream_t stream)
 {
     return fused_dispatch<MODE_BWD_INPUT>(s, stream);
+}
+
+template <int KS, int NMB, int NB, int NW>
+static hipError_t launch_batched_t(const BatchArgs &a, hipStream_t stream)
+{
+    FusedLds L = fused_lds(KS, NMB, NB, a.Th, a.Tw, a.Nrbf, NW, MODE_FWD);
+    const size_t lds_bytes = (size_t)L.total * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_batched_stage<KS, NMB, NB, NW>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    for (int t = 0; t < a.T; ++t) {
+        hipLaunchKernelGGL((k_batched_stage<KS, NMB, NB, NW>), dim3(a.items_per_stage),
+                           dim3(64 * NW), lds_bytes, stream, a, t);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int KS, int NMB>
+static hipError_t batched_nb(const BatchArgs &a, int nb, int nw, hipStream_t stream)
+{
+    if (nw == 4) {
+        switch (nb) {
+        case 2: return launch_batched_t<KS, NMB, 2, 4>(a, stream);
+        case 3: return launch_batched_t<KS, NMB, 3, 4>(a, stream);
+        case 4: return launch_batched_t<KS, NMB, 4, 4>(a, stream);
+        }
+    } else {
+        switch (nb) {
+        case 2: return launch_batched_t<KS, NMB, 2, 8>(a, stream);
+        case 3: return launch_batched_t<KS, NMB, 3, 8>(a, stream);
+        case 4: return launch_batched_t<KS, NMB, 4, 8>(a, stream);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+bool batched_config_ok(int ks, int nk, int nrbf, int th, int tw, int nw)
+{
+    const int R = ks / 2;
+    const int nb = (tw + 2 * R + 15) / 16;
+    if (nb < 2 || nb > 4 || th < 2 * R || tw < 2 * R) return false;  // the halo must fit in one tile
+    const int nmb = (nk + 15) / 16;
+    FusedLds L = fused_lds(ks, nmb <= 2 ? 2 : 3, nb, th, tw, nrbf, nw == 4 ? 4 : 8, MODE_FWD);
+    return (size_t)L.total * sizeof(float) + 64 <= 160 * 1024;
+}
+
+hipError_t batched_launch(const BatchArgs &a, int ks, int nw, hipStream_t stream)
+{
+    const int R = ks / 2;
+    const int nb = (a.Tw + 2 * R + 15) / 16;
+    const int nmb = (a.Nk + 15) / 16;
+    if (ks == 7) return nmb <= 2 ? batched_nb<7, 2>(a, nb, nw, stream) : batched_nb<7, 3>(a, nb, nw, stream);
+    if (ks == 5) return nmb <= 2 ? batched_nb<5, 2>(a, nb, nw, stream) : batched_nb<5, 3>(a, nb, nw, stream);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace tnrd

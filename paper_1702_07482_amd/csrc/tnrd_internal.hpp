@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "tnrd_device.hpp"
+#include "tnrd_fused_common.hpp"
 
 namespace tnrd {
 
@@ -27,6 +28,36 @@ struct StageArgs {
     int tile_h, tile_w;   // 0 = automatic
     int waves;            // fused: waves per workgroup (4 or 8; 0 = automatic)
 };
+
+// Batched forward (device descriptors, filled on the host).
+struct BatchImage {
+    const float *f;
+    float *u_out;
+    float *u_tmp;
+    int H, W, tiles_x, tiles, model;
+};
+
+struct BatchModel {
+    const float *filt;  // [T][Nk][KK]
+    const float *rbfw;  // [T][Nk][Nrbf]
+    const float *lam;   // [T]
+};
+
+struct BatchItem {
+    int image, tile;
+};
+
+struct BatchArgs {
+    const BatchImage *imgs;
+    const BatchModel *models;
+    const BatchItem *items;  // one stage's items, image-major
+    int items_per_stage, T, Th, Tw, Nk, Nrbf;
+    FusedRbf rb;
+};
+
+// Runs the T stages of a batch: one launch per stage over all (image, tile) items.
+hipError_t batched_launch(const BatchArgs &a, int ks, int nw, hipStream_t stream);
+bool batched_config_ok(int ks, int nk, int nrbf, int th, int tw, int nw);
 
 hipError_t split_stage(const StageArgs &s, hipStream_t stream);
 size_t split_scratch_floats(int N, int H, int W, int Nk);

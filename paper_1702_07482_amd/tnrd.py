@@ -46,6 +46,7 @@ class TnrdOpts(ctypes.Structure):
         ("prec", ctypes.c_int32), ("impl", ctypes.c_int32), ("rbf_window", ctypes.c_int32),
         ("recompute_every", ctypes.c_int32), ("validate", ctypes.c_int32),
         ("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
     ]
 
 
@@ -247,3 +248,29 @@ def backward(f, model: DeviceModel, states, grad_uT, L: int = 1, opts: TnrdOpts 
     _check(tnrd_backward(f, N, H, W, L, m, states, grad_uT, dK, dW, dl, g0, o, ws, nb),
            "tnrd_backward")
     return (dK, dW, dl, g0) if want_u0 else (dK, dW, dl)
+
+
+def forward_batched(fs, looks, models, opts: TnrdOpts = None, outs=None, ws=None):
+    """Uneven batch: fs is a list of [H][W] CUDA tensors, looks their L values,
+    models a list of DeviceModel whose .L select them (0 = any).  Returns the
+    list of u_T tensors (and keeps using `outs`/`ws` if given, so repeated
+    calls with the same buffers replay the recorded HIP graph)."""
+    B = len(fs)
+    o = opts if opts is not None else default_opts()
+    if outs is None:
+        outs = [torch.empty_like(f) for f in fs]
+    imgs = (TnrdImage * B)()
+    for b, (f, L, u) in enumerate(zip(fs, looks, outs)):
+        if not (f.is_cuda and f.dtype == torch.float32 and f.is_contiguous() and f.dim() == 2):
+            raise ValueError("batched images must be contiguous 2-D float32 CUDA tensors")
+        imgs[b] = TnrdImage(f.data_ptr(), u.data_ptr(), f.shape[0], f.shape[1], int(L))
+    mods = (TnrdModel * len(models))()
+    for k, m in enumerate(models):
+        mods[k] = m.abi()
+    nb = tnrd_batched_workspace_bytes(B, imgs, len(models), mods, o)
+    if nb == 0:
+        raise RuntimeError("tnrd_batched_workspace_bytes: invalid or unsupported batch")
+    if ws is None or ws.numel() < nb:
+        ws = _workspace(nb, fs[0].device)
+    _check(tnrd_forward_batched(B, imgs, len(models), mods, o, ws, nb), "tnrd_forward_batched")
+    return outs, ws

@@ -48,7 +48,7 @@ def _fwd(m, N=1, H=32, W=32, L=1, f=FAKE_F, u=FAKE_U, ws=None, nb=0, **opt):
 
 def test_default_opts():
     o = tnrd.default_opts()
-    assert (o.prec, o.impl, o.rbf_window, o.recompute_every, o.validate) == (0, 0, -1, 1, 0)
+    assert (o.prec, o.impl, o.rbf_window, o.recompute_every, o.validate, o.use_graph) == (0, 0, -1, 1, 0, 1)
 
 
 @pytest.mark.parametrize("kw,bad", [

@@ -1,0 +1,114 @@
+"""Batched uneven forward (tnrd_forward_batched: one launch per stage over the
+tiles of every image, replayed from a HIP graph) against per-image
+tnrd_forward and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1702_07482_amd import synth, tnrd
+from tests.helpers import oracle_uT_at, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _models(looks, cfg=4):
+    return {L: synth.config_model(cfg, look=L) for L in sorted(set(looks))}
+
+
+def _per_image(f, m, L, opts):
+    dm = tnrd.DeviceModel.from_numpy(m, L=L)
+    return tnrd.forward(_dev(f), dm, L=L, opts=opts).cpu().numpy()[0]
+
+
+def test_small_uneven_batch_matches_per_image_and_oracle():
+    sizes = [(40, 52), (96, 64), (33, 90), (64, 64), (120, 75), (7, 7)]
+    looks = [1, 4, 1, 2, 4, 2]
+    ms = _models(looks)
+    fs = [synth.make_pair(h, w, L, config_id=4, index=i)[1] for i, ((h, w), L) in enumerate(zip(sizes, looks))]
+    dms = [tnrd.DeviceModel.from_numpy(ms[L], L=L) for L in sorted(ms)]
+    o = tnrd.default_opts(use_graph=0, validate=1)
+    outs, _ = tnrd.forward_batched([_dev(f) for f in fs], looks, dms, opts=o)
+    torch.cuda.synchronize()
+    fo = tnrd.default_opts(tile_h=32, tile_w=32, wg_waves=8, impl=tnrd.IMPL_FUSED)
+    for b, (f, L) in enumerate(zip(fs, looks)):
+        ref = _per_image(f, ms[L], L, fo)
+        np.testing.assert_array_equal(outs[b].cpu().numpy(), ref, err_msg=f"image {b}")
+    for b in (2, 5):
+        ref = oracle.forward(fs[b], ms[looks[b]])
+        assert rel_inf(outs[b].cpu().numpy(), ref) <= TOL
+
+
+def test_graph_replay_recomputes_with_new_inputs():
+    sizes = [(64, 80), (50, 45), (96, 96)]
+    looks = [1, 2, 1]
+    ms = _models(looks)
+    dms = [tnrd.DeviceModel.from_numpy(ms[L], L=L) for L in sorted(ms)]
+    fs = [_dev(synth.make_pair(h, w, L, config_id=4, index=10 + i)[1])
+          for i, ((h, w), L) in enumerate(zip(sizes, looks))]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        og = tnrd.default_opts(use_graph=1)
+        outs, ws = tnrd.forward_batched(fs, looks, dms, opts=og)  # records
+        for rep in range(3):
+            # new contents in the same buffers, then a replay
+            for i, f in enumerate(fs):
+                f.copy_(_dev(synth.make_pair(*sizes[i], looks[i], config_id=4, index=20 + 3 * rep + i)[1]))
+            tnrd.forward_batched(fs, looks, dms, opts=og, outs=outs, ws=ws)
+            got = [u.clone() for u in outs]
+            ref, _ = tnrd.forward_batched(fs, looks, dms, opts=tnrd.default_opts(use_graph=0))
+            s.synchronize()
+            for a, b in zip(got, ref):
+                torch.testing.assert_close(a, b, rtol=0, atol=0)
+
+
+def test_model_selection_by_looks():
+    ms = _models([1, 4])
+    f = synth.make_pair(40, 40, 8, config_id=4, index=30)[1]
+    d1 = tnrd.DeviceModel.from_numpy(ms[1], L=1)
+    d0 = tnrd.DeviceModel.from_numpy(ms[4], L=0)  # matches any L
+    o = tnrd.default_opts(use_graph=0)
+    outs, _ = tnrd.forward_batched([_dev(f)], [8], [d1, d0], opts=o)
+    ref = oracle.forward(f, ms[4])
+    assert rel_inf(outs[0].cpu().numpy(), ref) <= TOL
+    with pytest.raises(RuntimeError):
+        tnrd.forward_batched([_dev(f)], [8], [d1], opts=o)
+
+
+def test_c4_full_batch():
+    """64 images from {256x256, 384x512, 512x512, 1024x768}, L in {1,2,4,8}:
+    sampled images equal per-image tnrd_forward bit for bit; sampled pixels
+    equal the oracle (crops covering the receptive field)."""
+    sizes, looks = synth.c4_batch(64)
+    ms = _models(looks)
+    dms = [tnrd.DeviceModel.from_numpy(ms[L], L=L) for L in sorted(ms)]
+    fs = [synth.make_pair(h, w, L, config_id=4, index=100 + i)[1]
+          for i, ((h, w), L) in enumerate(zip(sizes, looks))]
+    print(f"[c4 batch: {sum(h * w for h, w in sizes) / 1e6:.2f} MP]", flush=True)
+    outs, ws = tnrd.forward_batched([_dev(f) for f in fs], looks, dms, opts=tnrd.default_opts(validate=1))
+    torch.cuda.synchronize()
+    fo = tnrd.default_opts(tile_h=32, tile_w=32, wg_waves=8, impl=tnrd.IMPL_FUSED)
+    for b in (0, 17, 40, 63):
+        ref = _per_image(fs[b], ms[looks[b]], looks[b], fo)
+        np.testing.assert_array_equal(outs[b].cpu().numpy(), ref, err_msg=f"image {b}")
+    radius = 8 * 6
+    for b in (5, 33):
+        h, w = sizes[b]
+        pts = [(0, 0), (h - 1, w // 2), (h // 2, w - 1), (h // 3, w // 3)]
+        ref = oracle_uT_at(fs[b], ms[looks[b]], pts, radius)
+        got = np.array([outs[b].cpu().numpy()[p] for p in pts])
+        assert np.abs(got - ref).max() <= TOL * np.abs(ref).max(), (b, got, ref)
+
+
+@pytest.mark.skip(reason="The single persistent launch over all stages (work items handed out "
+                         "by an atomic counter, per-tile stage flags) hung twice on the GPU, the "
+                         "second time with a wall-clock-bounded wait; its cause is not found, so "
+                         "that variant is switched off and batches run one launch per stage.")
+def test_persistent_single_launch_variant():
+    pass
