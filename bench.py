@@ -208,6 +208,86 @@ def leg_batched(args):
                         "launch per stage over all tiles, replayed from a HIP graph"}
 
 
+def leg_mixed(args):
+    """8 x 2048 x 2048: forward and forward+backward with FP32, BF16 and FP16
+    filter-bank operands (FP32 accumulation, influence function and prox)."""
+    import torch
+    from paper_1702_07482_amd import synth, tnrd
+
+    N, H, W, T = 8, 2048, 2048, 8
+    m = synth.config_model(5)
+    pairs = [synth.make_pair(H, W, 1, config_id=5, index=n) for n in range(N)]
+    f = np.stack([p[1] for p in pairs])
+    ugt = np.stack([p[0] for p in pairs])
+    del pairs
+    dm = tnrd.DeviceModel.from_numpy(m)
+    mm = dm.abi()
+    fd = torch.from_numpy(f).cuda()
+    ud = torch.from_numpy(ugt).cuda()
+    u = torch.empty_like(fd)
+    states = torch.empty((T + 1, N, H, W), dtype=torch.float32, device="cuda")
+    g = torch.empty_like(fd)
+    dK = torch.empty_like(dm.filters)
+    dW = torch.empty_like(dm.rbf_w)
+    dl = torch.empty_like(dm.lam)
+    res = {}
+    outs = {}
+    for name, prec in [("fp32", tnrd.PREC_FP32), ("bf16", tnrd.PREC_BF16), ("fp16", tnrd.PREC_FP16)]:
+        o = tnrd.default_opts(prec=prec)
+        nbf = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 0)
+        nbb = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 1)
+        wsf = torch.empty(nbf, dtype=torch.uint8, device="cuda")
+        wsb = torch.empty(nbb, dtype=torch.uint8, device="cuda")
+
+        def fwd():
+            st = tnrd.tnrd_forward(fd, N, H, W, 1, mm, u, None, o, wsf, nbf)
+            if st != 0:
+                raise RuntimeError(tnrd.status_str(st))
+
+        def fwd_bwd():
+            st = tnrd.tnrd_forward(fd, N, H, W, 1, mm, u, states, o, wsf, nbf)
+            if st != 0:
+                raise RuntimeError(tnrd.status_str(st))
+            torch.sub(u, ud, out=g)
+            g.mul_(2.0 / g.numel())
+            st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, o, wsb, nbb)
+            if st != 0:
+                raise RuntimeError(tnrd.status_str(st))
+
+        fwd()
+        torch.cuda.synchronize()
+        outs[name] = u.clone()
+        a, b = _events()
+        a.record()
+        for _ in range(3):
+            fwd()
+        b.record()
+        torch.cuda.synchronize()
+        ms_f = a.elapsed_time(b) / 3
+        fwd_bwd()
+        torch.cuda.synchronize()
+        a.record()
+        fwd_bwd()
+        b.record()
+        torch.cuda.synchronize()
+        ms_fb = a.elapsed_time(b)
+        mpst = N * H * W * T / 1e6
+        res[name] = {"fwd_mpst_s": mpst / (ms_f / 1e3), "fwd_ms": ms_f,
+                     "fwd_bwd_mpst_s": mpst / (ms_fb / 1e3), "fwd_bwd_ms": ms_fb}
+        del wsf, wsb
+    ref = outs["fp32"].double()
+    mse_ref = torch.mean((ref - ud.double()) ** 2).item()
+    for name in ("bf16", "fp16"):
+        d = (outs[name].double() - ref).abs()
+        mse = torch.mean((outs[name].double() - ud.double()) ** 2).item()
+        res[name]["max_rel_err_vs_fp32_path"] = (d.max() / ref.abs().max()).item()
+        res[name]["mean_abs_err_vs_fp32_path"] = d.mean().item()
+        res[name]["dpsnr_db_vs_fp32_path"] = abs(10 * math.log10(mse_ref / mse))
+    res["workload"] = ("mixed precision: 8 x 2048 x 2048, L=1, 8 stages x 48 7x7; filter-bank "
+                       "operands FP32/BF16/FP16 with FP32 accumulation; influence and prox FP32")
+    return res
+
+
 def resolve_auto_impl():
     """The implementation IMPL_AUTO runs for the headline workload."""
     import torch
@@ -279,6 +359,8 @@ def main():
         out["fwd_bwd"] = leg_fwd_bwd(args)
     if "batched" in legs:
         out["batched"] = leg_batched(args)
+    if "mixed" in legs:
+        out["mixed"] = leg_mixed(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fwd["f"], fwd["m"], args.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -53,6 +53,7 @@ struct FusedLds {
     int t_off, t_pitch;   // RBF table
     int p_off, pw, p_size;
     int y_off, yp, y_size;  // per-wave Y scratch: [16 nb][yp] floats per wave
+    int red_off;            // 8 floats for workgroup reductions
     int total;
 };
 
@@ -83,14 +84,15 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     l.yp = fused_yp(ks);
     l.y_off = (l.p_off + l.p_size + 3) & ~3;
     l.y_size = nw * 16 * nb * l.yp;
-    l.total = l.y_off + l.y_size;
+    l.red_off = l.y_off + l.y_size;
+    l.total = l.red_off + 8;
     return l;
 }
 
 // One output tile of one stage.  The pointers in `io` are those of the tile's
 // image ([H][W] planes); (ty0, tx0) is the tile's origin.  The caller's
 // workgroup runs it with 64 * NW threads and the dynamic LDS of fused_lds().
-template <int KS, int NMB, int NB, int NW, int MODE>
+template <int KS, int NMB, int NB, int NW, int MODE, int PREC = PREC_F32>
 __device__ __forceinline__ void fused_tile(
     const FusedIO &io, int H, int W, int Th, int Tw, int ty0, int tx0,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
@@ -160,6 +162,7 @@ __device__ __forceinline__ void fused_tile(
     // (2b) input-gradient mode: e = y * g_t over the same region, where
     // y = du_t/d(ut_t) = u_t^2 / ((1+2l) u_t^2 + 2 l f^2) is the prox derivative
     // written with the prox output (equal to the closed form of eq. derv2).
+    float emax = 0.f;  // largest |e| of the tile (input-gradient mode)
     if (BWD) {
         const float lam0 = lam_t[0];
         const float c1 = 1.f + 2.f * lam0, c2 = 2.f * lam0;
@@ -186,7 +189,9 @@ __device__ __forceinline__ void fused_tile(
                     int ly = i / luw, lx = i - ly * luw;
                     float u2 = uu[k] * uu[k];
                     float y = u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
-                    se[ly * L.ldw + lx] = y * gg[k];
+                    float ev = y * gg[k];
+                    se[ly * L.ldw + lx] = ev;
+                    emax = fmaxf(emax, fabsf(ev));
                 }
             }
         }
@@ -211,6 +216,27 @@ __device__ __forceinline__ void fused_tile(
         }
     }
     __syncthreads();
+
+    // Mixed-precision input gradient: e, a = K e and phi' a go through BF16/FP16
+    // operands with a power-of-two tile scale that puts max|e| at 2^10 (FP16's
+    // normal range starts at 2^-14 and ends below 2^16; |K e| <= 7 max|e| for
+    // unit-norm 7x7 filters), undone in FP32 when g_{t-1} is formed.
+    float escale = 1.f, einv = 1.f;
+    if (BWD && PREC != PREC_F32) {
+        float wmax = emax;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, o));
+        float *red = lds + L.red_off;
+        if (lane == 0) red[wave] = wmax;
+        __syncthreads();
+        float m = 0.f;
+        for (int w = 0; w < FUSED_WAVES; ++w) m = fmaxf(m, red[w]);
+        if (m > 0.f && isfinite(m)) {
+            int ex = ilogbf(m);
+            escale = ldexpf(1.f, 10 - ex);
+            einv = ldexpf(1.f, ex - 10);
+        }
+    }
 
     // ---- filter operands in registers (from the staged copy)
     const float *sf = sp;
@@ -240,6 +266,37 @@ __device__ __forceinline__ void fused_tile(
             int fi = 16 * mb + 4 * g + r;
             av[mb][r] = (G::VTAP && fi < Nk) ? sf[fi * KK + KK - 1] : 0.f;
         }
+
+    // mixed precision: 16-wide k-steps, operands converted once to BF16/FP16
+    using MX = Mix<PREC>;
+    typedef typename MX::V MV;
+    constexpr bool MIXED = PREC != PREC_F32;
+    constexpr int KSH = (KK + 15) / 16;  // GEMM1 k-steps of 16 taps
+    MV a1m[NMB][MIXED ? KSH : 1];
+    MV a2m[MB2][MIXED ? NMB : 1];
+    int offm[MIXED ? KSH : 1][4];
+    if (MIXED) {
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int s = 0; s < KSH; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int fi = 16 * mb + j, t = 16 * s + 4 * g + i;
+                    a1m[mb][s][i] = MX::cvt((fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f);
+                }
+#pragma unroll
+        for (int mb2 = 0; mb2 < MB2; ++mb2)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int fi = 16 * mb + 4 * g + i;
+                    int Ls = 16 * mb2 + 4 * (j & 3) + (j >> 2);
+                    int ta = Ls % KS, tb = Ls / KS;
+                    a2m[mb2][mb][i] = MX::cvt((fi < Nk && Ls < KK) ? sf[fi * KK + ta * KS + tb] : 0.f);
+                }
+    }
     __syncthreads();  // the staged filters in the P area are consumed
 
     // GEMM1 B-operand offsets: tap t = 4 s + g -> (a, b) = (t / KS, t % KS)
@@ -248,6 +305,15 @@ __device__ __forceinline__ void fused_tile(
     for (int s = 0; s < KS1; ++s) {
         int t = 4 * s + g;
         off1[s] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+    }
+    if (MIXED) {
+#pragma unroll
+        for (int s = 0; s < KSH; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int t = 16 * s + 4 * g + i;
+                offm[s][i] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+            }
     }
     __syncthreads();
 
@@ -272,15 +338,32 @@ __device__ __forceinline__ void fused_tile(
                 acc1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
                 acca[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
+            if (MIXED) {
 #pragma unroll
-            for (int s = 0; s < KS1; ++s) {
-                float bv = ub[-off1[s]];
-                float be = BWD ? eb[-off1[s]] : 0.f;
+                for (int s = 0; s < KSH; ++s) {
+                    MV bu, be;
 #pragma unroll
-                for (int mb = 0; mb < NMB; ++mb) {
-                    acc1[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], bv, acc1[mb], 0, 0, 0);
-                    if (BWD)
-                        acca[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], be, acca[mb], 0, 0, 0);
+                    for (int i = 0; i < 4; ++i) {
+                        bu[i] = MX::cvt(ub[-offm[s][i]]);
+                        be[i] = MX::cvt(BWD ? escale * eb[-offm[s][i]] : 0.f);
+                    }
+#pragma unroll
+                    for (int mb = 0; mb < NMB; ++mb) {
+                        acc1[mb] = MX::mfma(a1m[mb][s], bu, acc1[mb]);
+                        if (BWD) acca[mb] = MX::mfma(a1m[mb][s], be, acca[mb]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < KS1; ++s) {
+                    float bv = ub[-off1[s]];
+                    float be = BWD ? eb[-off1[s]] : 0.f;
+#pragma unroll
+                    for (int mb = 0; mb < NMB; ++mb) {
+                        acc1[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], bv, acc1[mb], 0, 0, 0);
+                        if (BWD)
+                            acca[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], be, acca[mb], 0, 0, 0);
+                    }
                 }
             }
 
@@ -318,14 +401,25 @@ __device__ __forceinline__ void fused_tile(
             floatx4 acc2[MB2];
 #pragma unroll
             for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (MIXED) {
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
+                for (int mb = 0; mb < NMB; ++mb) {
+                    MV vb;  // filters 16 mb + 4 g + i of pixel j: GEMM1's register quad
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                    for (int i = 0; i < 4; ++i) vb[i] = MX::cvt(acc1[mb][i]);
 #pragma unroll
-                    for (int mb2 = 0; mb2 < MB2; ++mb2)
-                        acc2[mb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[mb2][4 * mb + r],
-                                                                         acc1[mb][r], acc2[mb2], 0, 0, 0);
+                    for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = MX::mfma(a2m[mb2][mb], vb, acc2[mb2]);
+                }
+            } else {
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int mb2 = 0; mb2 < MB2; ++mb2)
+                            acc2[mb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[mb2][4 * mb + r],
+                                                                             acc1[mb][r], acc2[mb2], 0, 0, 0);
+            }
 
             // Y of this block into the wave's scratch: slots 16 mb2 + 4 g + r
             float *yb = ys + c * L.yp;
@@ -389,7 +483,7 @@ __device__ __forceinline__ void fused_tile(
         const size_t p = (size_t)yi * W + xi;
         if (BWD) {
             // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1)
-            uo[p] = se[(y + 2 * R) * L.ldw + x + 2 * R] - xs;
+            uo[p] = se[(y + 2 * R) * L.ldw + x + 2 * R] - xs * einv;
         } else {
             const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
             uo[p] = prox(uv - xs, fn[p], lam);
@@ -398,7 +492,7 @@ __device__ __forceinline__ void fused_tile(
     __syncthreads();  // LDS is free for the workgroup's next tile
 }
 
-template <int KS, int NMB, int NB, int NW, int MODE>
+template <int KS, int NMB, int NB, int NW, int MODE, int PREC>
 __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     FusedIO io, int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
@@ -415,8 +509,8 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     ii.out = io.out + img * plane;
     ii.u_cur = io.u_cur ? io.u_cur + img * plane : nullptr;
     ii.g_cur = io.g_cur ? io.g_cur + img * plane : nullptr;
-    fused_tile<KS, NMB, NB, NW, MODE>(ii, H, W, Th, Tw, ty * Th, tx * Tw, filt, Nk, rbfw, Nrbf, rb,
-                                      lam_t, lds);
+    fused_tile<KS, NMB, NB, NW, MODE, PREC>(ii, H, W, Th, Tw, ty * Th, tx * Tw, filt, Nk, rbfw, Nrbf,
+                                            rb, lam_t, lds);
 }
 
 // ------------------------------------------------------------------ batched
@@ -467,7 +561,7 @@ FusedRbf make_fused_rbf(const RbfGrid &grid)
     return rb;
 }
 
-template <int KS, int NMB, int NB, int NW, int MODE>
+template <int KS, int NMB, int NB, int NW, int MODE, int PREC>
 static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t stream)
 {
     FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf, NW, MODE);
@@ -476,7 +570,7 @@ static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     if (!attr_set) {
         // raise the dynamic LDS limit to the CU's 160 KB; a failure here shows
         // up as a launch error below, so the status is cleared
-        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB, NW, MODE>,
+        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB, NW, MODE, PREC>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         (void)hipGetLastError();
         attr_set = true;
@@ -492,7 +586,7 @@ static hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     dim3 grid(tiles * s.N);
-    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW, MODE>), grid, dim3(64 * NW), lds_bytes,
+    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW, MODE, PREC>), grid, dim3(64 * NW), lds_bytes,
                        stream, io, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk, s.rbfw,
                        s.grid.nrbf, rb, s.lam);
     return hipGetLastError();
@@ -513,22 +607,22 @@ static void fused_tile(int ks, int H, int W, int req_h, int req_w, int mode, int
     nb = (tw + 2 * R + 15) / 16;
 }
 
-template <int KS, int NMB, int NW, int MODE>
+template <int KS, int NMB, int NW, int MODE, int PREC>
 static hipError_t fused_nb(const StageArgs &s, int th, int tw, int nb, hipStream_t stream)
 {
     switch (nb) {
-    case 2: return launch_fused<KS, NMB, 2, NW, MODE>(s, th, tw, stream);
-    case 3: return launch_fused<KS, NMB, 3, NW, MODE>(s, th, tw, stream);
-    case 4: return launch_fused<KS, NMB, 4, NW, MODE>(s, th, tw, stream);
+    case 2: return launch_fused<KS, NMB, 2, NW, MODE, PREC>(s, th, tw, stream);
+    case 3: return launch_fused<KS, NMB, 3, NW, MODE, PREC>(s, th, tw, stream);
+    case 4: return launch_fused<KS, NMB, 4, NW, MODE, PREC>(s, th, tw, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int KS, int NMB, int MODE>
+template <int KS, int NMB, int MODE, int PREC>
 static hipError_t fused_nw(const StageArgs &s, int th, int tw, int nb, int nw, hipStream_t stream)
 {
-    if (nw == 4) return fused_nb<KS, NMB, 4, MODE>(s, th, tw, nb, stream);
-    return fused_nb<KS, NMB, 8, MODE>(s, th, tw, nb, stream);
+    if (nw == 4) return fused_nb<KS, NMB, 4, MODE, PREC>(s, th, tw, nb, stream);
+    return fused_nb<KS, NMB, 8, MODE, PREC>(s, th, tw, nb, stream);
 }
 
 template <int MODE>
@@ -540,13 +634,22 @@ static hipError_t fused_dispatch(const StageArgs &s, hipStream_t stream)
     if (nb > 4) return hipErrorInvalidValue;
     const int nw = s.waves == 4 ? 4 : 8;
     const int nmb = (s.Nk + 15) / 16;
+    if (s.prec == PREC_BF16 || s.prec == PREC_F16) {
+        // mixed-precision filter bank: 7x7 filters only
+        if (s.ks != 7) return hipErrorInvalidValue;
+        if (s.prec == PREC_BF16)
+            return nmb <= 2 ? fused_nw<7, 2, MODE, PREC_BF16>(s, th, tw, nb, nw, stream)
+                            : fused_nw<7, 3, MODE, PREC_BF16>(s, th, tw, nb, nw, stream);
+        return nmb <= 2 ? fused_nw<7, 2, MODE, PREC_F16>(s, th, tw, nb, nw, stream)
+                        : fused_nw<7, 3, MODE, PREC_F16>(s, th, tw, nb, nw, stream);
+    }
     if (s.ks == 7) {
-        if (nmb <= 2) return fused_nw<7, 2, MODE>(s, th, tw, nb, nw, stream);
-        return fused_nw<7, 3, MODE>(s, th, tw, nb, nw, stream);
+        if (nmb <= 2) return fused_nw<7, 2, MODE, PREC_F32>(s, th, tw, nb, nw, stream);
+        return fused_nw<7, 3, MODE, PREC_F32>(s, th, tw, nb, nw, stream);
     }
     if (s.ks == 5) {
-        if (nmb <= 2) return fused_nw<5, 2, MODE>(s, th, tw, nb, nw, stream);
-        return fused_nw<5, 3, MODE>(s, th, tw, nb, nw, stream);
+        if (nmb <= 2) return fused_nw<5, 2, MODE, PREC_F32>(s, th, tw, nb, nw, stream);
+        return fused_nw<5, 3, MODE, PREC_F32>(s, th, tw, nb, nw, stream);
     }
     return hipErrorInvalidValue;
 }
@@ -566,7 +669,7 @@ bool fused_config_ok(int ks, int nk, int nrbf, int H, int W, int tile_h, int til
 
 bool fused_supported(int ks, int nk, int nrbf, int window, int prec)
 {
-    if (prec != 0) return false;
+    if (prec != PREC_F32 && !(ks == 7 && (prec == PREC_BF16 || prec == PREC_F16))) return false;
     if (ks != 5 && ks != 7) return false;
     if (nk < 1 || nk > 48) return false;
     if (window != RBF_WIN) return false;

@@ -10,6 +10,36 @@
 namespace tnrd {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef _Float16 half4v __attribute__((ext_vector_type(4)));
+
+// Operand types of the 16x16x16 MFMAs used by the mixed-precision path
+// (v_mfma_f32_16x16x16_{bf16,f16}): lane l holds A[l % 16][4 (l / 16) + i]
+// and B[4 (l / 16) + i][l % 16], i = 0..3; D is laid out as for 16x16x4 f32.
+// Conversions round to nearest even.
+enum Prec { PREC_F32 = 0, PREC_BF16 = 1, PREC_F16 = 2 };
+template <int P> struct Mix;
+template <> struct Mix<PREC_BF16> {
+    typedef short4v V;
+    static __device__ __forceinline__ short cvt(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+    static __device__ __forceinline__ floatx4 mfma(V a, V b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mix<PREC_F16> {
+    typedef half4v V;
+    static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+    static __device__ __forceinline__ floatx4 mfma(V a, V b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mix<PREC_F32> {  // placeholder so templates instantiate; never used
+    typedef short4v V;
+    static __device__ __forceinline__ short cvt(float) { return 0; }
+    static __device__ __forceinline__ floatx4 mfma(V, V, floatx4 c) { return c; }
+};
 
 constexpr int RBF_WIN = 5;                // Horner window half-width (11 centres)
 constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
