@@ -54,6 +54,29 @@ def parse():
     return ap.parse_args()
 
 
+FUSED_SOURCES = ["paper_1702_07482_amd/csrc/tnrd_fused.hip",
+                 "paper_1702_07482_amd/csrc/tnrd_fused_common.hpp",
+                 "paper_1702_07482_amd/csrc/tnrd_device.hpp"]
+FUSED_PROFILE = "profiles/fused_stage_fwd_512x512_48x7x7.md"
+
+
+def profiled_traffic():
+    """HBM bytes per fused-stage launch from the committed FETCH_SIZE/WRITE_SIZE
+    profile, or None if the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, FUSED_PROFILE)).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in FUSED_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def _events():
     import torch
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -107,7 +130,10 @@ def leg_forward(args, impl_code):
         "roofline": {
             "bound": "alu" if impl_name == "split" else "mfma",
             "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved_tflops / peak, "traffic": None,
+            "frac": achieved_tflops / peak,
+            "traffic": profiled_traffic() if impl_name == "fused" else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": H * W * 12,
             "kernel": "tnrd stage kernel (k_split_* pair)" if impl_name == "split"
                       else "tnrd::k_fused_stage",
             "per_launch_us": per_launch_s * 1e6,
