@@ -173,6 +173,7 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
     s.tile_h = o.tile_h;
     s.tile_w = o.tile_w;
     s.waves = o.wg_waves;
+    s.poly = o.rbf_window < 0;
     const float *cur = u_start;
     const size_t kk = (size_t)m->ksize * m->ksize;
     for (int t = t_begin; t < t_end; ++t) {

@@ -629,6 +629,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     ia.tile_h = 0;
     ia.tile_w = 0;
     ia.waves = 0;
+    ia.poly = 0;
 
     const float *g_cur = grad_uT;
     int ping = 0;

@@ -127,7 +127,8 @@ void build_descriptors(int B, const tnrd_image *imgs, int n_models, const tnrd_m
     }
 }
 
-BatchArgs make_args(const BatchPlan &plan, const tnrd_model &m, int window, char *ws)
+BatchArgs make_args(const BatchPlan &plan, const tnrd_model &m, int window, int automatic_window,
+                    char *ws)
 {
     BatchArgs a;
     a.imgs = (const BatchImage *)(ws + plan.off_imgs);
@@ -139,7 +140,9 @@ BatchArgs make_args(const BatchPlan &plan, const tnrd_model &m, int window, char
     a.Tw = plan.tw;
     a.Nk = m.Nk;
     a.Nrbf = m.Nrbf;
-    a.rb = make_fused_rbf(make_grid(&m, window));
+    const RbfGrid grid = make_grid(&m, window);
+    a.rb = make_fused_rbf(grid);
+    a.poly = poly_form_ok(grid, automatic_window);
     return a;
 }
 
@@ -231,7 +234,7 @@ extern "C" int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models,
             if (st != TNRD_OK) return st;
         }
     }
-    const BatchArgs a = make_args(plan, m, window, wsb);
+    const BatchArgs a = make_args(plan, m, window, oo.rbf_window < 0, wsb);
     const bool graph = oo.use_graph != 0 && stream != nullptr;
 
     if (!graph) {

@@ -44,6 +44,28 @@ template <> struct Mix<PREC_F32> {  // placeholder so templates instantiate; nev
 constexpr int RBF_WIN = 5;                // Horner window half-width (11 centres)
 constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
 
+// Piecewise polynomial form of the influence function (forward only).  On the
+// unit interval of s = (z - mu0) / step around centre j0 (|s - j0| <= 1/2),
+// phi is replaced by its degree-7 interpolant at the Chebyshev points of that
+// interval.  The interpolant is linear in the weights:
+//   phi(j0 + d) ~ sum_k c_k d^k,  c_k = sum_{|m| <= POLY_MW} M[k][|m|] sgn(m)^k w_{j0+m},
+// where M[k][m] are the monomial coefficients of the interpolant of the single
+// Gaussian exp(-rho (d - m)^2 / 2) (rho = (step/sigma)^2), so the table of c_k
+// is rebuilt from the weights in LDS at the start of every tile.  Intervals run
+// over j0 = -W .. Nrbf-1+W (W = RBF_WIN) with one zero interval at each end;
+// beyond them phi is taken as 0, the same cut as the window of the Gaussian
+// form.  Centres farther than POLY_MW spacings from the interval contribute
+// below exp(-rho 6.5^2 / 2) of their weight and are left out.
+constexpr int POLY_DEG = 7;
+constexpr int POLY_NC = POLY_DEG + 1;     // coefficients per interval
+constexpr int POLY_MW = RBF_WIN + 1;      // centres on each side of j0 in the fit
+constexpr int POLY_PAD = RBF_WIN + POLY_MW;  // zero padding of a weight row on each side
+
+__host__ __device__ inline int poly_intervals(int nrbf) { return nrbf + 2 * RBF_WIN + 2; }
+
+// Influence evaluation of the fused stage kernel.
+enum RbfMethod { RBF_HORNER = 0, RBF_POLY = 1 };
+
 // Constants of the windowed Horner evaluation of phi.
 //   s = (z - mu0) / step = j0 + d, j0 the nearest centre, |d| <= 1/2,
 //   G_{j0+m}(z) = exp(-rho (d - m)^2 / 2), rho = (step / sigma)^2
@@ -57,6 +79,7 @@ struct FusedRbf {
     float jmax;           // Nrbf - 1 + W (largest clamped centre index)
     float rho_over_step;  // rho / step (chain factor of d phi / dz)
     float c[RBF_TERMS];
+    float pm[POLY_NC][POLY_MW + 1];  // M[k][m] of the polynomial form
 };
 
 // Kernel arguments of one stage (forward or input-gradient mode).
@@ -80,5 +103,69 @@ struct Geo {
     static constexpr int MB2 = (KK % 16 <= 1) ? KK / 16 : (KK + 15) / 16;  // GEMM2 slot blocks
     static constexpr int VTAP = (KK > 16 * MB2) ? 1 : 0;             // leftover tap on the VALU
 };
+
+// Tap-slot geometry of the fused stage's K^T GEMM: accumulator register
+// R' = 4 mb2 + r holds tap column b = R' / HB and, in lane group g, tap row
+// a = 4 (R' % HB) + g, so that one register is one x-shift for all its lanes.
+template <int KS>
+struct Geo2 {
+    static constexpr int HB = (KS + 3) / 4;            // registers per tap column
+    static constexpr int NREG = KS * HB;               // registers that carry taps
+    static constexpr int MB2 = (NREG + 3) / 4;         // 16-slot MFMA blocks
+};
+
+// Row shift of a DPP row (16 lanes): lane i of the result holds lane i + n of
+// v (row_shl) or lane i - n (row_shr); lanes whose source is outside the row
+// read 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_zero(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float row_shl(float v, int n)
+{
+    switch (n) {
+    case 1: return dpp_zero<0x101>(v);
+    case 2: return dpp_zero<0x102>(v);
+    case 3: return dpp_zero<0x103>(v);
+    case 4: return dpp_zero<0x104>(v);
+    case 5: return dpp_zero<0x105>(v);
+    case 6: return dpp_zero<0x106>(v);
+    case 7: return dpp_zero<0x107>(v);
+    case 8: return dpp_zero<0x108>(v);
+    case 9: return dpp_zero<0x109>(v);
+    case 10: return dpp_zero<0x10A>(v);
+    case 11: return dpp_zero<0x10B>(v);
+    case 12: return dpp_zero<0x10C>(v);
+    case 13: return dpp_zero<0x10D>(v);
+    case 14: return dpp_zero<0x10E>(v);
+    case 15: return dpp_zero<0x10F>(v);
+    default: return v;
+    }
+}
+
+__device__ __forceinline__ float row_shr(float v, int n)
+{
+    switch (n) {
+    case 1: return dpp_zero<0x111>(v);
+    case 2: return dpp_zero<0x112>(v);
+    case 3: return dpp_zero<0x113>(v);
+    case 4: return dpp_zero<0x114>(v);
+    case 5: return dpp_zero<0x115>(v);
+    case 6: return dpp_zero<0x116>(v);
+    case 7: return dpp_zero<0x117>(v);
+    case 8: return dpp_zero<0x118>(v);
+    case 9: return dpp_zero<0x119>(v);
+    case 10: return dpp_zero<0x11A>(v);
+    case 11: return dpp_zero<0x11B>(v);
+    case 12: return dpp_zero<0x11C>(v);
+    case 13: return dpp_zero<0x11D>(v);
+    case 14: return dpp_zero<0x11E>(v);
+    case 15: return dpp_zero<0x11F>(v);
+    default: return v;
+    }
+}
 
 }  // namespace tnrd

@@ -27,6 +27,7 @@ struct StageArgs {
     int prec;             // tnrd_prec
     int tile_h, tile_w;   // 0 = automatic
     int waves;            // fused: waves per workgroup (4 or 8; 0 = automatic)
+    int poly;             // fused forward: the polynomial influence form may be used
 };
 
 // Batched forward (device descriptors, filled on the host).
@@ -52,6 +53,7 @@ struct BatchArgs {
     const BatchModel *models;
     const BatchItem *items;  // one stage's items, image-major
     int items_per_stage, T, Th, Tw, Nk, Nrbf;
+    int poly;  // the polynomial influence form may be used
     FusedRbf rb;
 };
 
@@ -68,5 +70,6 @@ bool fused_supported(int ks, int Nk, int nrbf, int window, int prec);
 bool fused_config_ok(int ks, int Nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves,
                      int mode);
 size_t fused_scratch_floats(int N, int H, int W, int Nk, int prec);
+bool poly_form_ok(const RbfGrid &grid, int automatic_window);
 
 }  // namespace tnrd
