@@ -18,8 +18,9 @@ LIB = os.path.join(PKG, "libtnrd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["tnrd_api.cpp", "tnrd_split.hip", "tnrd_fused.hip", "tnrd_backward.hip",
-           "tnrd_batched.hip"]
+SOURCES = ["tnrd_fused_fwd.hip", "tnrd_fused_mixed.hip", "tnrd_fused_bwd.hip",
+           "tnrd_fused_batched.hip", "tnrd_backward.hip", "tnrd_fused.hip", "tnrd_api.cpp",
+           "tnrd_split.hip", "tnrd_batched.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-x", "hip",

@@ -1,0 +1,838 @@
+// Device code of the fused stage kernel and its templated launchers; the
+// translation units tnrd_fused_{fwd,mixed,bwd,batched}.hip instantiate them.
+//
+// Fused stage: one kernel per stage computes, for a tile of output pixels,
+//
+//   z_i = K_i u        filter bank as an implicit GEMM on MFMA (v_mfma_f32_16x16x4_f32)
+//   v_i = phi_i(z_i)   influence on the vector ALUs: in the forward, a piecewise
+//                      degree-7 polynomial per unit interval of the RBF grid whose
+//                      coefficients are built in LDS from the weights; in the
+//                      input-gradient mode (which also needs phi'), the windowed
+//                      Gaussian sum evaluated with Horner's rule
+//   Y   = K^T-GEMM     [tap slots x pixels] = [tap slots x filters] . [filters x pixels] on MFMA
+//   x   = col2im(Y)    x-direction shift-add of the tap columns with DPP row shifts,
+//                      y-direction sum of the tap rows through LDS (plus the
+//                      reflected-border fold)
+//   u'  = prox(u - x)
+//
+// without writing the Nk response maps anywhere but registers.
+//
+// Tile geometry (R = (KS-1)/2): the workgroup owns an output tile of Th x Tw
+// pixels.  K^T needs v on the tile plus an R ring ("E region", Eh x Ew), and
+// z on E needs u on the tile plus a 2R ring (the u tile staged in LDS).  Each
+// wave takes whole E rows; a row is cut into NB blocks of 16 pixels, the N
+// dimension of every MFMA.  Pixels of a block that fall outside the image (or
+// beyond Ew) carry v = 0.
+//
+// GEMM layouts for v_mfma_f32_16x16x4_f32 (lane l, g = l / 16, j = l % 16):
+//   A operand  A[j][g]   (row j, k = g)
+//   B operand  B[g][j]
+//   D          D[4g + r][j] in accumulator register r
+// GEMM1: rows = filters (16 per m-block), k = taps (4 per k-step), cols = pixels.
+//   D gives lane l the responses of pixel j for filters 16 mb + 4 g + r.
+// GEMM2: rows = tap slots, k = filters, cols = pixels.  Its B operand for k-step
+//   (mb, r) is exactly GEMM1's D register r of m-block mb if k-row g of that
+//   step is taken to be filter 16 mb + 4 g + r, so the responses never move.
+//   Accumulator register R' = 4 mb2 + r holds tap column b = R' / HB and, in
+//   lane group g, tap row a = 4 (R' % HB) + g (HB = ceil(KS / 4)): every lane
+//   group of a register holds the same b for 16 consecutive pixels.
+//
+// col2im: Y of tap (a, b) at source pixel (e, c) belongs to output (e - a, c - b)
+// in tile coordinates.  Shifting by b along the 16 pixels of a block is one DPP
+// row shift per register (row_shl b inside the block, row_shr 16 - b for the
+// part that lands in the block to the left), so the sum over b stays in
+// registers and each E row leaves P[e][a][qx + 2R] = sum_b Y_(a,b)[qx + b] in a
+// ring of LDS rows, every entry written once by the wave that owns row e (no
+// atomics, deterministic).  Output row y is X(y, x) = sum_a P[y + a][a][x + 2R].
+//
+// The border fold (K^T is the exact adjoint of "reflect, then convolve"): an
+// output pixel within R of the image border also receives X at its mirror
+// position in the padded ring, which the tile's P already holds.
+#pragma once
+
+#include "tnrd_device.hpp"
+#include "tnrd_fused_common.hpp"
+#include "tnrd_internal.hpp"
+
+namespace tnrd {
+
+struct FusedLds {
+    int ldw;      // u tile row pitch
+    int u_off, u_size;
+    int e_off;    // input-gradient mode: e tile, same shape as the u tile
+    int t_off, t_pitch, t_size;  // influence table (Gaussian form: weight rows of t_pitch floats;
+                                 // polynomial form: [filter][2][intervals][4] coefficients)
+    int ni;                      // polynomial form: intervals per filter
+    int w_pitch;                 // polynomial form: padded weight row staged in the P area
+    int p_off, pw, ring, p_size; // row partials: ring of `ring` E rows x KS tap rows x pw
+    int red_off;                 // 8 floats for workgroup reductions
+    int dummy_off;               // 64 floats: target of the stores of masked-off lanes
+    int total;
+};
+
+__host__ __device__ inline int fused_ring(int ks, int nw) { return 2 * nw + 2 * (ks / 2); }
+
+__host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, int tw, int nrbf,
+                                              int nw, int mode, int rbfm)
+{
+    const int R = ks / 2;
+    FusedLds l;
+    const int luh = th + 4 * R;
+    l.ldw = tw + 4 * R + 1;
+    l.u_off = 0;
+    l.u_size = (luh * l.ldw + 3) & ~3;
+    l.e_off = l.u_off + l.u_size;
+    l.t_off = l.e_off + (mode == MODE_BWD_INPUT ? l.u_size : 0);
+    l.t_pitch = nrbf + 4 * RBF_WIN + 1;
+    l.ni = poly_intervals(nrbf);
+    l.w_pitch = nrbf + 2 * POLY_PAD;
+    l.t_size = rbfm == RBF_POLY ? 16 * nmb * POLY_NC * l.ni : ((16 * nmb * l.t_pitch + 3) & ~3);
+    l.p_off = l.t_off + l.t_size;
+    l.pw = 16 * nb + 2 * R;
+    l.ring = fused_ring(ks, nw);
+    l.p_size = l.ring * ks * l.pw;
+    // the prologue stages the filters (Gaussian form) or the padded weights
+    // (polynomial form) in the P area
+    const int stage = rbfm == RBF_POLY ? 16 * nmb * l.w_pitch : 16 * nmb * ks * ks;
+    if (l.p_size < stage) l.p_size = stage;
+    l.red_off = l.p_off + l.p_size;
+    l.dummy_off = l.red_off + 8;
+    l.total = l.dummy_off + 64;
+    return l;
+}
+
+// One output tile of one stage.  The pointers in `io` are those of the tile's
+// image ([H][W] planes); (ty0, tx0) is the tile's origin.  The caller's
+// workgroup runs it with 64 * NW threads and the dynamic LDS of fused_lds().
+template <int KS, int NMB, int NB, int NW, int MODE, int PREC, int RBFM>
+__device__ __forceinline__ void fused_tile(
+    const FusedIO &io, int H, int W, int Th, int Tw, int ty0, int tx0,
+    const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
+    const FusedRbf &rb, const float *__restrict__ lam_t, float *lds)
+{
+    constexpr bool BWD = MODE == MODE_BWD_INPUT;
+    constexpr bool POLY = RBFM == RBF_POLY;
+    static_assert(!(BWD && POLY), "the input-gradient mode needs phi' and uses the Gaussian form");
+    const float *__restrict__ u_prev = io.u_prev;
+    const float *__restrict__ f = io.f;
+    using G = Geo<KS>;
+    using G2 = Geo2<KS>;
+    constexpr int R = G::R, KK = G::KK, KS1 = G::KS1;
+    constexpr int HB = G2::HB, NREG = G2::NREG, MB2 = G2::MB2;
+    constexpr int KS2 = 4 * NMB;  // GEMM2 k-steps (4 filters each)
+    constexpr int THREADS = 64 * NW;
+    constexpr int RING = 2 * NW + 2 * R;
+    // output values a thread produces per round, at most: (NW + R) rows of a tile at most
+    // 16 NB - 2R wide
+    constexpr int PF = ((NW + R) * (16 * NB - 2 * R) + THREADS - 1) / THREADS;
+
+    const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW, MODE, RBFM);
+    float *su = lds + L.u_off;
+    float *se = lds + L.e_off;
+    float *stab = lds + L.t_off;
+    float *sp = lds + L.p_off;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+
+    const int Eh = Th + 2 * R, Ew = Tw + 2 * R;
+    const int luh = Th + 4 * R, luw = Tw + 4 * R;
+
+    // ---- prologue: every global load of a thread is issued before the first
+    // use, so the workgroup pays one memory latency, not one per element.
+    // (1) the stage's filters: into the table area (polynomial form, whose
+    // table is built only after the filters sit in registers) or the P area
+    float *sf = POLY ? stab : sp;
+    {
+        const int nf = Nk * KK;
+        for (int base = 0; base < nf; base += 8 * THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = filt[min(base + k * THREADS + tid, nf - 1)];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (base + k * THREADS + tid < nf) sf[base + k * THREADS + tid] = v[k];
+        }
+    }
+    // (2) the u tile (rows ty0-2R .. ty0+Th+2R-1), reflected at the border
+    {
+        const int n = luh * luw;
+        for (int base = 0; base < n; base += 8 * THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int i = min(base + k * THREADS + tid, n - 1);
+                int ly = i / luw, lx = i - ly * luw;
+                int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
+                v[k] = u_prev[(size_t)yy * W + xx];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int i = base + k * THREADS + tid;
+                if (i < n) {
+                    int ly = i / luw, lx = i - ly * luw;
+                    su[ly * L.ldw + lx] = v[k];
+                }
+            }
+        }
+    }
+    // (2b) input-gradient mode: e = y * g_t over the same region, where
+    // y = du_t/d(ut_t) = u_t^2 / ((1+2l) u_t^2 + 2 l f^2) is the prox derivative
+    // written with the prox output (equal to the closed form of eq. derv2).
+    float emax = 0.f;  // largest |e| of the tile (input-gradient mode)
+    if (BWD) {
+        const float lam0 = lam_t[0];
+        const float c1 = 1.f + 2.f * lam0, c2 = 2.f * lam0;
+        const float *ucn = io.u_cur;
+        const float *gcn = io.g_cur;
+        const float *fcn = f;
+        const int n = luh * luw;
+        for (int base = 0; base < n; base += 4 * THREADS) {
+            float uu[4], ff[4], gg[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int i = min(base + k * THREADS + tid, n - 1);
+                int ly = i / luw, lx = i - ly * luw;
+                int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
+                size_t q = (size_t)yy * W + xx;
+                uu[k] = ucn[q];
+                ff[k] = fcn[q];
+                gg[k] = gcn[q];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int i = base + k * THREADS + tid;
+                if (i < n) {
+                    int ly = i / luw, lx = i - ly * luw;
+                    float u2 = uu[k] * uu[k];
+                    float y = u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
+                    float ev = y * gg[k];
+                    se[ly * L.ldw + lx] = ev;
+                    emax = fmaxf(emax, fabsf(ev));
+                }
+            }
+        }
+    }
+    // (3) RBF weights.  Gaussian form: the table itself, rows zero padded by 2W
+    // on both sides.  Polynomial form: rows zero padded by POLY_PAD, staged in
+    // the P area for the coefficient build below.
+    {
+        float *dst = POLY ? sp : stab;
+        const int pitch = POLY ? L.w_pitch : L.t_pitch;
+        const int pad = POLY ? POLY_PAD : 2 * RBF_WIN;
+        const int n = 16 * NMB * pitch;
+        const int nw = Nk * Nrbf;
+        for (int base = 0; base < n; base += 8 * THREADS) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int i = base + k * THREADS + tid;
+                int fi = i / pitch, jj = i - fi * pitch - pad;
+                int src = min(max(fi * Nrbf + jj, 0), nw - 1);
+                float w = rbfw[src];
+                v[k] = (fi < Nk && jj >= 0 && jj < Nrbf) ? w : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (base + k * THREADS + tid < n) dst[base + k * THREADS + tid] = v[k];
+        }
+    }
+    __syncthreads();
+
+    // Mixed-precision input gradient: e, a = K e and phi' a go through BF16/FP16
+    // operands with a power-of-two tile scale that puts max|e| at 2^10 (FP16's
+    // normal range starts at 2^-14 and ends below 2^16; |K e| <= 7 max|e| for
+    // unit-norm 7x7 filters), undone in FP32 when g_{t-1} is formed.
+    float escale = 1.f, einv = 1.f;
+    if (BWD && PREC != PREC_F32) {
+        float wmax = emax;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, o));
+        float *red = lds + L.red_off;
+        if (lane == 0) red[wave] = wmax;
+        __syncthreads();
+        float m = 0.f;
+        for (int w = 0; w < NW; ++w) m = fmaxf(m, red[w]);
+        if (m > 0.f && isfinite(m)) {
+            int ex = ilogbf(m);
+            escale = ldexpf(1.f, 10 - ex);
+            einv = ldexpf(1.f, ex - 10);
+        }
+    }
+
+    // ---- filter operands in registers (from the staged copy)
+    float a1[NMB][KS1];
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+        for (int s = 0; s < KS1; ++s) {
+            int fi = 16 * mb + j, t = 4 * s + g;
+            a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
+        }
+    // GEMM2 A operand: lane (g, j) supplies slot row j of block mb2, i.e.
+    // register R' = 4 mb2 + (j & 3) in lane group j >> 2, and k-row g of k-step s,
+    // i.e. filter 16 (s >> 2) + 4 g + (s & 3).
+    int slot_a[MB2], slot_b[MB2];
+#pragma unroll
+    for (int mb2 = 0; mb2 < MB2; ++mb2) {
+        const int Rr = 4 * mb2 + (j & 3);
+        slot_b[mb2] = Rr < NREG ? Rr / HB : KS;
+        slot_a[mb2] = 4 * (Rr % HB) + (j >> 2);
+    }
+    float a2[MB2][KS2];
+#pragma unroll
+    for (int mb2 = 0; mb2 < MB2; ++mb2)
+#pragma unroll
+        for (int s = 0; s < KS2; ++s) {
+            int fi = 16 * (s >> 2) + 4 * g + (s & 3);
+            const int ta = slot_a[mb2], tb = slot_b[mb2];
+            a2[mb2][s] = (fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f;
+        }
+
+    // mixed precision: 16-wide k-steps, operands converted once to BF16/FP16
+    using MX = Mix<PREC>;
+    typedef typename MX::V MV;
+    constexpr bool MIXED = PREC != PREC_F32;
+    constexpr int KSH = (KK + 15) / 16;  // GEMM1 k-steps of 16 taps
+    MV a1m[NMB][MIXED ? KSH : 1];
+    MV a2m[MB2][MIXED ? NMB : 1];
+    int offm[MIXED ? KSH : 1][4];
+    if (MIXED) {
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int s = 0; s < KSH; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int fi = 16 * mb + j, t = 16 * s + 4 * g + i;
+                    a1m[mb][s][i] = MX::cvt((fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f);
+                }
+#pragma unroll
+        for (int mb2 = 0; mb2 < MB2; ++mb2)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int fi = 16 * mb + 4 * g + i;
+                    const int ta = slot_a[mb2], tb = slot_b[mb2];
+                    a2m[mb2][mb][i] =
+                        MX::cvt((fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f);
+                }
+    }
+    __syncthreads();  // the staged filters are consumed
+
+    if (POLY) {
+        // (4) coefficient table of the polynomial form from the staged weights:
+        // c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} + (-1)^k w_{j0-m})
+        const int ni = L.ni;
+        for (int idx = tid; idx < 16 * NMB * ni; idx += THREADS) {
+            const int fi = idx / ni, q = idx - fi * ni;
+            float c[POLY_NC];
+#pragma unroll
+            for (int k = 0; k < POLY_NC; ++k) c[k] = 0.f;
+            if (fi < Nk && q >= 1 && q <= ni - 2) {
+                const float *wc = sp + fi * L.w_pitch + (q - 1 - RBF_WIN) + POLY_PAD;  // w_j0
+                const float w0 = wc[0];
+#pragma unroll
+                for (int k = 0; k < POLY_NC; k += 2) c[k] = rb.pm[k][0] * w0;
+#pragma unroll
+                for (int m = 1; m <= POLY_MW; ++m) {
+                    const float sum = wc[m] + wc[-m], dif = wc[m] - wc[-m];
+#pragma unroll
+                    for (int k = 0; k < POLY_NC; ++k) c[k] = fmaf(rb.pm[k][m], (k & 1) ? dif : sum, c[k]);
+                }
+            }
+            float *dst = stab + fi * (POLY_NC * ni) + 4 * q;
+            *reinterpret_cast<floatx4 *>(dst) = floatx4{c[0], c[1], c[2], c[3]};
+            *reinterpret_cast<floatx4 *>(dst + 4 * ni) = floatx4{c[4], c[5], c[6], c[7]};
+        }
+        __syncthreads();  // the table is complete; the staged weights are dead
+    }
+
+    // GEMM1 B-operand offsets: tap t = 4 s + g -> (a, b) = (t / KS, t % KS)
+    int off1[KS1];
+#pragma unroll
+    for (int s = 0; s < KS1; ++s) {
+        int t = 4 * s + g;
+        off1[s] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+    }
+    if (MIXED) {
+#pragma unroll
+        for (int s = 0; s < KSH; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int t = 16 * s + 4 * g + i;
+                offm[s][i] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+            }
+    }
+
+    const float lam = lam_t[0];
+    // per-lane part of the polynomial table address: filter 16 mb + 4 g + r
+    const int tab_g = 4 * g * POLY_NC * L.ni;
+
+    // GEMM1 of block (E row e, 16-pixel block cb): z = K u (and a = K e in
+    // input-gradient mode).  The B operands are read first (gemm1_load), the
+    // MFMAs run in k-step ranges (gemm1_steps) spread over the next block's work.
+    constexpr int K1 = MIXED ? KSH : KS1;  // GEMM1 k-steps
+    float bu[MIXED ? 1 : KS1], be[MIXED || !BWD ? 1 : KS1];
+    MV bum[MIXED ? KSH : 1], bem[MIXED && BWD ? KSH : 1];
+    auto gemm1_load = [&](int e, int cb) {
+        const int c = 16 * cb + j;
+        const int cc = c < Ew ? c : Ew - 1;
+        const float *ub = su + (e + 2 * R) * L.ldw + cc + 2 * R;
+        const float *eb = se + (e + 2 * R) * L.ldw + cc + 2 * R;
+        if (MIXED) {
+#pragma unroll
+            for (int s = 0; s < KSH; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    bum[s][i] = MX::cvt(ub[-offm[s][i]]);
+                    if (BWD) bem[s][i] = MX::cvt(escale * eb[-offm[s][i]]);
+                }
+        } else {
+#pragma unroll
+            for (int s = 0; s < KS1; ++s) {
+                bu[s] = ub[-off1[s]];
+                if (BWD) be[s] = eb[-off1[s]];
+            }
+        }
+    };
+    auto gemm1_steps = [&](int s0, int s1, floatx4 *acc1, floatx4 *acca) {
+#pragma unroll
+        for (int s = s0; s < s1; ++s)
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) {
+                if (MIXED) {
+                    acc1[mb] = MX::mfma(a1m[mb][s], bum[s], acc1[mb]);
+                    if (BWD) acca[mb] = MX::mfma(a1m[mb][s], bem[s], acca[mb]);
+                } else {
+                    acc1[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], bu[s], acc1[mb], 0, 0, 0);
+                    if (BWD)
+                        acca[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mb][s], be[s], acca[mb], 0, 0, 0);
+                }
+            }
+    };
+    auto gemm1 = [&](int e, int cb, floatx4 *acc1, floatx4 *acca) {
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) {
+            acc1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acca[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        gemm1_load(e, cb);
+        gemm1_steps(0, K1, acc1, acca);
+    };
+
+    // Polynomial form: table reads of one filter group (the four filters of an
+    // accumulator register quad) into one of two buffers.
+    float dq[2][4];
+    floatx4 lo[2][4], hi[2][4];
+    auto fetch = [&](const floatx4 *acc1, int mb, int slot) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float s = fmaf(acc1[mb][r], rb.inv_step, -rb.mu0_over_step);
+            const float jr = rintf(s);
+            dq[slot][r] = s - jr;
+            const int q = (int)fminf(fmaxf(jr + (float)(RBF_WIN + 1), 0.f), (float)(L.ni - 1));
+            const float *cp = stab + (16 * mb + r) * (POLY_NC * L.ni) + tab_g + 4 * q;
+            lo[slot][r] = *reinterpret_cast<const floatx4 *>(cp);
+            hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * L.ni);
+        }
+    };
+    // influence of filter group mb, in place: v = phi(z) (times phi' and a in
+    // input-gradient mode), lane-local (pixel j, filters 16 mb + 4 g + r)
+    auto influence = [&](floatx4 *acc1, const floatx4 *acca, int mb, bool valid) {
+        if (POLY) {
+            const int cur = mb & 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float d = dq[cur][r];
+                const floatx4 l = lo[cur][r], h = hi[cur][r];
+                float p = fmaf(h[3], d, h[2]);
+                p = fmaf(p, d, h[1]);
+                p = fmaf(p, d, h[0]);
+                p = fmaf(p, d, l[3]);
+                p = fmaf(p, d, l[2]);
+                p = fmaf(p, d, l[1]);
+                p = fmaf(p, d, l[0]);
+                acc1[mb][r] = valid ? p : 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float s = fmaf(acc1[mb][r], rb.inv_step, -rb.mu0_over_step);
+                const float jr = fminf(fmaxf(rintf(s), -(float)RBF_WIN), rb.jmax);
+                const float d = s - jr;
+                const float *w = stab + (16 * mb + 4 * g + r) * L.t_pitch + (int)jr + RBF_WIN;
+                const float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
+                const float E = __builtin_amdgcn_exp2f(-rb.rho_log2e * d * fmaf(0.5f, d, (float)RBF_WIN));
+                float acc = w[2 * RBF_WIN] * rb.c[2 * RBF_WIN];
+                float accd = 0.f;  // derivative of the Horner polynomial
+#pragma unroll
+                for (int n = 2 * RBF_WIN - 1; n >= 0; --n) {
+                    if (BWD) accd = fmaf(accd, q, acc);
+                    acc = fmaf(acc, q, w[n] * rb.c[n]);
+                }
+                float v;
+                if (BWD) {
+                    // phi'(z) = (rho/step) E (q P'(q) - (d + W) P(q)), times a
+                    const float dphi = rb.rho_over_step * E * fmaf(q, accd, -(d + (float)RBF_WIN) * acc);
+                    v = dphi * acca[mb][r];
+                } else {
+                    v = E * acc;
+                }
+                acc1[mb][r] = (valid && fabsf(d) <= 0.5f) ? v : 0.f;
+            }
+        }
+    };
+    // GEMM2 k-steps of filter group mb: Y += K^T-slots . v
+    auto gemm2_group = [&](const floatx4 *acc1, int mb, floatx4 *acc2) {
+        if (MIXED) {
+            MV vb;  // filters 16 mb + 4 g + i of pixel j: GEMM1's register quad
+#pragma unroll
+            for (int i = 0; i < 4; ++i) vb[i] = MX::cvt(acc1[mb][i]);
+#pragma unroll
+            for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = MX::mfma(a2m[mb2][mb], vb, acc2[mb2]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int mb2 = 0; mb2 < MB2; ++mb2)
+                    acc2[mb2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[mb2][4 * mb + r], acc1[mb][r],
+                                                                     acc2[mb2], 0, 0, 0);
+        }
+    };
+
+    // Block (e, cb) from its responses c1 (and a = K e in ca), interleaved with
+    // GEMM1 of the next block (en, cbn) into n1/na: influence, K^T GEMM and
+    // the x-direction col2im.  xa[h] enters holding block cb-1's partial X (tap
+    // rows a = 4h + g) and leaves holding block cb's; block cb-1 is complete
+    // then and goes to the P ring:
+    //   P[e mod RING][a][qx + 2R] = sum_b Y_(a,b)[qx + b]   (qx relative to the E row)
+    // The scheduling fences split the work into NMB + 1 segments; in each, the
+    // table reads of the next filter group and a third of the next GEMM1 are
+    // in flight while the current group's influence and GEMM2 run.
+    auto process = [&](int e, int cb, floatx4 *c1, const floatx4 *ca, float *xa, int en, int cbn,
+                       floatx4 *n1, floatx4 *na) {
+        const int c = 16 * cb + j;
+        const int xi = tx0 - R + c;
+        const bool valid = (c < Ew) && (xi >= 0) && (xi < W);
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) {
+            n1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            na[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        floatx4 acc2[MB2];
+#pragma unroll
+        for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = floatx4{0.f, 0.f, 0.f, 0.f};
+        gemm1_load(en, cbn);
+        if (POLY) fetch(c1, 0, 0);
+        gemm1_steps(0, K1 / NMB, n1, na);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int m = 1; m <= NMB; ++m) {
+            if (POLY && m < NMB) fetch(c1, m, m & 1);
+            influence(c1, ca, m - 1, valid);
+            gemm2_group(c1, m - 1, acc2);
+            if (m < NMB) gemm1_steps(m * K1 / NMB, (m + 1) * K1 / NMB, n1, na);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+        // x-direction col2im with row shifts: tap column b moves pixel c to
+        // output column c - b, inside this block (row_shl b) or into block cb-1
+        // (row_shr 16 - b).
+        float xb[HB];
+#pragma unroll
+        for (int h = 0; h < HB; ++h) xb[h] = 0.f;
+#pragma unroll
+        for (int b = 0; b < KS; ++b)
+#pragma unroll
+            for (int h = 0; h < HB; ++h) {
+                const int Rr = b * HB + h;
+                const float y = acc2[Rr >> 2][Rr & 3];
+                if (b == 0) {
+                    xb[h] += y;
+                } else {
+                    xb[h] += row_shl(y, b);
+                    xa[h] += row_shr(y, 16 - b);
+                }
+            }
+        // branch-free stores: masked-off lanes write their own dummy word
+        const int prow = L.p_off + (e % RING) * KS * L.pw;
+        const int dummy = L.dummy_off + lane;
+#pragma unroll
+        for (int h = 0; h < HB; ++h) {
+            const int a = 4 * h + g;
+            // block cb-1: output columns 16 (cb-1) + j; block -1 only reaches j >= 16 - 2R
+            const bool ok_a = a < KS && (cb > 0 || j >= 16 - 2 * R);
+            lds[ok_a ? prow + a * L.pw + 16 * (cb - 1) + j + 2 * R : dummy] = xa[h];
+            if (cb == NB - 1) lds[a < KS ? prow + a * L.pw + 16 * cb + j + 2 * R : dummy] = xb[h];
+            xa[h] = xb[h];
+        }
+    };
+
+    // ---- gather X over the tap rows, fold the border ring, prox, store.
+    // Output row y needs the partials of E rows y .. y + 2R (the rows of its
+    // mirror position at a border lie in the same range).
+    const float *fn = f;
+    float *uo = io.out;
+    const int y_lim = min(Th, H - ty0);
+    auto out_index = [&](int i, int y0, int &y, int &x) {
+        y = y0 + i / Tw;
+        x = i - (i / Tw) * Tw;
+    };
+    auto produce = [&](int y0, int y1, const float *fpre) {
+        const int n = (y1 - y0) * Tw;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int i = tid + p * THREADS;
+            if (i >= n) break;
+            int y, x;
+            out_index(i, y0, y, x);
+            const int yi = ty0 + y, xi = tx0 + x;
+            if (xi >= W) continue;
+            int qy[2] = {y, 0}, qx[2] = {x, 0};
+            int nqy = 1, nqx = 1;
+            if (yi < R) qy[nqy++] = -yi - 1 - ty0;
+            else if (yi >= H - R) qy[nqy++] = 2 * H - 1 - yi - ty0;
+            if (xi < R) qx[nqx++] = -xi - 1 - tx0;
+            else if (xi >= W - R) qx[nqx++] = 2 * W - 1 - xi - tx0;
+            float xs = 0.f;
+            for (int iy = 0; iy < nqy; ++iy)
+                for (int ix = 0; ix < nqx; ++ix) {
+                    const int col = qx[ix] + 2 * R;
+#pragma unroll
+                    for (int a = 0; a < KS; ++a) {
+                        const int e = qy[iy] + a;
+                        const int ye = ty0 - R + e;
+                        if (e >= 0 && e < Eh && ye >= 0 && ye < H)
+                            xs += sp[((e % RING) * KS + a) * L.pw + col];
+                    }
+                }
+            const size_t pix = (size_t)yi * W + xi;
+            if (BWD) {
+                // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1)
+                uo[pix] = se[(y + 2 * R) * L.ldw + x + 2 * R] - xs * einv;
+            } else {
+                const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
+                uo[pix] = prox(uv - xs, fpre[p], lam);
+            }
+        }
+    };
+
+    // ---- main loop: rounds of NW E rows, one per wave.  After round k the
+    // partials of every E row below NW (k+1) are in the ring; the output rows
+    // they complete are produced before the next round's rows are stored.  The
+    // ring holds 2 NW + 2R rows, so the rows one round writes never share a
+    // slot with the rows the previous round's outputs still read.  GEMM1 of
+    // the wave's next block is issued before the influence of the current one.
+    const int e_lo = max(0, R - ty0), e_hi = min(Eh, H - ty0 + R);
+    const int rounds = (e_hi + NW - 1) / NW;
+    int y_done = 0;
+    bool have = false;
+    floatx4 c1[NMB], ca[NMB];
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb) {
+        c1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        ca[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int k = 0; k < rounds; ++k) {
+        int y_end = e_hi <= NW * (k + 1) ? Th : max(0, NW * (k + 1) - 2 * R);
+        y_end = min(y_end, y_lim);
+        const int y0 = min(y_done, y_end);
+        // f of this round's outputs, loaded ahead of the round's compute
+        float fpre[PF];
+        if (!BWD) {
+            const int n = (y_end - y0) * Tw;
+#pragma unroll
+            for (int p = 0; p < PF; ++p) {
+                const int i = tid + p * THREADS;
+                fpre[p] = 0.f;
+                if (i < n) {
+                    int y, x;
+                    out_index(i, y0, y, x);
+                    if (tx0 + x < W) fpre[p] = fn[(size_t)(ty0 + y) * W + tx0 + x];
+                }
+            }
+        }
+        const int e = NW * k + wave;
+        if (e >= e_lo && e < e_hi) {
+            if (!have) gemm1(e, 0, c1, ca);
+            float xa[HB];
+#pragma unroll
+            for (int h = 0; h < HB; ++h) xa[h] = 0.f;
+            // one basic block per row: the GEMM1 after the row's last block is
+            // that of the wave's next row (or a repeat of a row of this tile
+            // when there is none, whose result is dropped)
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                floatx4 n1[NMB], na[NMB];
+                const int en = cb + 1 < NB ? e : min(e + NW, e_hi - 1);
+                process(e, cb, c1, ca, xa, en, cb + 1 < NB ? cb + 1 : 0, n1, na);
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb) {
+                    c1[mb] = n1[mb];
+                    ca[mb] = na[mb];
+                }
+            }
+            have = true;
+        } else {
+            have = false;
+        }
+        __syncthreads();
+        produce(y0, y_end, fpre);
+        y_done = max(y_done, y_end);
+    }
+    __syncthreads();  // LDS is free for the workgroup's next tile
+}
+
+template <int KS, int NMB, int NB, int NW, int MODE, int PREC, int RBFM>
+__global__ void __launch_bounds__(64 * NW) k_fused_stage(
+    FusedIO io, int H, int W, int Th, int Tw, int tiles_x, int tiles_per_img,
+    const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf,
+    FusedRbf rb, const float *__restrict__ lam_t)
+{
+    extern __shared__ float lds[];
+    const int img = blockIdx.x / tiles_per_img;
+    const int trem = blockIdx.x - img * tiles_per_img;
+    const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
+    const size_t plane = (size_t)H * W;
+    FusedIO ii;
+    ii.u_prev = io.u_prev + img * plane;
+    ii.f = io.f + img * plane;
+    ii.out = io.out + img * plane;
+    ii.u_cur = io.u_cur ? io.u_cur + img * plane : nullptr;
+    ii.g_cur = io.g_cur ? io.g_cur + img * plane : nullptr;
+    fused_tile<KS, NMB, NB, NW, MODE, PREC, RBFM>(ii, H, W, Th, Tw, ty * Th, tx * Tw, filt, Nk, rbfw,
+                                                  Nrbf, rb, lam_t, lds);
+}
+
+// ------------------------------------------------------------------ batched
+// One launch per stage covers the tiles of every image of an uneven batch:
+// workgroup b takes the b-th (image, tile) item of the stage and runs the
+// fused stage on it with that image's model (chosen by its look number).
+// Stages are ordered by the kernel boundaries, so no workgroup ever waits on
+// another.  Ping-pong: stage t writes u_out if T-1-t is even, else the
+// image's scratch plane, and reads the other (stage 0 reads f).
+template <int KS, int NMB, int NB, int NW, int RBFM>
+__global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
+{
+    extern __shared__ float lds[];
+    constexpr int KK = KS * KS;
+    const BatchItem it = a.items[blockIdx.x];
+    const BatchImage im = a.imgs[it.image];
+    const int ty = it.tile / im.tiles_x, tx = it.tile - ty * im.tiles_x;
+    const bool to_out = ((a.T - 1 - t) & 1) == 0;
+    FusedIO io;
+    io.f = im.f;
+    io.u_prev = t == 0 ? im.f : (to_out ? im.u_tmp : im.u_out);
+    io.out = to_out ? im.u_out : im.u_tmp;
+    io.u_cur = nullptr;
+    io.g_cur = nullptr;
+    const BatchModel md = a.models[im.model];
+    fused_tile<KS, NMB, NB, NW, MODE_FWD, PREC_F32, RBFM>(
+        io, im.H, im.W, a.Th, a.Tw, ty * a.Th, tx * a.Tw, md.filt + (size_t)t * a.Nk * KK, a.Nk,
+        md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb, md.lam + t, lds);
+}
+
+template <int KS, int NMB, int NB, int NW, int MODE, int PREC, int RBFM>
+inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t stream)
+{
+    FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf, NW, MODE, RBFM);
+    size_t lds_bytes = (size_t)L.total * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        // raise the dynamic LDS limit to the CU's 160 KB; a failure here shows
+        // up as a launch error below, so the status is cleared
+        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB, NW, MODE, PREC, RBFM>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    FusedRbf rb = make_fused_rbf(s.grid);
+    FusedIO io;
+    io.u_prev = s.u_prev;
+    io.f = s.f;
+    io.out = s.u_next;
+    io.u_cur = s.u_cur;
+    io.g_cur = s.g_cur;
+    const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
+    const int tiles = tiles_x * tiles_y;
+    dim3 grid(tiles * s.N);
+    hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW, MODE, PREC, RBFM>), grid, dim3(64 * NW),
+                       lds_bytes, stream, io, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk, s.rbfw,
+                       s.grid.nrbf, rb, s.lam);
+    return hipGetLastError();
+}
+
+template <int KS, int NMB, int NW, int MODE, int PREC, int RBFM>
+inline hipError_t fused_nb(const StageArgs &s, int th, int tw, int nb, hipStream_t stream)
+{
+    switch (nb) {
+    case 2: return launch_fused<KS, NMB, 2, NW, MODE, PREC, RBFM>(s, th, tw, stream);
+    case 3: return launch_fused<KS, NMB, 3, NW, MODE, PREC, RBFM>(s, th, tw, stream);
+    case 4: return launch_fused<KS, NMB, 4, NW, MODE, PREC, RBFM>(s, th, tw, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int KS, int NMB, int MODE, int PREC, int RBFM>
+inline hipError_t fused_nw(const StageArgs &s, int th, int tw, int nb, int nw, hipStream_t stream)
+{
+    if (nw == 4) return fused_nb<KS, NMB, 4, MODE, PREC, RBFM>(s, th, tw, nb, stream);
+    return fused_nb<KS, NMB, 8, MODE, PREC, RBFM>(s, th, tw, nb, stream);
+}
+
+template <int KS, int NMB, int MODE, int PREC>
+inline hipError_t fused_form(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
+                             hipStream_t stream)
+{
+    if constexpr (MODE == MODE_FWD) {
+        if (rbfm == RBF_POLY) return fused_nw<KS, NMB, MODE_FWD, PREC, RBF_POLY>(s, th, tw, nb, nw, stream);
+    }
+    return fused_nw<KS, NMB, MODE, PREC, RBF_HORNER>(s, th, tw, nb, nw, stream);
+}
+
+template <int KS, int NMB, int NB, int NW, int RBFM>
+inline hipError_t launch_batched_t(const BatchArgs &a, hipStream_t stream)
+{
+    FusedLds L = fused_lds(KS, NMB, NB, a.Th, a.Tw, a.Nrbf, NW, MODE_FWD, RBFM);
+    const size_t lds_bytes = (size_t)L.total * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_batched_stage<KS, NMB, NB, NW, RBFM>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    for (int t = 0; t < a.T; ++t) {
+        hipLaunchKernelGGL((k_batched_stage<KS, NMB, NB, NW, RBFM>), dim3(a.items_per_stage),
+                           dim3(64 * NW), lds_bytes, stream, a, t);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int KS, int NMB, int RBFM>
+inline hipError_t batched_nb(const BatchArgs &a, int nb, int nw, hipStream_t stream)
+{
+    if (nw == 4) {
+        switch (nb) {
+        case 2: return launch_batched_t<KS, NMB, 2, 4, RBFM>(a, stream);
+        case 3: return launch_batched_t<KS, NMB, 3, 4, RBFM>(a, stream);
+        case 4: return launch_batched_t<KS, NMB, 4, 4, RBFM>(a, stream);
+        }
+    } else {
+        switch (nb) {
+        case 2: return launch_batched_t<KS, NMB, 2, 8, RBFM>(a, stream);
+        case 3: return launch_batched_t<KS, NMB, 3, 8, RBFM>(a, stream);
+        case 4: return launch_batched_t<KS, NMB, 4, 8, RBFM>(a, stream);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tnrd

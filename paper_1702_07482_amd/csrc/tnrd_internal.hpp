@@ -72,4 +72,13 @@ bool fused_config_ok(int ks, int Nk, int nrbf, int H, int W, int tile_h, int til
 size_t fused_scratch_floats(int N, int H, int W, int Nk, int prec);
 bool poly_form_ok(const RbfGrid &grid, int automatic_window);
 
+// Per-family launchers of the fused stage kernel (one translation unit each).
+hipError_t fused_launch_fwd_f32(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
+                                hipStream_t stream);
+hipError_t fused_launch_fwd_mixed(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
+                                  hipStream_t stream);
+hipError_t fused_launch_bwd(const StageArgs &s, int th, int tw, int nb, int nw, hipStream_t stream);
+hipError_t batched_launch_impl(const BatchArgs &a, int ks, int nb, int nw, int rbfm,
+                               hipStream_t stream);
+
 }  // namespace tnrd
