@@ -26,7 +26,8 @@
 //
 // k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms with one lane per
 // filter (each lane owns its row, each wave its histogram), so no two lanes
-// ever update the same word and no atomics are needed.
+// ever update the same word and no atomics are needed (LDS float atomics run an
+// order of magnitude slower here than plain read-modify-writes).
 #include <math.h>
 
 #include <vector>
@@ -39,10 +40,12 @@
 
 namespace tnrd {
 
-constexpr int BP_TH = 32;   // k_bwd_params tile height
+constexpr int BP_TH_MIN = 16;  // k_bwd_params tile height range (the workspace is sized
+constexpr int BP_TH_MAX = 64;  // for the smallest, i.e. the most tiles)
 constexpr int BP_NBW = 2;   // 16-pixel blocks per tile row (tile width 32)
 constexpr int BP_NW = 4;    // waves per workgroup
 constexpr int DW_NW = 8;    // k_bwd_dw waves per workgroup
+constexpr int DW_U = 16;    // k_bwd_dw pixels per wave step
 
 struct BwdParamsIO {
     const float *u_prev;  // u_{t-1}
@@ -239,34 +242,33 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
         if (yi >= H) break;
 #pragma unroll 1
         for (int cb = 0; cb < NBW; ++cb) {
-            // transposed GEMM1: rows = pixels j of the block, columns = filters
+            // transposed GEMM1: rows = pixels j of the block, columns = filters;
+            // its B operands (u and e at every tap) are read once per block
             const float *ubase = su + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
             const float *ebase = se + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
-            floatx4 accz[NMB], acca[NMB];
-#pragma unroll
-            for (int nb = 0; nb < NMB; ++nb) {
-                accz[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-                acca[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            }
+            float bu[KS1], be[KS1];
 #pragma unroll
             for (int s = 0; s < KS1; ++s) {
-                float bu = ubase[-off1[s]], be = ebase[-off1[s]];
-#pragma unroll
-                for (int nb = 0; nb < NMB; ++nb) {
-                    accz[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bu, bf[nb][s], accz[nb], 0, 0, 0);
-                    acca[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(be, bf[nb][s], acca[nb], 0, 0, 0);
-                }
+                bu[s] = ubase[-off1[s]];
+                be[s] = ebase[-off1[s]];
             }
-            // influence, export, and the two dK operands (v, h) in place
+            // one filter block at a time keeps 8 response registers live
 #pragma unroll
             for (int nb = 0; nb < NMB; ++nb) {
+                floatx4 accz = floatx4{0.f, 0.f, 0.f, 0.f}, acca = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS1; ++s) {
+                    accz = __builtin_amdgcn_mfma_f32_16x16x4f32(bu[s], bf[nb][s], accz, 0, 0, 0);
+                    acca = __builtin_amdgcn_mfma_f32_16x16x4f32(be[s], bf[nb][s], acca, 0, 0, 0);
+                }
+                // influence, export, and the two dK operands (v, h) in place
                 const float *row = stab + (16 * nb + j) * L.t_pitch;
                 const int fi = 16 * nb + j;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int x = 16 * cb + 4 * g + r, xi = tx0 + x;
                     const bool valid = xi < W;
-                    float z = accz[nb][r], a = acca[nb][r];
+                    float z = accz[r], a = acca[r];
                     float ph, dph;
                     rbf_phi_dphi_horner(z, row, rb, ph, dph);
                     if (valid && fi < Nk) {
@@ -274,30 +276,25 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
                         io.zexp[pix * Nk + fi] = z;
                         io.aexp[pix * Nk + fi] = a;
                     }
-                    accz[nb][r] = valid ? ph : 0.f;
-                    acca[nb][r] = valid ? dph * a : 0.f;
+                    accz[r] = valid ? ph : 0.f;
+                    acca[r] = valid ? dph * a : 0.f;
                 }
-            }
-            // dK^T GEMM: k-step r, k-row g = pixel 4 g + r
+                // dK^T GEMM: k-step r, k-row g = pixel 4 g + r
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int x = 16 * cb + 4 * g + r;
-                const int b2 = (y + 2 * R) * L.ldw + x + 2 * R;
+                for (int r = 0; r < 4; ++r) {
+                    const int x = 16 * cb + 4 * g + r;
+                    const int b2 = (y + 2 * R) * L.ldw + x + 2 * R;
 #pragma unroll
-                for (int mt = 0; mt < MB2; ++mt) {
-                    float ae = tapok[mt] ? se[b2 - offt[mt]] : 0.f;
-                    float au = tapok[mt] ? su[b2 - offt[mt]] : 0.f;
-#pragma unroll
-                    for (int nb = 0; nb < NMB; ++nb) {
-                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, accz[nb][r], dkt[mt][nb], 0, 0, 0);
-                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(au, acca[nb][r], dkt[mt][nb], 0, 0, 0);
+                    for (int mt = 0; mt < MB2; ++mt) {
+                        float ae = tapok[mt] ? se[b2 - offt[mt]] : 0.f;
+                        float au = tapok[mt] ? su[b2 - offt[mt]] : 0.f;
+                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, accz[r], dkt[mt][nb], 0, 0, 0);
+                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(au, acca[r], dkt[mt][nb], 0, 0, 0);
                     }
-                }
-                if (G::VTAP) {
-                    float ev = se[b2 - offv], uvv = su[b2 - offv];
-#pragma unroll
-                    for (int nb = 0; nb < NMB; ++nb)
-                        acc48[nb] = fmaf(accz[nb][r], ev, fmaf(acca[nb][r], uvv, acc48[nb]));
+                    if (G::VTAP) {
+                        float ev = se[b2 - offv], uvv = su[b2 - offv];
+                        acc48[nb] = fmaf(accz[r], ev, fmaf(acca[r], uvv, acc48[nb]));
+                    }
                 }
             }
         }
@@ -367,25 +364,50 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
     const long long p0 = (long long)blockIdx.x * per_wg;
     const long long p1 = min(P, p0 + per_wg);
     if (lane < Nk) {
-        for (long long p = p0 + wave; p < p1; p += NW) {
-            const float z = zexp[p * Nk + lane], a = aexp[p * Nk + lane];
-            float s = fmaf(z, rb.inv_step, -rb.mu0_over_step);
-            float jr = fminf(fmaxf(rintf(s), -(float)RBF_WIN), rb.jmax);
-            float d = s - jr;
-            if (fabsf(d) > 0.5f) continue;  // beyond every centre by more than W spacings
-            // G_{jr+m} = E0 q^m c_m,  E0 = exp(-rho d^2/2),  q = exp(rho d)
-            float E0 = __builtin_amdgcn_exp2f(-0.5f * rb.rho_log2e * d * d);
-            float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
-            float qi = __builtin_amdgcn_exp2f(-rb.rho_log2e * d);
-            float *hrow = hist + (int)jr;
-            float up = a * E0, dn = a * E0;
-            hrow[0] += up * rb.c[RBF_WIN];
+        // DW_U pixels per step; the z and a of the next step are loaded while
+        // this step's are binned (an element past p1 carries a = 0 and adds 0)
+        constexpr int U = DW_U;
+        float zn[U], an[U];
+        auto load = [&](long long pb) {
 #pragma unroll
-            for (int m = 1; m <= RBF_WIN; ++m) {
-                up *= q;
-                dn *= qi;
-                hrow[m] += up * rb.c[RBF_WIN + m];
-                hrow[-m] += dn * rb.c[RBF_WIN - m];
+            for (int u = 0; u < U; ++u) {
+                const long long p = pb + (long long)u * NW;
+                const long long pc = p < p1 ? p : p0;
+                zn[u] = zexp[pc * Nk + lane];
+                an[u] = p < p1 ? aexp[pc * Nk + lane] : 0.f;
+            }
+        };
+        load(p0 + wave);
+        for (long long pb = p0 + wave; pb < p1; pb += (long long)U * NW) {
+            float zc[U], ac[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                zc[u] = zn[u];
+                ac[u] = an[u];
+            }
+            load(pb + (long long)U * NW);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float z = zc[u];
+                float s = fmaf(z, rb.inv_step, -rb.mu0_over_step);
+                float jr = fminf(fmaxf(rintf(s), -(float)RBF_WIN), rb.jmax);
+                float d = s - jr;
+                // beyond every centre by more than W spacings: nothing to add
+                const float a = fabsf(d) <= 0.5f ? ac[u] : 0.f;
+                // G_{jr+m} = E0 q^m c_m,  E0 = exp(-rho d^2/2),  q = exp(rho d)
+                float E0 = __builtin_amdgcn_exp2f(-0.5f * rb.rho_log2e * d * d);
+                float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
+                float qi = __builtin_amdgcn_exp2f(-rb.rho_log2e * d);
+                float *hrow = hist + (int)jr;
+                float up = a * E0, dn = a * E0;
+                hrow[0] += up * rb.c[RBF_WIN];
+#pragma unroll
+                for (int m = 1; m <= RBF_WIN; ++m) {
+                    up *= q;
+                    dn *= qi;
+                    hrow[m] += up * rb.c[RBF_WIN + m];
+                    hrow[-m] += dn * rb.c[RBF_WIN - m];
+                }
             }
         }
     }
@@ -434,27 +456,58 @@ __global__ void __launch_bounds__(RED_E * RED_R) k_reduce_partials(
 namespace {
 
 struct BwdGeom {
+    int th;                        // k_bwd_params tile height
     int tiles_x, tiles_y, tiles;   // k_bwd_params tiles (per image) and total
     int dw_grid;
     long long dw_per_wg;
     size_t img;                    // N*H*W
 };
 
-BwdGeom bwd_geom(int N, int H, int W)
+// k_bwd_params tiles of th rows (and 16 BP_NBW columns); the dW grid.
+BwdGeom bwd_geom(int N, int H, int W, int th)
 {
     BwdGeom gm;
     const int tw = 16 * BP_NBW;
+    gm.th = th;
     gm.tiles_x = (W + tw - 1) / tw;
-    gm.tiles_y = (H + BP_TH - 1) / BP_TH;
+    gm.tiles_y = (H + th - 1) / th;
     gm.tiles = gm.tiles_x * gm.tiles_y * N;
     gm.img = (size_t)N * H * W;
     long long P = (long long)gm.img;
+    // at most 256 workgroups: k_bwd_dw holds one per compute unit (its LDS
+    // histograms), and a longer workgroup pays the zeroing and the final
+    // reduction of its histograms once
     long long grid = (P + 255) / 256;
-    if (grid > 1024) grid = 1024;
+    if (grid > 256) grid = 256;
     if (grid < 1) grid = 1;
     gm.dw_per_wg = (P + grid - 1) / grid;
     gm.dw_grid = (int)((P + gm.dw_per_wg - 1) / gm.dw_per_wg);
     return gm;
+}
+
+// Tile height of k_bwd_params: the kernel holds two 4-wave workgroups per
+// compute unit (its register footprint), so n tiles run in ceil(n / (2 CUs))
+// rounds of th rows of BP_NBW blocks each (plus a fixed cost of ~4 blocks).
+int bwd_tile_h(int N, int H, int W)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const long slots = 2L * cus;
+    int best_th = BP_TH_MIN;
+    double best = 0.0;
+    for (int th = BP_TH_MIN; th <= BP_TH_MAX; ++th) {
+        const long tiles = (long)N * ((H + th - 1) / th) * ((W + 16 * BP_NBW - 1) / (16 * BP_NBW));
+        const long rounds = (tiles + slots - 1) / slots;
+        const double cost = (double)rounds * (th * BP_NBW + 4) + 1e-6 * th;
+        if (th == BP_TH_MIN || cost < best) {
+            best = cost;
+            best_th = th;
+        }
+        if (th >= H) break;
+    }
+    return best_th;
 }
 
 constexpr size_t AL = 256;
@@ -467,7 +520,7 @@ struct BwdWs {
 
 BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s)
 {
-    BwdGeom gm = bwd_geom(N, H, W);
+    BwdGeom gm = bwd_geom(N, H, W, BP_TH_MIN);  // the most tiles any launch uses
     const size_t kk = (size_t)m->ksize * m->ksize;
     BwdWs w;
     size_t off = AL;  // flags
@@ -489,11 +542,11 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s)
 }
 
 template <int KS, int NMB>
-hipError_t launch_bwd_params(const BwdParamsIO &io, int N, int H, int W, const float *filt, int Nk,
-                             const float *rbfw, const RbfGrid &grid, const float *lam,
+hipError_t launch_bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, int W, const float *filt,
+                             int Nk, const float *rbfw, const RbfGrid &grid, const float *lam,
                              hipStream_t stream)
 {
-    BpLds L = bp_lds(KS, NMB, BP_TH, 16 * BP_NBW, grid.nrbf, BP_NW);
+    BpLds L = bp_lds(KS, NMB, gm.th, 16 * BP_NBW, grid.nrbf, BP_NW);
     size_t lds_bytes = (size_t)L.total * sizeof(float);
     static bool attr_set = false;
     if (!attr_set) {
@@ -502,33 +555,31 @@ hipError_t launch_bwd_params(const BwdParamsIO &io, int N, int H, int W, const f
         (void)hipGetLastError();
         attr_set = true;
     }
-    BwdGeom gm = bwd_geom(N, H, W);
     const int per_img = gm.tiles_x * gm.tiles_y;
     FusedRbf rb = make_fused_rbf(grid);
     hipLaunchKernelGGL((k_bwd_params<KS, NMB, BP_NBW, BP_NW>), dim3(gm.tiles), dim3(64 * BP_NW),
-                       lds_bytes, stream, io, H, W, BP_TH, gm.tiles_x, per_img, filt, Nk, rbfw,
+                       lds_bytes, stream, io, H, W, gm.th, gm.tiles_x, per_img, filt, Nk, rbfw,
                        grid.nrbf, rb, lam);
     return hipGetLastError();
 }
 
-hipError_t bwd_params(const BwdParamsIO &io, int N, int H, int W, int ks, const float *filt,
+hipError_t bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, int W, int ks, const float *filt,
                       int Nk, const float *rbfw, const RbfGrid &grid, const float *lam,
                       hipStream_t stream)
 {
     const int nmb = (Nk + 15) / 16;
     if (ks == 7)
-        return nmb <= 2 ? launch_bwd_params<7, 2>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream)
-                        : launch_bwd_params<7, 3>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream);
+        return nmb <= 2 ? launch_bwd_params<7, 2>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params<7, 3>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     if (ks == 5)
-        return nmb <= 2 ? launch_bwd_params<5, 2>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream)
-                        : launch_bwd_params<5, 3>(io, N, H, W, filt, Nk, rbfw, grid, lam, stream);
+        return nmb <= 2 ? launch_bwd_params<5, 2>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params<5, 3>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     return hipErrorInvalidValue;
 }
 
-hipError_t bwd_dw(const float *zexp, const float *aexp, int N, int H, int W, int Nk,
+hipError_t bwd_dw(const float *zexp, const float *aexp, const BwdGeom &gm, int Nk,
                   const RbfGrid &grid, float *dw_part, hipStream_t stream)
 {
-    BwdGeom gm = bwd_geom(N, H, W);
     const size_t lds_bytes = (size_t)DW_NW * Nk * (grid.nrbf + 4 * RBF_WIN + 1) * sizeof(float);
     static bool attr_set = false;
     if (!attr_set) {
@@ -554,7 +605,7 @@ hipError_t reduce_partials(const float *part, int nparts, int nelem, float scale
 bool bwd_lds_ok(const tnrd_model *m)
 {
     const int nmb = (m->Nk + 15) / 16 <= 2 ? 2 : 3;
-    BpLds L = bp_lds(m->ksize, nmb, BP_TH, 16 * BP_NBW, m->Nrbf, BP_NW);
+    BpLds L = bp_lds(m->ksize, nmb, BP_TH_MAX, 16 * BP_NBW, m->Nrbf, BP_NW);
     size_t dw = (size_t)DW_NW * m->Nk * (m->Nrbf + 4 * RBF_WIN + 1) * sizeof(float);
     return (size_t)L.total * sizeof(float) <= 160 * 1024 && dw <= 160 * 1024;
 }
@@ -605,7 +656,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
         return TNRD_OK;
     }
     BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s);
-    BwdGeom gm = bwd_geom(N, H, W);
+    BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W));
     const size_t img = gm.img;
     if (oo.validate) {
         st = run_domain_check(f, img, (int *)ws, stream);
@@ -629,7 +680,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     ia.tile_h = 0;
     ia.tile_w = 0;
     ia.waves = 0;
-    ia.poly = 0;
+    ia.poly = oo.rbf_window < 0;
 
     const float *g_cur = grad_uT;
     int ping = 0;
@@ -664,9 +715,9 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             io.aexp = w.aexp;
             io.dk_part = w.dk_part;
             io.dl_part = w.dl_part;
-            if (bwd_params(io, N, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) != hipSuccess)
+            if (bwd_params(io, gm, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) != hipSuccess)
                 return TNRD_ERR_HIP;
-            if (bwd_dw(w.zexp, w.aexp, N, H, W, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
+            if (bwd_dw(w.zexp, w.aexp, gm, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
                 return TNRD_ERR_HIP;
             if (reduce_partials(w.dk_part, gm.tiles, (int)(m->Nk * kk), -1.f,
                                 grad_filters + (size_t)ts * m->Nk * kk, stream) != hipSuccess ||

@@ -78,6 +78,9 @@ __device__ __forceinline__ void rbf_phi_dphi_direct(float z, const float *__rest
 //   u = (ut + s) / (2(1+2l)),  s = sqrt(ut^2 + 8(1+2l) l f^2).
 // For ut < 0 the same root is evaluated as c / ((s - ut) 2(1+2l)), c = 8(1+2l) l f^2,
 // which avoids the cancellation in ut + s ((ut + s)(s - ut) = c).
+// Correctly rounded square root and divisions: the states feed the lambda
+// gradient, a sum over all pixels with heavy cancellation, which 1-ulp
+// hardware approximations here move by several 1e-4 relative.
 __device__ __forceinline__ float prox(float ut, float f, float lam)
 {
     float c1 = 1.f + 2.f * lam;

@@ -5,9 +5,10 @@
 
 namespace tnrd {
 
-// Monomial coefficients M[k][m] (k = 0..7) of the degree-7 interpolant of
-// exp(-rho (d - m)^2 / 2) at the Chebyshev points of [-1/2, 1/2], in FP64.
-static void poly_gauss_coeffs(double rho, double M[POLY_NC][POLY_MW + 1])
+// Monomial coefficients M[k][m] (k = 0..7) of the degree-7 interpolant at the
+// Chebyshev points of [-1/2, 1/2] of exp(-rho (d - m)^2 / 2) (deriv = false)
+// or of its derivative -rho (d - m) exp(-rho (d - m)^2 / 2) (deriv = true), in FP64.
+static void poly_gauss_coeffs(double rho, bool deriv, double M[POLY_NC][POLY_MW + 1])
 {
     const double pi = 3.14159265358979323846;
     double x[POLY_NC];
@@ -21,7 +22,8 @@ static void poly_gauss_coeffs(double rho, double M[POLY_NC][POLY_MW + 1])
                 A[n][k] = p;
                 p *= x[n];
             }
-            A[n][POLY_NC] = exp(-rho * (x[n] - m) * (x[n] - m) / 2.0);
+            const double g = exp(-rho * (x[n] - m) * (x[n] - m) / 2.0);
+            A[n][POLY_NC] = deriv ? -rho * (x[n] - m) * g : g;
         }
         for (int col = 0; col < POLY_NC; ++col) {
             int piv = col;
@@ -58,16 +60,21 @@ FusedRbf make_fused_rbf(const RbfGrid &grid)
         double m = n - RBF_WIN;
         rb.c[n] = (float)exp(-rho * m * m / 2.0);
     }
-    double M[POLY_NC][POLY_MW + 1];
-    poly_gauss_coeffs(rho, M);
+    double M[POLY_NC][POLY_MW + 1], Md[POLY_NC][POLY_MW + 1];
+    poly_gauss_coeffs(rho, false, M);
+    poly_gauss_coeffs(rho, true, Md);
     for (int k = 0; k < POLY_NC; ++k)
-        for (int m = 0; m <= POLY_MW; ++m) rb.pm[k][m] = (float)M[k][m];
+        for (int m = 0; m <= POLY_MW; ++m) {
+            rb.pm[k][m] = (float)M[k][m];
+            rb.pmd[k][m] = (float)Md[k][m];
+        }
     return rb;
 }
 
 // The polynomial form is used with the automatic window only, i.e. for
 // rho = (step / sigma)^2 in [0.914, 1.365), where the interpolation error summed
-// over all centres stays below 8e-7 of the largest weight (2.5e-7 at rho = 1).
+// over all centres stays below 8e-7 of the largest weight for phi (2.5e-7 at
+// rho = 1) and below 1e-6 of it for d phi / ds (1.8e-7 at rho = 1).
 bool poly_form_ok(const RbfGrid &grid, int automatic_window)
 {
     if (!automatic_window || grid.window != RBF_WIN) return false;
@@ -107,8 +114,9 @@ struct TilePlan {
 // is taken as given (clamped to the image).  Otherwise the tile minimises the
 // modelled time: the kernel holds one workgroup per compute unit (its LDS
 // footprint), so a launch of n tiles runs in ceil(n / CUs) rounds, each as
-// long as one tile: (Th + 2R) E rows of nb 16-pixel blocks, plus a fixed cost
-// (prologue, output pass) worth about 14 blocks of the polynomial form.  Tile widths are those whose
+// long as one tile.  A tile's (Th + 2R) E rows go to its waves in rounds, so a
+// wave runs ceil((Th + 2R) / waves) rows of nb 16-pixel blocks, plus a fixed
+// cost (prologue, output passes) worth about 2 such blocks.  Tile widths are those whose
 // E rows fill their blocks exactly (16 nb - 2R).
 static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req_h, int req_w,
                           int waves, int mode, bool poly)
@@ -118,7 +126,7 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
     p.nw = waves == 4 ? 4 : 8;
     p.ok = false;
     auto form = [&](int th, int tw, int nb) {
-        if (mode == MODE_FWD && poly && lds_fits(ks, nk, nrbf, th, tw, nb, p.nw, mode, RBF_POLY))
+        if (poly && lds_fits(ks, nk, nrbf, th, tw, nb, p.nw, mode, RBF_POLY))
             return (int)RBF_POLY;
         if (lds_fits(ks, nk, nrbf, th, tw, nb, p.nw, mode, RBF_HORNER)) return (int)RBF_HORNER;
         return -1;
@@ -145,9 +153,12 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
             if (rbfm < 0) continue;
             const long tiles = (long)N * ((H + t - 1) / t) * ((W + tw - 1) / tw);
             const long rounds = (tiles + cus - 1) / cus;
-            // a block of the Gaussian form costs about 1.3 blocks of the polynomial form
-            const double blk = (mode == MODE_FWD && rbfm == RBF_HORNER ? 1.3 : 1.0) * (t + 2 * R) * nb;
-            const double cost = (double)rounds * (blk + 14) + 1e-6 * (double)tiles * blk;  // ties: fewer blocks
+            // per wave: ceil(E rows / waves) rows of nb blocks (the rows go to the
+            // waves in rounds); a block of the Gaussian form costs about 1.3 blocks
+            // of the polynomial form
+            const int erows = (t < H ? t : H) + 2 * R;
+            const double blk = (rbfm == RBF_HORNER ? 1.3 : 1.0) * ((erows + p.nw - 1) / p.nw) * nb;
+            const double cost = (double)rounds * (blk + 2) + 1e-6 * (double)tiles * erows * nb;  // ties: fewer blocks
             if (!p.ok || cost < best) {
                 best = cost;
                 p.th = t;
@@ -165,11 +176,11 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
 template <int MODE>
 static hipError_t fused_dispatch(const StageArgs &s, hipStream_t stream)
 {
-    const bool poly = MODE == MODE_FWD && s.poly && poly_form_ok(s.grid, 1);
+    const bool poly = s.poly && poly_form_ok(s.grid, 1);
     const TilePlan p = plan_tile(s.ks, s.Nk, s.grid.nrbf, s.N, s.H, s.W, s.tile_h, s.tile_w, s.waves,
                                  MODE, poly);
     if (!p.ok) return hipErrorInvalidValue;
-    if (MODE == MODE_BWD_INPUT) return fused_launch_bwd(s, p.th, p.tw, p.nb, p.nw, stream);
+    if (MODE == MODE_BWD_INPUT) return fused_launch_bwd(s, p.th, p.tw, p.nb, p.nw, p.rbfm, stream);
     if (s.prec == PREC_BF16 || s.prec == PREC_F16)
         return fused_launch_fwd_mixed(s, p.th, p.tw, p.nb, p.nw, p.rbfm, stream);
     return fused_launch_fwd_f32(s, p.th, p.tw, p.nb, p.nw, p.rbfm, stream);

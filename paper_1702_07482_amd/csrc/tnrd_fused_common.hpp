@@ -55,7 +55,10 @@ constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
 // over j0 = -W .. Nrbf-1+W (W = RBF_WIN) with one zero interval at each end;
 // beyond them phi is taken as 0, the same cut as the window of the Gaussian
 // form.  Centres farther than POLY_MW spacings from the interval contribute
-// below exp(-rho 6.5^2 / 2) of their weight and are left out.
+// below exp(-rho 6.5^2 / 2) of their weight and are left out.  The input-
+// gradient mode, which needs phi', uses the interpolant of d phi / ds built the
+// same way from the derivatives -rho (d - m) exp(-rho (d - m)^2 / 2) (Md[k][m],
+// odd in m: c_k = sum Md[k][|m|] sgn(m)^(k+1) w_{j0+m}).
 constexpr int POLY_DEG = 7;
 constexpr int POLY_NC = POLY_DEG + 1;     // coefficients per interval
 constexpr int POLY_MW = RBF_WIN + 1;      // centres on each side of j0 in the fit
@@ -79,7 +82,8 @@ struct FusedRbf {
     float jmax;           // Nrbf - 1 + W (largest clamped centre index)
     float rho_over_step;  // rho / step (chain factor of d phi / dz)
     float c[RBF_TERMS];
-    float pm[POLY_NC][POLY_MW + 1];  // M[k][m] of the polynomial form
+    float pm[POLY_NC][POLY_MW + 1];   // M[k][m] of the polynomial form of phi
+    float pmd[POLY_NC][POLY_MW + 1];  // the same for d phi / ds (input-gradient mode)
 };
 
 // Kernel arguments of one stage (forward or input-gradient mode).
@@ -120,8 +124,7 @@ struct Geo2 {
 template <int CTRL>
 __device__ __forceinline__ float dpp_zero(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
-                                                                 0xF, 0xF, true));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float row_shl(float v, int n)

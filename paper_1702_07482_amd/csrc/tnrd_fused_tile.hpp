@@ -80,7 +80,7 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     const int luh = th + 4 * R;
     l.ldw = tw + 4 * R + 1;
     l.u_off = 0;
-    l.u_size = (luh * l.ldw + 3) & ~3;
+    l.u_size = (luh * l.ldw + 63) & ~63;  // whole 64-word chunks (the direct-to-LDS loads)
     l.e_off = l.u_off + l.u_size;
     l.t_off = l.e_off + (mode == MODE_BWD_INPUT ? l.u_size : 0);
     l.t_pitch = nrbf + 4 * RBF_WIN + 1;
@@ -112,7 +112,6 @@ __device__ __forceinline__ void fused_tile(
 {
     constexpr bool BWD = MODE == MODE_BWD_INPUT;
     constexpr bool POLY = RBFM == RBF_POLY;
-    static_assert(!(BWD && POLY), "the input-gradient mode needs phi' and uses the Gaussian form");
     const float *__restrict__ u_prev = io.u_prev;
     const float *__restrict__ f = io.f;
     using G = Geo<KS>;
@@ -153,28 +152,6 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 if (base + k * THREADS + tid < nf) sf[base + k * THREADS + tid] = v[k];
-        }
-    }
-    // (2) the u tile (rows ty0-2R .. ty0+Th+2R-1), reflected at the border
-    {
-        const int n = luh * luw;
-        for (int base = 0; base < n; base += 8 * THREADS) {
-            float v[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                int i = min(base + k * THREADS + tid, n - 1);
-                int ly = i / luw, lx = i - ly * luw;
-                int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
-                v[k] = u_prev[(size_t)yy * W + xx];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                int i = base + k * THREADS + tid;
-                if (i < n) {
-                    int ly = i / luw, lx = i - ly * luw;
-                    su[ly * L.ldw + lx] = v[k];
-                }
-            }
         }
     }
     // (2b) input-gradient mode: e = y * g_t over the same region, where
@@ -236,6 +213,20 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 if (base + k * THREADS + tid < n) dst[base + k * THREADS + tid] = v[k];
+        }
+    }
+    // (2) the u tile (rows ty0-2R .. ty0+Th+2R-1, reflected at the border),
+    // loaded straight into LDS in 64-word chunks (lane l of a wave fills word
+    // l of its chunk).  The loads stay in flight while the filter registers
+    // and the coefficient table are set up; padding words get an in-image value.
+    {
+        for (int c = wave; c * 64 < L.u_size; c += NW) {
+            const int k = c * 64 + lane;
+            const int ly = k / L.ldw, lx = k - ly * L.ldw;
+            const bool in = ly < luh && lx < luw;
+            const int yy = reflect_clamp(ty0 - 2 * R + (in ? ly : 0), H);
+            const int xx = reflect_clamp(tx0 - 2 * R + (in ? lx : 0), W);
+            __builtin_amdgcn_global_load_lds(u_prev + (size_t)yy * W + xx, su + c * 64, 4, 0, 0);
         }
     }
     __syncthreads();
@@ -324,8 +315,12 @@ __device__ __forceinline__ void fused_tile(
 
     if (POLY) {
         // (4) coefficient table of the polynomial form from the staged weights:
-        // c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} + (-1)^k w_{j0-m})
+        // phi:        c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} + (-1)^k w_{j0-m})
+        // d phi / ds: c_k = Md[k][0] w_j0 + sum_{m>=1} Md[k][m] (w_{j0+m} - (-1)^k w_{j0-m})
+        // (the even-in-d part of a term centred at j0 vanishes for the derivative)
         const int ni = L.ni;
+        const float(*pm)[POLY_MW + 1] = BWD ? rb.pmd : rb.pm;
+        constexpr int par = BWD ? 1 : 0;  // parity of k whose terms are sums
         for (int idx = tid; idx < 16 * NMB * ni; idx += THREADS) {
             const int fi = idx / ni, q = idx - fi * ni;
             float c[POLY_NC];
@@ -335,20 +330,21 @@ __device__ __forceinline__ void fused_tile(
                 const float *wc = sp + fi * L.w_pitch + (q - 1 - RBF_WIN) + POLY_PAD;  // w_j0
                 const float w0 = wc[0];
 #pragma unroll
-                for (int k = 0; k < POLY_NC; k += 2) c[k] = rb.pm[k][0] * w0;
+                for (int k = par; k < POLY_NC; k += 2) c[k] = pm[k][0] * w0;
 #pragma unroll
                 for (int m = 1; m <= POLY_MW; ++m) {
                     const float sum = wc[m] + wc[-m], dif = wc[m] - wc[-m];
 #pragma unroll
-                    for (int k = 0; k < POLY_NC; ++k) c[k] = fmaf(rb.pm[k][m], (k & 1) ? dif : sum, c[k]);
+                    for (int k = 0; k < POLY_NC; ++k) c[k] = fmaf(pm[k][m], ((k & 1) == par) ? sum : dif, c[k]);
                 }
             }
             float *dst = stab + fi * (POLY_NC * ni) + 4 * q;
             *reinterpret_cast<floatx4 *>(dst) = floatx4{c[0], c[1], c[2], c[3]};
             *reinterpret_cast<floatx4 *>(dst + 4 * ni) = floatx4{c[4], c[5], c[6], c[7]};
         }
-        __syncthreads();  // the table is complete; the staged weights are dead
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the direct-to-LDS u tile loads have landed
+    __syncthreads();  // u tile and table complete; the staged weights are dead
 
     // GEMM1 B-operand offsets: tap t = 4 s + g -> (a, b) = (t / KS, t % KS)
     int off1[KS1];
@@ -433,7 +429,7 @@ __device__ __forceinline__ void fused_tile(
             const float s = fmaf(acc1[mb][r], rb.inv_step, -rb.mu0_over_step);
             const float jr = rintf(s);
             dq[slot][r] = s - jr;
-            const int q = (int)fminf(fmaxf(jr + (float)(RBF_WIN + 1), 0.f), (float)(L.ni - 1));
+            const int q = (int)__builtin_amdgcn_fmed3f(jr + (float)(RBF_WIN + 1), 0.f, (float)(L.ni - 1));
             const float *cp = stab + (16 * mb + r) * (POLY_NC * L.ni) + tab_g + 4 * q;
             lo[slot][r] = *reinterpret_cast<const floatx4 *>(cp);
             hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * L.ni);
@@ -455,6 +451,8 @@ __device__ __forceinline__ void fused_tile(
                 p = fmaf(p, d, l[2]);
                 p = fmaf(p, d, l[1]);
                 p = fmaf(p, d, l[0]);
+                // input-gradient mode: p = d phi / ds, so phi'(z) a = p a / step
+                if (BWD) p *= rb.inv_step * acca[mb][r];
                 acc1[mb][r] = valid ? p : 0.f;
             }
         } else {
@@ -788,9 +786,7 @@ template <int KS, int NMB, int MODE, int PREC>
 inline hipError_t fused_form(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
                              hipStream_t stream)
 {
-    if constexpr (MODE == MODE_FWD) {
-        if (rbfm == RBF_POLY) return fused_nw<KS, NMB, MODE_FWD, PREC, RBF_POLY>(s, th, tw, nb, nw, stream);
-    }
+    if (rbfm == RBF_POLY) return fused_nw<KS, NMB, MODE, PREC, RBF_POLY>(s, th, tw, nb, nw, stream);
     return fused_nw<KS, NMB, MODE, PREC, RBF_HORNER>(s, th, tw, nb, nw, stream);
 }
 

@@ -27,7 +27,7 @@ struct StageArgs {
     int prec;             // tnrd_prec
     int tile_h, tile_w;   // 0 = automatic
     int waves;            // fused: waves per workgroup (4 or 8; 0 = automatic)
-    int poly;             // fused forward: the polynomial influence form may be used
+    int poly;             // fused kernel: the polynomial influence form may be used
 };
 
 // Batched forward (device descriptors, filled on the host).
@@ -77,7 +77,8 @@ hipError_t fused_launch_fwd_f32(const StageArgs &s, int th, int tw, int nb, int 
                                 hipStream_t stream);
 hipError_t fused_launch_fwd_mixed(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
                                   hipStream_t stream);
-hipError_t fused_launch_bwd(const StageArgs &s, int th, int tw, int nb, int nw, hipStream_t stream);
+hipError_t fused_launch_bwd(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
+                            hipStream_t stream);
 hipError_t batched_launch_impl(const BatchArgs &a, int ks, int nb, int nw, int rbfm,
                                hipStream_t stream);
 

@@ -96,3 +96,59 @@ def test_odd_coefficients_vanish_at_the_centre():
     # the Gaussian centred on the interval is even in d
     M = gauss_coeffs(1.0)
     assert np.all(np.abs(M[1::2, 0]) < 1e-12)
+
+
+def deriv_coeffs(rho):
+    """Md[k][m]: monomial coefficients of the interpolant of -rho (d - m) exp(-rho (d - m)^2 / 2)."""
+    x = chebyshev_nodes()
+    V = np.vander(x, DEG + 1, increasing=True)
+    M = np.zeros((DEG + 1, MW + 1))
+    for m in range(MW + 1):
+        M[:, m] = np.linalg.solve(V, -rho * (x - m) * np.exp(-rho * (x - m) ** 2 / 2))
+    return M
+
+
+@pytest.mark.parametrize("rho", [0.915, 1.0, 1.2, 1.364])
+def test_derivative_form_bound(rho):
+    """The input-gradient mode's interpolant of d phi / ds: summed error over all
+    centres below 1e-6 of the largest weight over the automatic-window range
+    (and below 2e-7 at rho = 1)."""
+    M = deriv_coeffs(rho)
+    d = np.linspace(-0.5, 0.5, 4001)
+    tot = np.zeros_like(d)
+    for m in range(-40, 41):
+        h = -rho * (d - m) * np.exp(-rho * (d - m) ** 2 / 2)
+        if abs(m) <= MW:
+            c = M[:, abs(m)] * ((-1.0) ** (np.arange(DEG + 1) + 1) if m < 0 else 1.0)
+            p = np.polynomial.polynomial.polyval(d, c)
+        else:
+            p = 0.0
+        tot += np.abs(h - p)
+    assert tot.max() < (2e-7 if rho == 1.0 else 1e-6)
+
+
+def test_derivative_form_matches_full_sum():
+    """d phi / ds on an interval from the weights (odd part as sums, even part as
+    differences) equals the full sum's derivative within the bound."""
+    rng = np.random.default_rng(7482)
+    nrbf, rho = 63, 1.0
+    M = deriv_coeffs(rho)
+    assert np.all(np.abs(M[0::2, 0]) < 1e-12)  # the centred term is odd in d
+    w = rng.normal(0.0, 0.1, nrbf)
+    wp = np.zeros(nrbf + 2 * (W + MW))
+    wp[W + MW:W + MW + nrbf] = w
+    d = np.linspace(-0.5, 0.5, 101)
+    j = np.arange(nrbf)
+    worst = 0.0
+    for j0 in range(-W, nrbf + W):
+        wc = lambda m: wp[j0 + m + W + MW]
+        c = np.zeros(DEG + 1)
+        for k in range(DEG + 1):
+            c[k] = M[k, 0] * wc(0) if k % 2 == 1 else 0.0
+            for m in range(1, MW + 1):
+                c[k] += M[k, m] * (wc(m) - (-1) ** k * wc(-m))
+        approx = np.polynomial.polynomial.polyval(d, c)
+        s = (j0 + d)[:, None] - j[None, :]
+        exact = (w[None, :] * (-rho * s) * np.exp(-rho * s ** 2 / 2)).sum(1)
+        worst = max(worst, np.abs(approx - exact).max() / np.abs(w).max())
+    assert worst < 2e-7
