@@ -10,6 +10,8 @@ Extra legs reported on the same JSON line (each its own workload):
   fwd_bwd  16 x 180 x 180, forward with saved states + hand-written backward
   batched  64 uneven images, one launch per stage over all tiles, replayed from a HIP graph
   mixed    8 x 2048 x 2048 with BF16/FP16 filter-bank operands
+  peaks    measured copy, matrix, vector-FMA and exp2 throughput; the legs' rates
+           against them ("fractions")
 
 The CPU baseline times the FP64 oracle (tests' reference, not a product path)
 on a bounded strip of the same workload.
@@ -44,7 +46,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--impl", default="auto", choices=["auto", "fused", "split"])
-    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed")
+    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed,peaks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of known "
@@ -315,6 +317,61 @@ def leg_mixed(args):
     return res
 
 
+def leg_peaks(args):
+    """Measured throughput of the units the kernels run on (copy, FP32 and BF16
+    matrix instructions, FP32 vector FMA, hardware exp2), from the library's probes."""
+    import torch
+    from paper_1702_07482_amd import tnrd
+
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.empty(tnrd.tnrd_peaks_sink_floats(), device="cuda")
+    torch.cuda.synchronize()
+    p = tnrd.tnrd_measure_peaks(src, dst, nbytes, sink)
+    del src, dst, sink
+    return p
+
+
+def fractions(out):
+    """Rates of the legs against the measured peaks.  The modelled ceiling of the
+    FP32 forward counts the algorithmic work of a pixel-stage: 9408 flop of
+    convolution on the FP32 matrix unit plus the influence function's 48 x 7
+    FMAs (polynomial form) on the vector unit, which share one datapath, so
+    their times add."""
+    pk = out.get("peaks")
+    if not pk:
+        return None
+    fr = {}
+    conv = out["roofline"]["achieved"]
+    fr["fwd_conv_vs_measured_mfma_f32"] = conv / pk["mfma_f32_tflops"]
+    t_px = (FLOP_PER_PX_STAGE_FWD / (pk["mfma_f32_tflops"] * 1e12)
+            + 2 * 48 * 7 / (pk["valu_f32_tflops"] * 1e12))
+    ceiling = 1.0 / t_px / 1e6  # megapixel-stages/s
+    fr["fwd_modelled_ceiling_mpst_s"] = ceiling
+    fr["fwd_vs_modelled_ceiling"] = out["value"] / ceiling
+    fr["fwd_hbm_algorithmic_gbs"] = out["roofline"]["algorithmic_bytes_per_launch"] / (
+        out["roofline"]["per_launch_us"] * 1e-6) / 1e9
+    fr["fwd_hbm_algorithmic_vs_measured_copy"] = fr["fwd_hbm_algorithmic_gbs"] / pk["copy_gbs"]
+    if out["roofline"].get("traffic"):
+        fr["fwd_hbm_counted_gbs"] = out["roofline"]["traffic"] / (out["roofline"]["per_launch_us"] * 1e-6) / 1e9
+    mx = out.get("mixed")
+    if mx:
+        for name in ("fp32", "bf16", "fp16"):
+            if name in mx:
+                tf = mx[name]["fwd_mpst_s"] * 1e6 * FLOP_PER_PX_STAGE_FWD / 1e12
+                peak = pk["mfma_f32_tflops"] if name == "fp32" else pk["mfma_bf16_k16_tflops"]
+                fr[f"mixed_{name}_fwd_conv_tflops"] = tf
+                fr[f"mixed_{name}_fwd_conv_vs_measured_peak"] = tf / peak
+    fb = out.get("fwd_bwd")
+    if fb:
+        # forward (9408) + backward: recomputed K u, K e, K^T, two dK correlations (5 x 4704)
+        tf = fb["value"] * 1e6 * (FLOP_PER_PX_STAGE_FWD + 5 * 4704) / 1e12
+        fr["fwd_bwd_conv_tflops"] = tf
+        fr["fwd_bwd_conv_vs_measured_mfma_f32"] = tf / pk["mfma_f32_tflops"]
+    return fr
+
+
 def resolve_auto_impl():
     """The implementation IMPL_AUTO runs for the headline workload."""
     import torch
@@ -329,15 +386,18 @@ def cpu_baseline(f, m, rows):
     import oracle
 
     strip = np.ascontiguousarray(f[:rows])
-    t0 = time.perf_counter()
-    oracle.forward(strip, m)
-    dt = time.perf_counter() - t0
+    # repeated until about 10 s of CPU work (at most 4 runs)
+    runs, t0 = 0, time.perf_counter()
+    while runs < 4 and (runs == 0 or time.perf_counter() - t0 < 10.0):
+        oracle.forward(strip, m)
+        runs += 1
+    dt = (time.perf_counter() - t0) / runs
     T = m["filters"].shape[0]
     return {
         "value": strip.size * T / 1e6 / dt, "unit": "megapixel-stages/s",
         "cores": oracle.max_threads(), "kind": "oracle",
         "sample": f"FP64 oracle forward, all {T} stages, on rows 0..{rows - 1} of the "
-                  f"512x512 image ({rows}x512 px), {dt:.1f} s",
+                  f"512x512 image ({rows}x512 px), {runs} runs of {dt:.1f} s each",
     }
 
 
@@ -388,6 +448,9 @@ def main():
         out["batched"] = leg_batched(args)
     if "mixed" in legs:
         out["mixed"] = leg_mixed(args)
+    if "peaks" in legs:
+        out["peaks"] = leg_peaks(args)
+        out["fractions"] = fractions(out)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fwd["f"], fwd["m"], args.cpu_rows)
     print(json.dumps(out), flush=True)

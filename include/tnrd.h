@@ -178,6 +178,29 @@ int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models, const tnrd
 /* Static description of a status code. */
 const char *tnrd_status_str(int status);
 
+/* ---- Measurement aid (not part of the filter) ----------------------------
+ * Throughput probes of the units the stage kernels run on, so that their rates
+ * can be read against measured rather than published peaks.  Each probe runs a
+ * fixed launch on `stream` and is timed with HIP events over several launches
+ * after a warm-up; the call synchronises with the stream.
+ *   copy_gbs              device-to-device copy of copy_bytes (read + write bytes / s)
+ *   mfma_f32_tflops       v_mfma_f32_16x16x4_f32 (the FP32 filter-bank instruction)
+ *   mfma_bf16_k16_tflops  v_mfma_f32_16x16x16_bf16 (the mixed-precision instruction)
+ *   mfma_bf16_k32_tflops  v_mfma_f32_16x16x32_bf16
+ *   valu_f32_tflops       FP32 vector FMA, unpacked (2 flop per lane)
+ *   exp_per_s             hardware exp2 (v_exp_f32) results per second
+ * copy_src/copy_dst: device buffers of copy_bytes each (>= 16 MiB, a multiple
+ * of 16); sink: device buffer of tnrd_peaks_sink_floats() floats (overwritten
+ * with throw-away values).  Returns TNRD_ERR_ARG for a NULL pointer or a bad
+ * size, TNRD_ERR_HIP if a launch or event call fails. */
+typedef struct tnrd_peaks {
+    double copy_gbs, mfma_f32_tflops, mfma_bf16_k16_tflops, mfma_bf16_k32_tflops;
+    double valu_f32_tflops, exp_per_s;
+} tnrd_peaks;
+size_t tnrd_peaks_sink_floats(void);
+int tnrd_measure_peaks(const void *copy_src, void *copy_dst, size_t copy_bytes, float *sink,
+                       tnrd_peaks *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

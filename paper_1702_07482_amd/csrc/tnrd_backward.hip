@@ -12,22 +12,26 @@
 //   g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)                  (transposed eq. derv1-1)
 //
 // Three kernels per stage, then one deterministic reduction:
-//   k_fused_stage<.., MODE_BWD_INPUT>  g_{t-1}  (tnrd_fused.hip)
-//   k_bwd_params   dK and dl partial sums per tile; exports z, a per pixel
-//   k_bwd_dw       dW partial sums from the exported z, a
-//   k_reduce_partials  fixed-order sums of the partials into the outputs
+//   k_fused_stage<.., MODE_BWD_INPUT>  g_{t-1} (tnrd_fused_tile.hpp); in FP32 it
+//                  also stores z and a of every pixel (za_index layout)
+//   k_bwd_params   dK and dl partial sums per tile, from the stored z, a (FP32),
+//                  or computing and storing them itself (BF16/FP16, and the first
+//                  stage when dl/du_0 is not asked for)
+//   k_bwd_dw       dW partial sums from the stored z, a
+//   k_reduce_partials  fixed-order sums of the partials into the outputs (one launch)
 //
-// k_bwd_params runs the filter-bank GEMM transposed (rows = 16 pixels,
-// columns = 16 filters), so its accumulator register r of lane (g, j) holds
-// pixel 4g + r and filter j.  That register is exactly the B operand of the
-// dK^T GEMM (rows = taps, k = pixels) for k-step r if k-row g of that step is
-// pixel 4g + r: v and phi'a go from the influence function straight into the
-// weight-gradient contraction without passing through LDS.
+// In k_bwd_params lane (g, j) holds, for register r, pixel 4g + r of a 16-pixel
+// block and filter j of a 16-filter block: that register is exactly the B
+// operand of the dK^T GEMM (rows = taps, k = pixels) for k-step r if k-row g
+// of that step is pixel 4g + r, so v and phi'a go from the influence function
+// straight into the weight-gradient contraction without passing through LDS.
+// When it computes z and a itself, the filter-bank GEMM runs transposed
+// (rows = 16 pixels, columns = 16 filters) to leave them in that layout.
 //
 // k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms with one lane per
-// filter (each lane owns its row, each wave its histogram), so no two lanes
-// ever update the same word and no atomics are needed (LDS float atomics run an
-// order of magnitude slower here than plain read-modify-writes).
+// filter (each lane owns its column, each wave its histogram), so no two lanes
+// ever update the same word and no atomics are needed.
+#include <limits.h>
 #include <math.h>
 
 #include <vector>
@@ -44,7 +48,6 @@ constexpr int BP_TH_MIN = 16;  // k_bwd_params tile height range (the workspace 
 constexpr int BP_TH_MAX = 64;  // for the smallest, i.e. the most tiles)
 constexpr int BP_NBW = 2;   // 16-pixel blocks per tile row (tile width 32)
 constexpr int BP_NW = 4;    // waves per workgroup
-constexpr int DW_NW = 8;    // k_bwd_dw waves per workgroup
 constexpr int DW_U = 16;    // k_bwd_dw pixels per wave step
 
 struct BwdParamsIO {
@@ -52,8 +55,7 @@ struct BwdParamsIO {
     const float *u_cur;   // u_t
     const float *f;
     const float *g_cur;   // dl/du_t
-    float *zexp;          // [N*H*W][Nk] z = K u_{t-1}
-    float *aexp;          // [N*H*W][Nk] a = K e
+    float *za;            // z = K u_{t-1} and a = K e per pixel (za_index layout)
     float *dk_part;       // [tiles][Nk*KK]
     float *dl_part;       // [tiles]
 };
@@ -70,7 +72,7 @@ __host__ __device__ inline BpLds bp_lds(int ks, int nmb, int th, int tw, int nrb
     l.tile_size = (th + 2 * R) * l.ldw;
     l.u_off = 0;
     l.e_off = l.tile_size;
-    l.t_pitch = nrbf + 4 * RBF_WIN + 1;
+    l.t_pitch = (nrbf + 4 * RBF_WIN + 1) | 1;  // odd: the rows of 16 filters start in distinct banks
     l.t_off = 2 * l.tile_size;
     l.red_off = l.t_off + 16 * nmb * l.t_pitch;
     l.red_size = 16 * nmb * ks * ks;
@@ -101,7 +103,7 @@ __device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__rest
     dphi = in ? rb.rho_over_step * E * fmaf(q, accd, -(d + (float)RBF_WIN) * acc) : 0.f;
 }
 
-template <int KS, int NMB, int NBW, int NW>
+template <int KS, int NMB, int NBW, int NW, bool LOADZA>
 __global__ void __launch_bounds__(64 * NW) k_bwd_params(
     BwdParamsIO io, int H, int W, int Th, int tiles_x, int tiles_per_img,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf, FusedRbf rb,
@@ -131,8 +133,9 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
     const float lam = lam_t[0];
     const float c1 = 1.f + 2.f * lam, c2 = 2.f * lam;
 
-    // ---- prologue: filters (via red), u_{t-1} and e tiles with an R ring, weight table
-    {
+    // ---- prologue: filters (via red; not needed when z and a are loaded),
+    // u_{t-1} and e tiles with an R ring, weight table
+    if (!LOADZA) {
         const int nf = Nk * KK;
         for (int base = 0; base < nf; base += 8 * THREADS) {
             float v[8];
@@ -209,7 +212,7 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
 #pragma unroll
         for (int s = 0; s < KS1; ++s) {
             int fi = 16 * nb + j, t = 4 * s + g;
-            bf[nb][s] = (fi < Nk && t < KK) ? red[fi * KK + t] : 0.f;
+            bf[nb][s] = (!LOADZA && fi < Nk && t < KK) ? red[fi * KK + t] : 0.f;
         }
     int off1[KS1];
 #pragma unroll
@@ -237,7 +240,80 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
 #pragma unroll
     for (int nb = 0; nb < NMB; ++nb) acc48[nb] = 0.f;
 
-    for (int y = wave; y < Th; y += NW) {
+    // dK^T GEMM of one filter block nb of a 16-pixel block: k-step r, k-row g =
+    // pixel 4 g + r; vz = v = phi(z), vh = phi'(z) a of those pixels
+    auto dk_block = [&](int y, int cb, int nb, const floatx4 &vz, const floatx4 &vh) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = 16 * cb + 4 * g + r;
+            const int b2 = (y + 2 * R) * L.ldw + x + 2 * R;
+#pragma unroll
+            for (int mt = 0; mt < MB2; ++mt) {
+                float ae = tapok[mt] ? se[b2 - offt[mt]] : 0.f;
+                float au = tapok[mt] ? su[b2 - offt[mt]] : 0.f;
+                dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, vz[r], dkt[mt][nb], 0, 0, 0);
+                dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(au, vh[r], dkt[mt][nb], 0, 0, 0);
+            }
+            if (G::VTAP) {
+                float ev = se[b2 - offv], uvv = su[b2 - offv];
+                acc48[nb] = fmaf(vz[r], ev, fmaf(vh[r], uvv, acc48[nb]));
+            }
+        }
+    };
+
+    if constexpr (LOADZA) {
+        // z and a exported by the input-gradient kernel, pixel 4 g + r of the
+        // block and filter 16 nb + j per lane; the next block's are loaded
+        // while this one is processed
+        const int ylim = min(Th, H - ty0);
+        const int nrows = ylim > wave ? (ylim - wave + NW - 1) / NW : 0;
+        const int nblk = nrows * NBW;
+        const float *zaimg = io.za + img * plane * za_stride(Nk);
+        float zn[NMB][4], an[NMB][4];
+        auto load = [&](int b) {
+            const int y = wave + NW * (b / NBW), cb = b % NBW;
+#pragma unroll
+            for (int nb = 0; nb < NMB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int xi = tx0 + 16 * cb + 4 * g + r, fi = 16 * nb + j;
+                    const bool ok = b < nblk && xi < W && fi < Nk;
+                    const size_t q = ok ? za_index((size_t)(ty0 + y) * W + xi, Nk, fi) : 0;
+                    const float zz = zaimg[q], aa = zaimg[q + 4];
+                    zn[nb][r] = ok ? zz : 0.f;
+                    an[nb][r] = ok ? aa : 0.f;
+                }
+        };
+        load(0);
+#pragma unroll 1
+        for (int b = 0; b < nblk; ++b) {
+            float zc[NMB][4], ac[NMB][4];
+#pragma unroll
+            for (int nb = 0; nb < NMB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    zc[nb][r] = zn[nb][r];
+                    ac[nb][r] = an[nb][r];
+                }
+            load(b + 1);
+            const int y = wave + NW * (b / NBW), cb = b % NBW;
+#pragma unroll
+            for (int nb = 0; nb < NMB; ++nb) {
+                const float *row = stab + (16 * nb + j) * L.t_pitch;
+                floatx4 vz, vh;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool valid = tx0 + 16 * cb + 4 * g + r < W;
+                    float ph, dph;
+                    rbf_phi_dphi_horner(zc[nb][r], row, rb, ph, dph);
+                    vz[r] = valid ? ph : 0.f;
+                    vh[r] = valid ? dph * ac[nb][r] : 0.f;
+                }
+                dk_block(y, cb, nb, vz, vh);
+            }
+        }
+    }
+    for (int y = wave; !LOADZA && y < Th; y += NW) {
         const int yi = ty0 + y;
         if (yi >= H) break;
 #pragma unroll 1
@@ -273,29 +349,13 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
                     rbf_phi_dphi_horner(z, row, rb, ph, dph);
                     if (valid && fi < Nk) {
                         size_t pix = img * plane + (size_t)yi * W + xi;
-                        io.zexp[pix * Nk + fi] = z;
-                        io.aexp[pix * Nk + fi] = a;
+                        io.za[za_index(pix, Nk, fi)] = z;
+                        io.za[za_index(pix, Nk, fi) + 4] = a;
                     }
                     accz[r] = valid ? ph : 0.f;
                     acca[r] = valid ? dph * a : 0.f;
                 }
-                // dK^T GEMM: k-step r, k-row g = pixel 4 g + r
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int x = 16 * cb + 4 * g + r;
-                    const int b2 = (y + 2 * R) * L.ldw + x + 2 * R;
-#pragma unroll
-                    for (int mt = 0; mt < MB2; ++mt) {
-                        float ae = tapok[mt] ? se[b2 - offt[mt]] : 0.f;
-                        float au = tapok[mt] ? su[b2 - offt[mt]] : 0.f;
-                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ae, accz[r], dkt[mt][nb], 0, 0, 0);
-                        dkt[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(au, acca[r], dkt[mt][nb], 0, 0, 0);
-                    }
-                    if (G::VTAP) {
-                        float ev = se[b2 - offv], uvv = su[b2 - offv];
-                        acc48[nb] = fmaf(accz[r], ev, fmaf(acca[r], uvv, acc48[nb]));
-                    }
-                }
+                dk_block(y, cb, nb, accz, acca);
             }
         }
     }
@@ -347,20 +407,28 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
     }
 }
 
-// dW partial sums: lane = filter, each wave its own histogram of
-// Nk rows x (Nrbf + 4W + 1) bins (bin b stored at b + 2W).
+// k_bwd_dw histograms are bin-major, [bin][64 lanes]: lane = filter, bin b of
+// filter i at word (b + 2W) * 64 + i.  Every lane of a wave owns a bank of its
+// own, so the 48 lanes of an update never conflict whatever bins their z
+// values fall in (a filter-major layout, [filter][bins], puts lanes whose
+// bins differ by a multiple of the bank count on one bank).  Updates are
+// plain read-modify-writes: the LDS float atomic add measured over ten times
+// slower for this pattern.
+__host__ __device__ inline int dw_bins(int nrbf) { return nrbf + 4 * RBF_WIN; }
+__host__ __device__ inline size_t dw_wave_bytes(int nrbf) { return (size_t)dw_bins(nrbf) * 64 * sizeof(float); }
+
+// dW partial sums: lane = filter, each wave its own histogram.
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
-    const float *__restrict__ zexp, const float *__restrict__ aexp, long long P, long long per_wg,
+    const float *__restrict__ za, long long P, long long per_wg,
     int Nk, int Nrbf, FusedRbf rb, float *__restrict__ dw_part)
 {
     extern __shared__ float lds[];
-    const int hb = Nrbf + 4 * RBF_WIN + 1;
-    const int hsize = Nk * hb;
+    const int hsize = dw_bins(Nrbf) * 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < NW * hsize; i += 64 * NW) lds[i] = 0.f;
     __syncthreads();
-    float *hist = lds + wave * hsize + lane * hb + 2 * RBF_WIN;
+    float *hist = lds + wave * hsize + 2 * RBF_WIN * 64 + lane;
     const long long p0 = (long long)blockIdx.x * per_wg;
     const long long p1 = min(P, p0 + per_wg);
     if (lane < Nk) {
@@ -373,8 +441,9 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
             for (int u = 0; u < U; ++u) {
                 const long long p = pb + (long long)u * NW;
                 const long long pc = p < p1 ? p : p0;
-                zn[u] = zexp[pc * Nk + lane];
-                an[u] = p < p1 ? aexp[pc * Nk + lane] : 0.f;
+                const size_t q = za_index((size_t)pc, Nk, lane);
+                zn[u] = za[q];
+                an[u] = p < p1 ? za[q + 4] : 0.f;
             }
         };
         load(p0 + wave);
@@ -398,15 +467,15 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
                 float E0 = __builtin_amdgcn_exp2f(-0.5f * rb.rho_log2e * d * d);
                 float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
                 float qi = __builtin_amdgcn_exp2f(-rb.rho_log2e * d);
-                float *hrow = hist + (int)jr;
+                float *hrow = hist + (int)jr * 64;
                 float up = a * E0, dn = a * E0;
                 hrow[0] += up * rb.c[RBF_WIN];
 #pragma unroll
                 for (int m = 1; m <= RBF_WIN; ++m) {
                     up *= q;
                     dn *= qi;
-                    hrow[m] += up * rb.c[RBF_WIN + m];
-                    hrow[-m] += dn * rb.c[RBF_WIN - m];
+                    hrow[64 * m] += up * rb.c[RBF_WIN + m];
+                    hrow[-64 * m] += dn * rb.c[RBF_WIN - m];
                 }
             }
         }
@@ -416,22 +485,40 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
     for (int i = tid; i < Nk * Nrbf; i += 64 * NW) {
         int fi = i / Nrbf, jj = i - fi * Nrbf;
         float sum = 0.f;
-        for (int w = 0; w < NW; ++w) sum += lds[w * hsize + fi * hb + 2 * RBF_WIN + jj];
+        for (int w = 0; w < NW; ++w) sum += lds[w * hsize + (jj + 2 * RBF_WIN) * 64 + fi];
         dst[i] = sum;
     }
 }
 
-// out[e] = scale * sum_k part[k * nelem + e].  A block owns 16 consecutive
-// elements; its 16 rows of threads sum interleaved subsets of k (row r takes
-// k = r, r + 16, ...) and the 16 row sums are then added in row order, so
-// the result does not depend on scheduling.
-constexpr int RED_E = 16, RED_R = 16;
-__global__ void __launch_bounds__(RED_E * RED_R) k_reduce_partials(
-    const float *__restrict__ part, int nparts, int nelem, float scale, float *__restrict__ out)
+// Fixed-order sums of partials, several outputs per launch:
+// out[e] = scale * sum_k part[k * nelem + e] for each job.  A block owns 16
+// consecutive elements of one job; its 16 rows of threads sum interleaved
+// subsets of k (row r takes k = r, r + 16, ...) and the 16 row sums are then
+// added in row order, so the result does not depend on scheduling.
+constexpr int RED_E = 16, RED_R = 16, RED_JOBS = 3;
+struct RedJob {
+    const float *part;
+    float *out;
+    int nparts, nelem;
+    float scale;
+    int block0;  // first block of this job
+};
+struct RedJobs {
+    RedJob j[RED_JOBS];
+    int n;
+};
+
+__global__ void __launch_bounds__(RED_E * RED_R) k_reduce_partials(RedJobs jobs)
 {
     __shared__ float rows[RED_R][RED_E];
+    int q = 0;
+    for (int k = 1; k < jobs.n; ++k)
+        if ((int)blockIdx.x >= jobs.j[k].block0) q = k;
+    const RedJob jb = jobs.j[q];
     const int te = threadIdx.x % RED_E, tr = threadIdx.x / RED_E;
-    const int e = blockIdx.x * RED_E + te;
+    const int e = ((int)blockIdx.x - jb.block0) * RED_E + te;
+    const float *part = jb.part;
+    const int nparts = jb.nparts, nelem = jb.nelem;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     if (e < nelem) {
         int k = tr;
@@ -448,7 +535,7 @@ __global__ void __launch_bounds__(RED_E * RED_R) k_reduce_partials(
     if (tr == 0 && e < nelem) {
         float s = 0.f;
         for (int r = 0; r < RED_R; ++r) s += rows[r][te];
-        out[e] = scale * s;
+        jb.out[e] = jb.scale * s;
     }
 }
 
@@ -514,7 +601,7 @@ constexpr size_t AL = 256;
 size_t al(size_t x) { return (x + AL - 1) / AL * AL; }
 
 struct BwdWs {
-    float *g[2], *zexp, *aexp, *dk_part, *dl_part, *dw_part, *seg;
+    float *g[2], *za, *dk_part, *dl_part, *dw_part, *seg;
     size_t bytes;
 };
 
@@ -531,8 +618,7 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s)
     };
     w.g[0] = take(gm.img);
     w.g[1] = take(gm.img);
-    w.zexp = take(gm.img * m->Nk);
-    w.aexp = take(gm.img * m->Nk);
+    w.za = take(gm.img * za_stride(m->Nk));
     w.dk_part = take((size_t)gm.tiles * m->Nk * kk);
     w.dl_part = take((size_t)gm.tiles);
     w.dw_part = take((size_t)gm.dw_grid * m->Nk * m->Nrbf);
@@ -541,7 +627,7 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s)
     return w;
 }
 
-template <int KS, int NMB>
+template <int KS, int NMB, bool LOADZA>
 hipError_t launch_bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, int W, const float *filt,
                              int Nk, const float *rbfw, const RbfGrid &grid, const float *lam,
                              hipStream_t stream)
@@ -550,55 +636,86 @@ hipError_t launch_bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, in
     size_t lds_bytes = (size_t)L.total * sizeof(float);
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW>,
+        (void)hipFuncSetAttribute((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         (void)hipGetLastError();
         attr_set = true;
     }
     const int per_img = gm.tiles_x * gm.tiles_y;
     FusedRbf rb = make_fused_rbf(grid);
-    hipLaunchKernelGGL((k_bwd_params<KS, NMB, BP_NBW, BP_NW>), dim3(gm.tiles), dim3(64 * BP_NW),
+    hipLaunchKernelGGL((k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA>), dim3(gm.tiles), dim3(64 * BP_NW),
                        lds_bytes, stream, io, H, W, gm.th, gm.tiles_x, per_img, filt, Nk, rbfw,
                        grid.nrbf, rb, lam);
     return hipGetLastError();
 }
 
-hipError_t bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, int W, int ks, const float *filt,
-                      int Nk, const float *rbfw, const RbfGrid &grid, const float *lam,
-                      hipStream_t stream)
+template <int KS, int NMB>
+hipError_t launch_bwd_params_mode(bool loadza, const BwdParamsIO &io, const BwdGeom &gm, int H, int W,
+                                  const float *filt, int Nk, const float *rbfw, const RbfGrid &grid,
+                                  const float *lam, hipStream_t stream)
+{
+    return loadza ? launch_bwd_params<KS, NMB, true>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
+                  : launch_bwd_params<KS, NMB, false>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+}
+
+// Parameter-gradient partials of one stage.  loadza: z = K u and a = K e come
+// from the input-gradient kernel's export (FP32 path); otherwise they are
+// computed here and exported for k_bwd_dw.
+hipError_t bwd_params(bool loadza, const BwdParamsIO &io, const BwdGeom &gm, int H, int W, int ks,
+                      const float *filt, int Nk, const float *rbfw, const RbfGrid &grid,
+                      const float *lam, hipStream_t stream)
 {
     const int nmb = (Nk + 15) / 16;
     if (ks == 7)
-        return nmb <= 2 ? launch_bwd_params<7, 2>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
-                        : launch_bwd_params<7, 3>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+        return nmb <= 2 ? launch_bwd_params_mode<7, 2>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params_mode<7, 3>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     if (ks == 5)
-        return nmb <= 2 ? launch_bwd_params<5, 2>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
-                        : launch_bwd_params<5, 3>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+        return nmb <= 2 ? launch_bwd_params_mode<5, 2>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params_mode<5, 3>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     return hipErrorInvalidValue;
 }
 
-hipError_t bwd_dw(const float *zexp, const float *aexp, const BwdGeom &gm, int Nk,
-                  const RbfGrid &grid, float *dw_part, hipStream_t stream)
+template <int NW>
+hipError_t launch_bwd_dw(const float *za, const BwdGeom &gm, int Nk,
+                         const RbfGrid &grid, float *dw_part, hipStream_t stream)
 {
-    const size_t lds_bytes = (size_t)DW_NW * Nk * (grid.nrbf + 4 * RBF_WIN + 1) * sizeof(float);
+    const size_t lds_bytes = NW * dw_wave_bytes(grid.nrbf);
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_bwd_dw<DW_NW>,
+        (void)hipFuncSetAttribute((const void *)k_bwd_dw<NW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         (void)hipGetLastError();
         attr_set = true;
     }
     FusedRbf rb = make_fused_rbf(grid);
-    hipLaunchKernelGGL((k_bwd_dw<DW_NW>), dim3(gm.dw_grid), dim3(64 * DW_NW), lds_bytes, stream,
-                       zexp, aexp, (long long)gm.img, gm.dw_per_wg, Nk, grid.nrbf, rb, dw_part);
+    hipLaunchKernelGGL((k_bwd_dw<NW>), dim3(gm.dw_grid), dim3(64 * NW), lds_bytes, stream,
+                       za, (long long)gm.img, gm.dw_per_wg, Nk, grid.nrbf, rb, dw_part);
     return hipGetLastError();
 }
 
-hipError_t reduce_partials(const float *part, int nparts, int nelem, float scale, float *out,
-                           hipStream_t stream)
+// As many waves (histograms) per workgroup as fit the LDS: 7 for 63 RBFs.
+hipError_t bwd_dw(const float *za, const BwdGeom &gm, int Nk,
+                  const RbfGrid &grid, float *dw_part, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_reduce_partials, dim3((nelem + RED_E - 1) / RED_E), dim3(RED_E * RED_R), 0,
-                       stream, part, nparts, nelem, scale, out);
+    const size_t per_wave = dw_wave_bytes(grid.nrbf), cap = 160 * 1024;
+    if (7 * per_wave <= cap) return launch_bwd_dw<7>(za, gm, Nk, grid, dw_part, stream);
+    if (4 * per_wave <= cap) return launch_bwd_dw<4>(za, gm, Nk, grid, dw_part, stream);
+    if (2 * per_wave <= cap) return launch_bwd_dw<2>(za, gm, Nk, grid, dw_part, stream);
+    return launch_bwd_dw<1>(za, gm, Nk, grid, dw_part, stream);
+}
+
+// One launch for the (up to RED_JOBS) reductions of a stage.
+hipError_t reduce_partials(const RedJob *jobs, int n, hipStream_t stream)
+{
+    RedJobs J;
+    J.n = n;
+    int blocks = 0;
+    for (int k = 0; k < n; ++k) {
+        J.j[k] = jobs[k];
+        J.j[k].block0 = blocks;
+        blocks += (jobs[k].nelem + RED_E - 1) / RED_E;
+    }
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(RED_E * RED_R), 0, stream, J);
     return hipGetLastError();
 }
 
@@ -606,8 +723,8 @@ bool bwd_lds_ok(const tnrd_model *m)
 {
     const int nmb = (m->Nk + 15) / 16 <= 2 ? 2 : 3;
     BpLds L = bp_lds(m->ksize, nmb, BP_TH_MAX, 16 * BP_NBW, m->Nrbf, BP_NW);
-    size_t dw = (size_t)DW_NW * m->Nk * (m->Nrbf + 4 * RBF_WIN + 1) * sizeof(float);
-    return (size_t)L.total * sizeof(float) <= 160 * 1024 && dw <= 160 * 1024;
+    return (size_t)L.total * sizeof(float) <= 160 * 1024 && dw_wave_bytes(m->Nrbf) <= 160 * 1024 &&
+           m->Nk <= 64;
 }
 
 }  // namespace
@@ -711,22 +828,16 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             io.u_cur = ut[t];
             io.f = f;
             io.g_cur = g_cur;
-            io.zexp = w.zexp;
-            io.aexp = w.aexp;
+            io.za = w.za;
             io.dk_part = w.dk_part;
             io.dl_part = w.dl_part;
-            if (bwd_params(io, gm, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) != hipSuccess)
-                return TNRD_ERR_HIP;
-            if (bwd_dw(w.zexp, w.aexp, gm, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
-                return TNRD_ERR_HIP;
-            if (reduce_partials(w.dk_part, gm.tiles, (int)(m->Nk * kk), -1.f,
-                                grad_filters + (size_t)ts * m->Nk * kk, stream) != hipSuccess ||
-                reduce_partials(w.dw_part, gm.dw_grid, m->Nk * m->Nrbf, -1.f,
-                                grad_rbf_w + (size_t)ts * m->Nk * m->Nrbf, stream) != hipSuccess ||
-                reduce_partials(w.dl_part, gm.tiles, 1, 1.f, grad_lambda + ts, stream) != hipSuccess)
-                return TNRD_ERR_HIP;
-            if (t > 1 || grad_u0) {
-                float *g_next = (t == 1) ? grad_u0 : w.g[ping];
+            // The input-gradient kernel (FP32) computes z = K u and a = K e at
+            // every pixel anyway and exports them, so it runs first and the
+            // parameter-gradient kernels load them instead of recomputing.
+            const bool need_g = t > 1 || grad_u0;
+            const bool loadza = need_g && oo.prec == TNRD_PREC_FP32 && (long long)H * W <= INT_MAX;
+            float *g_next = (t == 1) ? grad_u0 : w.g[ping];
+            if (need_g) {
                 ia.u_prev = ut[t - 1];
                 ia.u_cur = ut[t];
                 ia.g_cur = g_cur;
@@ -734,7 +845,20 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
                 ia.filt = filt;
                 ia.rbfw = rbfw;
                 ia.lam = lam;
+                ia.za = loadza ? w.za : nullptr;
                 if (fused_stage_input_grad(ia, stream) != hipSuccess) return TNRD_ERR_HIP;
+            }
+            if (bwd_params(loadza, io, gm, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) !=
+                hipSuccess)
+                return TNRD_ERR_HIP;
+            if (bwd_dw(w.za, gm, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
+                return TNRD_ERR_HIP;
+            const RedJob jobs[RED_JOBS] = {
+                {w.dk_part, grad_filters + (size_t)ts * m->Nk * kk, gm.tiles, (int)(m->Nk * kk), -1.f, 0},
+                {w.dw_part, grad_rbf_w + (size_t)ts * m->Nk * m->Nrbf, gm.dw_grid, m->Nk * m->Nrbf, -1.f, 0},
+                {w.dl_part, grad_lambda + ts, gm.tiles, 1, 1.f, 0}};
+            if (reduce_partials(jobs, RED_JOBS, stream) != hipSuccess) return TNRD_ERR_HIP;
+            if (need_g) {
                 g_cur = g_next;
                 ping ^= 1;
             }

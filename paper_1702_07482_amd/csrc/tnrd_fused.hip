@@ -116,8 +116,10 @@ struct TilePlan {
 // footprint), so a launch of n tiles runs in ceil(n / CUs) rounds, each as
 // long as one tile.  A tile's (Th + 2R) E rows go to its waves in rounds, so a
 // wave runs ceil((Th + 2R) / waves) rows of nb 16-pixel blocks, plus a fixed
-// cost (prologue, output passes) worth about 2 such blocks.  Tile widths are those whose
-// E rows fill their blocks exactly (16 nb - 2R).
+// cost (prologue, output passes) worth about 2 such blocks.  Among tiles of
+// equal modelled time the one with the fewest E rows wins (its output passes
+// and prologue are the shortest), then the one with fewer tiles.  Tile widths
+// are those whose E rows fill their blocks exactly (16 nb - 2R).
 static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req_h, int req_w,
                           int waves, int mode, bool poly)
 {
@@ -158,7 +160,7 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
             // of the polynomial form
             const int erows = (t < H ? t : H) + 2 * R;
             const double blk = (rbfm == RBF_HORNER ? 1.3 : 1.0) * ((erows + p.nw - 1) / p.nw) * nb;
-            const double cost = (double)rounds * (blk + 2) + 1e-6 * (double)tiles * erows * nb;  // ties: fewer blocks
+            const double cost = (double)rounds * (blk + 2) + 1e-4 * erows * nb + 1e-9 * (double)tiles;
             if (!p.ok || cost < best) {
                 best = cost;
                 p.th = t;

@@ -93,7 +93,18 @@ struct FusedIO {
     float *out;           // forward: u_t;  input gradient: g_{t-1}
     const float *u_cur;   // input gradient: u_t
     const float *g_cur;   // input gradient: g_t = dl/du_t
+    float *za;            // input gradient, optional: z = K u and a = K e at the tile's own
+                          // pixels, layout of za_index()
 };
+
+// Export of z = K u and a = K e for the parameter-gradient kernels: per pixel
+// 8 ceil(Nk / 4) floats, filters in quads, each quad's four z followed by its
+// four a, so a lane holding four consecutive filters writes two 16-byte words.
+__host__ __device__ inline int za_stride(int nk) { return 8 * ((nk + 3) / 4); }
+__host__ __device__ inline size_t za_index(size_t pix, int nk, int f)  // z; a at + 4
+{
+    return pix * za_stride(nk) + 8 * (f >> 2) + (f & 3);
+}
 
 enum FusedMode { MODE_FWD = 0, MODE_BWD_INPUT = 1 };
 

@@ -63,6 +63,8 @@ struct FusedLds {
     int t_off, t_pitch, t_size;  // influence table (Gaussian form: weight rows of t_pitch floats;
                                  // polynomial form: [filter][2][intervals][4] coefficients)
     int ni;                      // polynomial form: intervals per filter
+    int tf_pitch;                // polynomial form: floats per filter (8 ni, padded to 4 mod 16 so
+                                 // that the 4 filters a wave's lane groups read start in distinct banks)
     int w_pitch;                 // polynomial form: padded weight row staged in the P area
     int p_off, pw, ring, p_size; // row partials: ring of `ring` E rows x KS tap rows x pw
     int red_off;                 // 8 floats for workgroup reductions
@@ -85,8 +87,9 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     l.t_off = l.e_off + (mode == MODE_BWD_INPUT ? l.u_size : 0);
     l.t_pitch = nrbf + 4 * RBF_WIN + 1;
     l.ni = poly_intervals(nrbf);
+    l.tf_pitch = POLY_NC * l.ni + ((4 - POLY_NC * l.ni % 16) + 16) % 16;
     l.w_pitch = nrbf + 2 * POLY_PAD;
-    l.t_size = rbfm == RBF_POLY ? 16 * nmb * POLY_NC * l.ni : ((16 * nmb * l.t_pitch + 3) & ~3);
+    l.t_size = rbfm == RBF_POLY ? 16 * nmb * l.tf_pitch : ((16 * nmb * l.t_pitch + 3) & ~3);
     l.p_off = l.t_off + l.t_size;
     l.pw = 16 * nb + 2 * R;
     l.ring = fused_ring(ks, nw);
@@ -338,7 +341,7 @@ __device__ __forceinline__ void fused_tile(
                     for (int k = 0; k < POLY_NC; ++k) c[k] = fmaf(pm[k][m], ((k & 1) == par) ? sum : dif, c[k]);
                 }
             }
-            float *dst = stab + fi * (POLY_NC * ni) + 4 * q;
+            float *dst = stab + fi * L.tf_pitch + 4 * q;
             *reinterpret_cast<floatx4 *>(dst) = floatx4{c[0], c[1], c[2], c[3]};
             *reinterpret_cast<floatx4 *>(dst + 4 * ni) = floatx4{c[4], c[5], c[6], c[7]};
         }
@@ -365,7 +368,7 @@ __device__ __forceinline__ void fused_tile(
 
     const float lam = lam_t[0];
     // per-lane part of the polynomial table address: filter 16 mb + 4 g + r
-    const int tab_g = 4 * g * POLY_NC * L.ni;
+    const int tab_g = 4 * g * L.tf_pitch;
 
     // GEMM1 of block (E row e, 16-pixel block cb): z = K u (and a = K e in
     // input-gradient mode).  The B operands are read first (gemm1_load), the
@@ -430,7 +433,7 @@ __device__ __forceinline__ void fused_tile(
             const float jr = rintf(s);
             dq[slot][r] = s - jr;
             const int q = (int)__builtin_amdgcn_fmed3f(jr + (float)(RBF_WIN + 1), 0.f, (float)(L.ni - 1));
-            const float *cp = stab + (16 * mb + r) * (POLY_NC * L.ni) + tab_g + 4 * q;
+            const float *cp = stab + (16 * mb + r) * L.tf_pitch + tab_g + 4 * q;
             lo[slot][r] = *reinterpret_cast<const floatx4 *>(cp);
             hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * L.ni);
         }
@@ -515,6 +518,18 @@ __device__ __forceinline__ void fused_tile(
         const int c = 16 * cb + j;
         const int xi = tx0 - R + c;
         const bool valid = (c < Ew) && (xi >= 0) && (xi < W);
+        // input-gradient mode with export: z and a of this lane's pixel if it is
+        // one of the tile's own (every image pixel is own to exactly one tile),
+        // stored before anything else of the block, when the fewest registers are live
+        if (BWD && io.za && c >= R && c < R + Tw && xi < W && e >= R && e < R + Th && ty0 - R + e < H) {
+            float *q = io.za + za_index((size_t)(ty0 - R + e) * W + xi, Nk, 4 * g);
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+                if (16 * mb + 4 * g < Nk) {
+                    *reinterpret_cast<floatx4 *>(q + 8 * 4 * mb) = c1[mb];
+                    *reinterpret_cast<floatx4 *>(q + 8 * 4 * mb + 4) = ca[mb];
+                }
+        }
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) {
             n1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -701,6 +716,7 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     ii.out = io.out + img * plane;
     ii.u_cur = io.u_cur ? io.u_cur + img * plane : nullptr;
     ii.g_cur = io.g_cur ? io.g_cur + img * plane : nullptr;
+    ii.za = io.za ? io.za + img * plane * za_stride(Nk) : nullptr;
     fused_tile<KS, NMB, NB, NW, MODE, PREC, RBFM>(ii, H, W, Th, Tw, ty * Th, tx * Tw, filt, Nk, rbfw,
                                                   Nrbf, rb, lam_t, lds);
 }
@@ -727,6 +743,7 @@ __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
     io.out = to_out ? im.u_out : im.u_tmp;
     io.u_cur = nullptr;
     io.g_cur = nullptr;
+    io.za = nullptr;
     const BatchModel md = a.models[im.model];
     fused_tile<KS, NMB, NB, NW, MODE_FWD, PREC_F32, RBFM>(
         io, im.H, im.W, a.Th, a.Tw, ty * a.Th, tx * a.Tw, md.filt + (size_t)t * a.Nk * KK, a.Nk,
@@ -755,6 +772,7 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     io.out = s.u_next;
     io.u_cur = s.u_cur;
     io.g_cur = s.g_cur;
+    io.za = MODE == MODE_BWD_INPUT && PREC == PREC_F32 ? s.za : nullptr;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     dim3 grid(tiles * s.N);

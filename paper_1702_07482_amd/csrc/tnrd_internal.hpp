@@ -28,6 +28,8 @@ struct StageArgs {
     int tile_h, tile_w;   // 0 = automatic
     int waves;            // fused: waves per workgroup (4 or 8; 0 = automatic)
     int poly;             // fused kernel: the polynomial influence form may be used
+    float *za = nullptr;  // input-gradient mode, FP32: if set, z = K u and a = K e at every
+                          // pixel (za_index layout), the parameter-gradient kernels' input
 };
 
 // Batched forward (device descriptors, filled on the host).

@@ -50,6 +50,12 @@ class TnrdOpts(ctypes.Structure):
     ]
 
 
+class TnrdPeaks(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "copy_gbs", "mfma_f32_tflops", "mfma_bf16_k16_tflops", "mfma_bf16_k32_tflops",
+        "valu_f32_tflops", "exp_per_s")]
+
+
 class TnrdImage(ctypes.Structure):
     _fields_ = [
         ("f", ctypes.c_void_p), ("u_out", ctypes.c_void_p),
@@ -77,6 +83,8 @@ SIGNATURES = [
     ("tnrd_forward_batched", _I, [_I, ctypes.POINTER(TnrdImage), _I, ctypes.POINTER(TnrdModel),
                                   ctypes.POINTER(TnrdOpts), _P, _SZ, _P]),
     ("tnrd_status_str", ctypes.c_char_p, [_I]),
+    ("tnrd_peaks_sink_floats", _SZ, []),
+    ("tnrd_measure_peaks", _I, [_P, _P, _SZ, _P, ctypes.POINTER(TnrdPeaks), _P]),
 ]
 
 
@@ -157,6 +165,18 @@ def tnrd_batched_workspace_bytes(B, imgs, n_models, models, opts: TnrdOpts) -> i
 def tnrd_forward_batched(B, imgs, n_models, models, opts: TnrdOpts, ws, ws_bytes, stream=None) -> int:
     return int(load().tnrd_forward_batched(B, imgs, n_models, models, ctypes.byref(opts),
                                            _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def tnrd_peaks_sink_floats() -> int:
+    return int(load().tnrd_peaks_sink_floats())
+
+
+def tnrd_measure_peaks(copy_src, copy_dst, copy_bytes, sink, stream=None) -> dict:
+    """Measured throughput of the units the kernels run on (a measurement aid)."""
+    out = TnrdPeaks()
+    _check(load().tnrd_measure_peaks(_ptr(copy_src), _ptr(copy_dst), copy_bytes, _ptr(sink),
+                                     ctypes.byref(out), _stream(stream)), "tnrd_measure_peaks")
+    return {n: getattr(out, n) for n, _ in TnrdPeaks._fields_}
 
 
 # ------------------------------------------------------------------ conveniences
