@@ -54,10 +54,24 @@ def _load():
         lib.oracle_prox.argtypes = [d, d, d]
         lib.oracle_prox.restype = d
         lib.oracle_prox_grad.argtypes = [d, d, d, _D, _D]
+        lib.oracle_prox_df.argtypes = [d, d, d]
+        lib.oracle_prox_df.restype = d
+        lib.oracle_psi.argtypes = [d, d, d]
+        lib.oracle_psi.restype = d
+        lib.oracle_psi_du.argtypes = [d, d, d]
+        lib.oracle_psi_du.restype = d
+        lib.oracle_psi_dlam.argtypes = [d, d]
+        lib.oracle_psi_dlam.restype = d
+        lib.oracle_psi_df.argtypes = [d, d, d]
+        lib.oracle_psi_df.restype = d
         lib.oracle_forward.argtypes = [_D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D,
                                        _D, _D, _D, i]
+        lib.oracle_forward_ex.argtypes = [_D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D, i, d,
+                                          _D, _D, _D, i]
         lib.oracle_backward.argtypes = [_D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D,
                                         _D, _D, _D, _D, _D, _D, i]
+        lib.oracle_backward_ex.argtypes = [_D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D, i, d,
+                                           _D, _D, _D, _D, _D, _D, _D, i]
         _lib = lib
     return _lib
 
@@ -138,6 +152,37 @@ def prox_grad(ut: float, f: float, lam: float):
     return y.value, xl.value
 
 
+def psi(u, f, lam: float) -> np.ndarray:
+    """Reaction (lambda/u)(1 - f^2/u^2) of the projected variant, elementwise."""
+    lib = _load()
+    u = np.asarray(u, dtype=np.float64)
+    f = np.broadcast_to(np.asarray(f, dtype=np.float64), u.shape)
+    out = np.array([lib.oracle_psi(float(a), float(b), float(lam)) for a, b in zip(u.ravel(), f.ravel())])
+    return out.reshape(u.shape)
+
+
+def psi_partials(u: float, f: float, lam: float):
+    """(d psi/du, d psi/dlambda, d psi/df) at one point."""
+    lib = _load()
+    return (lib.oracle_psi_du(float(u), float(f), float(lam)),
+            lib.oracle_psi_dlam(float(u), float(f)),
+            lib.oracle_psi_df(float(u), float(f), float(lam)))
+
+
+def prox_df(ut: float, f: float, lam: float) -> float:
+    """d prox / d f at fixed ut."""
+    return float(_load().oracle_prox_df(float(ut), float(f), float(lam)))
+
+
+REACTIONS = {"prox": 0, "projected": 1}
+
+
+def _reaction(model):
+    """(reaction code, projection threshold c) of a model dict: reaction
+    "prox" (default, eq. diffusionprocessfinal) or "projected" (eq. diffusion_backP)."""
+    return REACTIONS[model.get("reaction", "prox")], float(model.get("proj_c", 1.0))
+
+
 def _model_args(m):
     filters = _f64(m["filters"])
     rbf_w = _f64(m["rbf_w"])
@@ -162,10 +207,11 @@ def forward(f, model, want_states: bool = False, want_utilde: bool = False,
     uT = np.empty_like(f)
     states = np.empty((T + 1, N, H, W)) if want_states else None
     utilde = np.empty((T, N, H, W)) if want_utilde else None
-    _load().oracle_forward(_p(f), N, H, W, T, Nk, ks, Nrbf,
-                           float(model["mu0"]), float(model["step"]), float(model["sigma"]),
-                           _p(filters), _p(rbf_w), _p(lam), _p(uT), _p(states), _p(utilde),
-                           int(nthreads))
+    react, cproj = _reaction(model)
+    _load().oracle_forward_ex(_p(f), N, H, W, T, Nk, ks, Nrbf,
+                              float(model["mu0"]), float(model["step"]), float(model["sigma"]),
+                              _p(filters), _p(rbf_w), _p(lam), react, cproj,
+                              _p(uT), _p(states), _p(utilde), int(nthreads))
     out = [uT[0] if squeeze else uT]
     if want_states:
         out.append(states[:, 0] if squeeze else states)
@@ -174,9 +220,10 @@ def forward(f, model, want_states: bool = False, want_utilde: bool = False,
     return out[0] if len(out) == 1 else tuple(out)
 
 
-def backward(f, model, states, gT, nthreads: int = 0):
+def backward(f, model, states, gT, nthreads: int = 0, want_df: bool = False):
     """Gradients (dK, dW, dlam, g0) of a loss with dl/du_T = gT, given the
-    forward states u_0..u_T.  Sums over images."""
+    forward states u_0..u_T.  Sums over images.  With want_df, also dl/df in
+    full (g0 plus the explicit f-dependence of every stage)."""
     f = _f64(f)
     squeeze = f.ndim == 2
     if squeeze:
@@ -191,8 +238,13 @@ def backward(f, model, states, gT, nthreads: int = 0):
     dW = np.empty_like(rbf_w)
     dlam = np.empty_like(lam)
     g0 = np.empty_like(f)
-    _load().oracle_backward(_p(f), N, H, W, T, Nk, ks, Nrbf,
-                            float(model["mu0"]), float(model["step"]), float(model["sigma"]),
-                            _p(filters), _p(rbf_w), _p(lam), _p(states), _p(gT),
-                            _p(dK), _p(dW), _p(dlam), _p(g0), int(nthreads))
-    return dK, dW, dlam, (g0[0] if squeeze else g0)
+    gf = np.empty_like(f) if want_df else None
+    react, cproj = _reaction(model)
+    _load().oracle_backward_ex(_p(f), N, H, W, T, Nk, ks, Nrbf,
+                               float(model["mu0"]), float(model["step"]), float(model["sigma"]),
+                               _p(filters), _p(rbf_w), _p(lam), react, cproj, _p(states), _p(gT),
+                               _p(dK), _p(dW), _p(dlam), _p(g0), _p(gf), int(nthreads))
+    out = (dK, dW, dlam, (g0[0] if squeeze else g0))
+    if want_df:
+        out = out + ((gf[0] if squeeze else gf),)
+    return out

@@ -20,6 +20,10 @@
  *
  *   gradients (Sec. 3.2, eqs. derv1, derv1-1, derv2, derv4): see oracle_backward.
  *
+ *   projected variant (Sec. 3.1, eq. diffusion_backP), the paper's comparison model:
+ *     ut  = u_{t-1} - ( x + (l / u_{t-1}) (1 - f^2 / u_{t-1}^2) )
+ *     u_t = max(ut, c)
+ *
  * Readings of points the paper leaves open (listed with reasons in the design notes):
  *   - u_0 = f (the paper leaves the initial state I_0 open);
  *   - K_i is a true convolution: the kernel is flipped (the paper defines k*u as
@@ -197,6 +201,38 @@ void oracle_prox_grad(double ut, double f, double lam, double *y, double *xl)
     *xl = (2.0 * f * f + 8.0 * lam * f * f) / (c * s) - (ut + s) / (c * c);
 }
 
+/* Full derivative of the prox output with respect to f (f enters only
+ * through s): du/df = 4 lambda f / s, s = sqrt(ut^2 + 8(1+2l) l f^2). */
+double oracle_prox_df(double ut, double f, double lam)
+{
+    double c = 1.0 + 2.0 * lam;
+    double s = sqrt(ut * ut + 8.0 * c * lam * f * f);
+    if (s == 0.0) return 0.0;
+    return 4.0 * lam * f / s;
+}
+
+/* Reaction of the projected variant (eq. diffusion_backP), exactly as printed:
+ * psi(u) = (lambda / u) (1 - f^2 / u^2). */
+double oracle_psi(double u, double f, double lam)
+{
+    return lam / u * (1.0 - f * f / (u * u));
+}
+
+/* Its partial derivatives: d psi / du = lambda (3 f^2 / u^4 - 1 / u^2),
+ * d psi / d lambda = (1 / u) (1 - f^2 / u^2), d psi / df = -2 lambda f / u^3. */
+double oracle_psi_du(double u, double f, double lam)
+{
+    return lam * (3.0 * f * f / (u * u * u * u) - 1.0 / (u * u));
+}
+double oracle_psi_dlam(double u, double f)
+{
+    return (1.0 / u) * (1.0 - f * f / (u * u));
+}
+double oracle_psi_df(double u, double f, double lam)
+{
+    return -2.0 * lam * f / (u * u * u);
+}
+
 /* Pointer helpers for the parameter layout
  *   filters [T][Nk][ks][ks], rbf_w [T][Nk][Nrbf], lambda [T]. */
 static const double *filt(const double *filters, int t, int i, int Nk, int ks)
@@ -208,11 +244,15 @@ static const double *rbfw(const double *w, int t, int i, int Nk, int Nrbf)
     return w + ((size_t)t * Nk + i) * Nrbf;
 }
 
+/* Reaction of a stage: 0 = proximal step of eq. diffusionprocessfinal,
+ * 1 = gradient step and projection max(., c) of eq. diffusion_backP. */
+enum { REACT_PROX = 0, REACT_PROJECTED = 1 };
+
 /* One stage on one image: computes ut (length H*W) and u_next from u_prev. */
 static void stage_forward(const double *u_prev, const double *f, int H, int W, int t,
                           int Nk, int ks, int Nrbf, double mu0, double step, double sigma,
                           const double *filters, const double *rbf_w, const double *lam,
-                          double *ut, double *u_next)
+                          int reaction, double cproj, double *ut, double *u_next)
 {
     size_t n = (size_t)H * W;
     double *z = (double *)malloc(sizeof(double) * n);
@@ -230,8 +270,13 @@ static void stage_forward(const double *u_prev, const double *f, int H, int W, i
         for (size_t p = 0; p < n; ++p) x[p] += xi[p];
     }
     for (size_t p = 0; p < n; ++p) {
-        ut[p] = u_prev[p] - x[p];
-        u_next[p] = oracle_prox(ut[p], f[p], lam[t]);
+        if (reaction == REACT_PROJECTED) {
+            ut[p] = u_prev[p] - (x[p] + oracle_psi(u_prev[p], f[p], lam[t]));
+            u_next[p] = ut[p] > cproj ? ut[p] : cproj;
+        } else {
+            ut[p] = u_prev[p] - x[p];
+            u_next[p] = oracle_prox(ut[p], f[p], lam[t]);
+        }
     }
     free(z); free(v); free(xi); free(x);
 }
@@ -241,10 +286,11 @@ static void stage_forward(const double *u_prev, const double *f, int H, int W, i
  *   states  [T+1][N][H][W] or NULL  u_0 .. u_T
  *   utilde  [T][N][H][W] or NULL    ut_1 .. ut_T (pre-prox values)
  */
-void oracle_forward(const double *f, int N, int H, int W, int T, int Nk, int ks, int Nrbf,
-                    double mu0, double step, double sigma,
-                    const double *filters, const double *rbf_w, const double *lam,
-                    double *uT, double *states, double *utilde, int nthreads)
+void oracle_forward_ex(const double *f, int N, int H, int W, int T, int Nk, int ks, int Nrbf,
+                       double mu0, double step, double sigma,
+                       const double *filters, const double *rbf_w, const double *lam,
+                       int reaction, double cproj,
+                       double *uT, double *states, double *utilde, int nthreads)
 {
     set_threads(nthreads);
     size_t n = (size_t)H * W;
@@ -257,7 +303,7 @@ void oracle_forward(const double *f, int N, int H, int W, int T, int Nk, int ks,
         if (states) memcpy(states + (size_t)img * n, ua, sizeof(double) * n);
         for (int t = 0; t < T; ++t) {
             stage_forward(ua, fi, H, W, t, Nk, ks, Nrbf, mu0, step, sigma,
-                          filters, rbf_w, lam, ut, ub);
+                          filters, rbf_w, lam, reaction, cproj, ut, ub);
             if (states) memcpy(states + ((size_t)(t + 1) * N + img) * n, ub, sizeof(double) * n);
             if (utilde) memcpy(utilde + ((size_t)t * N + img) * n, ut, sizeof(double) * n);
             double *tmp = ua; ua = ub; ub = tmp;
@@ -267,6 +313,16 @@ void oracle_forward(const double *f, int N, int H, int W, int T, int Nk, int ks,
     free(ua); free(ub); free(ut);
 }
 
+/* The proximal model (eq. diffusionprocessfinal). */
+void oracle_forward(const double *f, int N, int H, int W, int T, int Nk, int ks, int Nrbf,
+                    double mu0, double step, double sigma,
+                    const double *filters, const double *rbf_w, const double *lam,
+                    double *uT, double *states, double *utilde, int nthreads)
+{
+    oracle_forward_ex(f, N, H, W, T, Nk, ks, Nrbf, mu0, step, sigma, filters, rbf_w, lam,
+                      REACT_PROX, 0.0, uT, states, utilde, nthreads);
+}
+
 /* Backward pass (Sec. 3.2).  Given gT = dl/du_T and the forward states
  * u_0..u_T ([T+1][N][H][W]), accumulates over all images:
  *   dK   [T][Nk][ks][ks]  dl/dk_i^t
@@ -274,6 +330,9 @@ void oracle_forward(const double *f, int N, int H, int W, int T, int Nk, int ks,
  *   dlam [T]              dl/dlambda^t
  *   g0   [N][H][W] or NULL  dl/du_0 (through the diffusion chain only; u_0 = f
  *                           also enters the prox, which is not included here)
+ *   gf   [N][H][W] or NULL  dl/df in full: g0 plus, at every stage, g_t times the
+ *                           explicit derivative of u_t with respect to f
+ *                           (prox: 4 lambda f / s; projected: m . (-d psi / df))
  *
  * Per stage t = T..1, with g = dl/du_t:
  *   ut  = u_{t-1} - sum_i K_i^T phi_i(K_i u_{t-1})   (recomputed)
@@ -286,12 +345,17 @@ void oracle_forward(const double *f, int N, int H, int W, int T, int Nk, int ks,
  *   g  <- e - sum_i K_i^T( phi_i'(z_i) . a_i )        (eq. derv1-1 transposed)
  * The k and phi parts follow from differentiating -<e, K_i^T phi_i(K_i u)>,
  * which the paper defers to the original TNRD derivation.
+ *
+ * Projected variant (eq. diffusion_backP): the projection's derivative is
+ * m = 1 where ut > c and 0 elsewhere, e = m . g, dlam^t = -<e, d psi / d lambda>,
+ * and the reaction adds -(d psi / du)(u_{t-1}) . e to g_{t-1}.
  */
-void oracle_backward(const double *f, int N, int H, int W, int T, int Nk, int ks, int Nrbf,
-                     double mu0, double step, double sigma,
-                     const double *filters, const double *rbf_w, const double *lam,
-                     const double *states, const double *gT,
-                     double *dK, double *dW, double *dlam, double *g0, int nthreads)
+void oracle_backward_ex(const double *f, int N, int H, int W, int T, int Nk, int ks, int Nrbf,
+                        double mu0, double step, double sigma,
+                        const double *filters, const double *rbf_w, const double *lam,
+                        int reaction, double cproj,
+                        const double *states, const double *gT,
+                        double *dK, double *dW, double *dlam, double *g0, double *gf, int nthreads)
 {
     set_threads(nthreads);
     size_t n = (size_t)H * W;
@@ -310,22 +374,34 @@ void oracle_backward(const double *f, int N, int H, int W, int T, int Nk, int ks
     double *dp = (double *)malloc(sizeof(double) * n);
     double *xi = (double *)malloc(sizeof(double) * n);
     double *gacc = (double *)malloc(sizeof(double) * n);
+    double *fexp = (double *)malloc(sizeof(double) * n);
 
     for (int img = 0; img < N; ++img) {
         const double *fi = f + (size_t)img * n;
         memcpy(g, gT + (size_t)img * n, sizeof(double) * n);
+        memset(fexp, 0, sizeof(double) * n);
         for (int t = T - 1; t >= 0; --t) {
             const double *uprev = states + ((size_t)t * N + img) * n;
             /* recompute ut_t from u_{t-1} exactly as the forward does */
             stage_forward(uprev, fi, H, W, t, Nk, ks, Nrbf, mu0, step, sigma,
-                          filters, rbf_w, lam, ut, unext);
-            /* prox backward */
+                          filters, rbf_w, lam, reaction, cproj, ut, unext);
             double dl = 0.0;
-            for (size_t p = 0; p < n; ++p) {
-                double y, xl;
-                oracle_prox_grad(ut[p], fi[p], lam[t], &y, &xl);
-                dl += g[p] * xl;
-                e[p] = y * g[p];
+            if (reaction == REACT_PROJECTED) {
+                /* projection backward: e = m g with m = [ut > c] */
+                for (size_t p = 0; p < n; ++p) {
+                    e[p] = ut[p] > cproj ? g[p] : 0.0;
+                    dl -= e[p] * oracle_psi_dlam(uprev[p], fi[p]);
+                    fexp[p] -= e[p] * oracle_psi_df(uprev[p], fi[p], lam[t]);
+                }
+            } else {
+                /* prox backward */
+                for (size_t p = 0; p < n; ++p) {
+                    double y, xl;
+                    oracle_prox_grad(ut[p], fi[p], lam[t], &y, &xl);
+                    dl += g[p] * xl;
+                    e[p] = y * g[p];
+                    fexp[p] += g[p] * oracle_prox_df(ut[p], fi[p], lam[t]);
+                }
             }
             dlam[t] += dl;
             memset(gacc, 0, sizeof(double) * n);
@@ -369,10 +445,26 @@ void oracle_backward(const double *f, int N, int H, int W, int T, int Nk, int ks
                 oracle_conv_adj(dp, H, W, k, ks, xi);
                 for (size_t p = 0; p < n; ++p) gacc[p] += xi[p];
             }
-            for (size_t p = 0; p < n; ++p) g[p] = e[p] - gacc[p];
+            for (size_t p = 0; p < n; ++p) {
+                g[p] = e[p] - gacc[p];
+                if (reaction == REACT_PROJECTED) g[p] -= oracle_psi_du(uprev[p], fi[p], lam[t]) * e[p];
+            }
         }
         if (g0) memcpy(g0 + (size_t)img * n, g, sizeof(double) * n);
+        if (gf)
+            for (size_t p = 0; p < n; ++p) gf[(size_t)img * n + p] = g[p] + fexp[p];  /* u_0 = f */
     }
     free(g); free(e); free(ut); free(unext); free(z); free(v); free(a);
-    free(dp); free(xi); free(gacc);
+    free(dp); free(xi); free(gacc); free(fexp);
+}
+
+/* The proximal model (eq. diffusionprocessfinal), without dl/df. */
+void oracle_backward(const double *f, int N, int H, int W, int T, int Nk, int ks, int Nrbf,
+                     double mu0, double step, double sigma,
+                     const double *filters, const double *rbf_w, const double *lam,
+                     const double *states, const double *gT,
+                     double *dK, double *dW, double *dlam, double *g0, int nthreads)
+{
+    oracle_backward_ex(f, N, H, W, T, Nk, ks, Nrbf, mu0, step, sigma, filters, rbf_w, lam,
+                       REACT_PROX, 0.0, states, gT, dK, dW, dlam, g0, NULL, nthreads);
 }

@@ -75,9 +75,14 @@ def make_model(T: int, Nk: int, ks: int, rng: np.random.Generator, Nrbf: int = 6
     }
 
 
-def make_pair(H: int, W: int, L: int, config_id: int, index: int = 0, amplitude: bool = False):
-    """(clean u_gt, speckled f) for one image, both FP32 H x W."""
+def make_pair(H: int, W: int, L: int, config_id: int, index: int = 0, amplitude: bool = False,
+              peak: float | None = None):
+    """(clean u_gt, speckled f) for one image, both FP32 H x W.  With ``peak``
+    the clean image is divided by max(u)/peak first (the low-peak images of the
+    paper's comparison of the projected model, peaks 0.5 to 255)."""
     u = make_clean(H, W, rng_for(config_id, 0, index))
+    if peak is not None:
+        u = (u.astype(np.float64) * (peak / float(u.max()))).astype(np.float32)
     f = speckle(u, L, rng_for(config_id, 1, index), amplitude=amplitude)
     return u, f
 
@@ -94,6 +99,9 @@ CONFIGS = {
             sizes=None, looks=None),
     5: dict(name="c5 mixed precision 8x2048x2048, L=1, 8 stages x 48 7x7", T=8, Nk=48, ks=7,
             sizes=[(2048, 2048)] * 8, looks=[1] * 8),
+    # the paper's comparison of the projected model: 5 stages of 5x5 filters, L = 1
+    6: dict(name="projected variant 1x128x128, L=1, 5 stages x 24 5x5, c = 1", T=5, Nk=24, ks=5,
+            sizes=[(128, 128)], looks=[1], reaction="projected"),
 }
 
 C4_SIZES = [(256, 256), (384, 512), (512, 512), (1024, 768)]
@@ -110,4 +118,8 @@ def c4_batch(n_images: int = 64):
 
 def config_model(config_id: int, look: int = 0) -> dict:
     c = CONFIGS[config_id]
-    return make_model(c["T"], c["Nk"], c["ks"], rng_for(config_id, 2, look))
+    m = make_model(c["T"], c["Nk"], c["ks"], rng_for(config_id, 2, look))
+    if c.get("reaction", "prox") != "prox":
+        m["reaction"] = c["reaction"]
+        m["proj_c"] = 1.0
+    return m
