@@ -10,6 +10,8 @@ Extra legs reported on the same JSON line (each its own workload):
   fwd_bwd  16 x 180 x 180, forward with saved states + hand-written backward
   batched  64 uneven images, one launch per stage over all tiles, replayed from a HIP graph
   mixed    8 x 2048 x 2048 with BF16/FP16 filter-bank operands
+  projected  the paper's comparison model (projection onto u >= 1), 8 x 512 x 512,
+           5 stages of 24 5x5 filters, forward and forward + backward with dl/df
   peaks    measured copy, matrix, vector-FMA and exp2 throughput; the legs' rates
            against them ("fractions")
 
@@ -46,7 +48,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--impl", default="auto", choices=["auto", "fused", "split"])
-    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed,peaks")
+    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed,projected,peaks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of known "
@@ -180,7 +182,7 @@ def leg_fwd_bwd(args):
             raise RuntimeError(tnrd.status_str(st))
         torch.sub(u, ud, out=g)
         g.mul_(2.0 / g.numel())
-        st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, o, wsb, nbb)
+        st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, None, o, wsb, nbb)
         if st != 0:
             raise RuntimeError(tnrd.status_str(st))
 
@@ -279,7 +281,7 @@ def leg_mixed(args):
                 raise RuntimeError(tnrd.status_str(st))
             torch.sub(u, ud, out=g)
             g.mul_(2.0 / g.numel())
-            st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, o, wsb, nbb)
+            st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, None, o, wsb, nbb)
             if st != 0:
                 raise RuntimeError(tnrd.status_str(st))
 
@@ -314,6 +316,69 @@ def leg_mixed(args):
         res[name]["dpsnr_db_vs_fp32_path"] = abs(10 * math.log10(mse_ref / mse))
     res["workload"] = ("mixed precision: 8 x 2048 x 2048, L=1, 8 stages x 48 7x7; filter-bank "
                        "operands FP32/BF16/FP16 with FP32 accumulation; influence and prox FP32")
+    return res
+
+
+def leg_projected(args):
+    """The paper's comparison model (eq. diffusion_backP, projection onto u >= 1)
+    at the shape of its comparison experiment (5 stages of 24 5x5 filters, L = 1),
+    8 images of 512 x 512 whose clean version peaks at 6 (many pixels projected):
+    forward, and forward + backward with dl/df."""
+    import torch
+    from paper_1702_07482_amd import synth, tnrd
+
+    N, H, W = 8, 512, 512
+    m = synth.config_model(6)
+    T = m["filters"].shape[0]
+    pairs = [synth.make_pair(H, W, 1, config_id=6, index=200 + n, peak=6.0) for n in range(N)]
+    fd = torch.from_numpy(np.stack([p[1] for p in pairs])).cuda().contiguous()
+    ud = torch.from_numpy(np.stack([p[0] for p in pairs])).cuda().contiguous()
+    dm = tnrd.DeviceModel.from_numpy(m)
+    mm = dm.abi()
+    o = tnrd.default_opts()
+    nbf = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 0)
+    nbb = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 1)
+    wsf = torch.empty(nbf, dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(nbb, dtype=torch.uint8, device="cuda")
+    u = torch.empty_like(fd)
+    states = torch.empty((T + 1, N, H, W), dtype=torch.float32, device="cuda")
+    g = torch.empty_like(fd)
+    gf = torch.empty_like(fd)
+    dK, dW, dl = torch.empty_like(dm.filters), torch.empty_like(dm.rbf_w), torch.empty_like(dm.lam)
+
+    def fwd(st=None):
+        r = tnrd.tnrd_forward(fd, N, H, W, 1, mm, u, st, o, wsf, nbf)
+        if r != 0:
+            raise RuntimeError(tnrd.status_str(r))
+
+    def fwd_bwd():
+        fwd(states)
+        torch.sub(u, ud, out=g)
+        g.mul_(2.0 / g.numel())
+        r = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, gf, o, wsb, nbb)
+        if r != 0:
+            raise RuntimeError(tnrd.status_str(r))
+
+    res = {}
+    for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = _events()
+        reps = 5
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        res[f"{name}_mpst_s"] = N * H * W * T / 1e6 / (ms / 1e3)
+        res[f"{name}_ms"] = ms
+    fwd(states)
+    torch.cuda.synchronize()
+    res["projected_fraction_final"] = float((states[T] <= 1.0).float().mean().item())
+    res["workload"] = ("projected variant (eq. diffusion_backP, c = 1): 8 x 512 x 512, clean peak 6, "
+                       "L=1, 5 stages x 24 5x5, FP32; fwd_bwd includes dl/df")
     return res
 
 
@@ -448,6 +513,8 @@ def main():
         out["batched"] = leg_batched(args)
     if "mixed" in legs:
         out["mixed"] = leg_mixed(args)
+    if "projected" in legs:
+        out["projected"] = leg_projected(args)
     if "peaks" in legs:
         out["peaks"] = leg_peaks(args)
         out["fractions"] = fractions(out)

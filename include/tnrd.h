@@ -70,6 +70,19 @@ typedef enum tnrd_impl {
                              the workspace, then (K^T, prox).  Reference design for comparison. */
 } tnrd_impl;
 
+/* Reaction step of a stage.
+ *   TNRD_REACT_PROX       the proximal step of the paper's model (Sec. 3.1, eqs. subproblemGIdiv,
+ *                         diffusionprocessfinal): u_t = prox(ut_t), ut_t = u_{t-1} - sum_i K_i^T v_i
+ *   TNRD_REACT_PROJECTED  the paper's comparison model (Sec. 3.1, eq. diffusion_backP): a gradient
+ *                         step on the data term followed by the projection onto u >= c,
+ *                         ut_t = u_{t-1} - (sum_i K_i^T v_i + (l/u_{t-1})(1 - f^2/u_{t-1}^2)),
+ *                         u_t = max(ut_t, c), c = proj_c (the paper uses c = 1).  Its backward
+ *                         takes the projection's derivative as 1 where ut_t > c, else 0. */
+typedef enum tnrd_reaction {
+    TNRD_REACT_PROX = 0,
+    TNRD_REACT_PROJECTED = 1
+} tnrd_reaction;
+
 /* Per-stage parameters Theta^t = {lambda^t, phi_i^t, k_i^t} (Sec. 2.2.2, eq. learning). */
 typedef struct tnrd_model {
     int32_t T;            /* stages, >= 1 */
@@ -83,6 +96,8 @@ typedef struct tnrd_model {
     const float *filters; /* device [T][Nk][ksize][ksize], k_i^t (convolution kernels) */
     const float *rbf_w;   /* device [T][Nk][Nrbf], w_ij^t */
     const float *lambda;  /* device [T], lambda^t >= 0 (the backward needs lambda^t > 0) */
+    int32_t reaction;     /* tnrd_reaction */
+    float proj_c;         /* TNRD_REACT_PROJECTED: the projection threshold c > 0 */
 } tnrd_model;
 
 typedef struct tnrd_opts {
@@ -114,7 +129,8 @@ size_t tnrd_workspace_bytes(int N, int H, int W, const tnrd_model *m, const tnrd
  * t = 0, s, 2s, ... < T, followed by u_T; that is T + 1 slots when s = 1. */
 int tnrd_num_checkpoints(int T, int recompute_every);
 
-/* Forward pass (Sec. 3.1, eq. diffusionprocessfinal, Fig. feedforwardCNNspeckle).
+/* Forward pass (Sec. 3.1, eq. diffusionprocessfinal, Fig. feedforwardCNNspeckle; with
+ * m->reaction == TNRD_REACT_PROJECTED, eq. diffusion_backP).
  *   f       [N][H][W]  observed amplitude, f > 0 (the prox is positive only then)
  *   L       number of looks of f, >= 1; must equal m->L unless m->L == 0.  L does not
  *           enter the arithmetic (the paper trains one model per L).
@@ -123,7 +139,8 @@ int tnrd_num_checkpoints(int T, int recompute_every);
  *           the backward needs (u_0 = f first, u_T last)
  * Errors: TNRD_ERR_ARG for NULL f/u_out/m/parameter pointers, N < 0, H or W < ksize,
  * even ksize, T/Nk < 1, Nrbf outside 1..255, rbf_step or rbf_sigma <= 0 or not finite,
- * L < 1 or m->L not in {0, L}, u_out == f; TNRD_ERR_UNSUPPORTED for ksize not in
+ * L < 1 or m->L not in {0, L}, u_out == f, a reaction outside tnrd_reaction, proj_c <= 0
+ * or not finite for the projected reaction; TNRD_ERR_UNSUPPORTED for ksize not in
  * {3,5,7}, a precision the chosen implementation lacks, or a tile that does not fit
  * the fused kernel's local memory; TNRD_ERR_WORKSPACE. */
 int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
@@ -139,14 +156,19 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
  *   grad_lambda  [T]                    dl/dlambda^t  (for lambda = e^beta, eq. derv5:
  *                                       dl/dbeta^t = lambda^t * dl/dlambda^t)
  *   grad_u0      NULL or [N][H][W]      dl/du_0 through the diffusion chain, with f
- *                                       held fixed in the prox
+ *                                       held fixed in the reaction steps
+ *   grad_f       NULL or [N][H][W]      dl/df in full: grad_u0 (u_0 = f) plus, at every
+ *                                       stage, dl/du_t times the reaction's explicit
+ *                                       derivative in f (prox: 4 l f / s with
+ *                                       s = sqrt(ut^2 + 8(1+2l) l f^2); projected:
+ *                                       2 l f / u_{t-1}^3 where ut_t > c, else 0)
  * lambda^t must be > 0.  Results are deterministic: the same inputs give the
  * same bits for every recompute_every.  Errors as tnrd_forward, and
- * TNRD_ERR_ARG for NULL states/grad pointers. */
+ * TNRD_ERR_ARG for NULL states/grad pointers or grad_f aliasing grad_u0. */
 int tnrd_backward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
                   const float *states, const float *grad_uT,
                   float *grad_filters, float *grad_rbf_w, float *grad_lambda,
-                  float *grad_u0, const tnrd_opts *o,
+                  float *grad_u0, float *grad_f, const tnrd_opts *o,
                   void *ws, size_t ws_bytes, void *stream);
 
 /* One image of an uneven batch. */

@@ -8,7 +8,10 @@ provides memory, the stream and the graph bookkeeping.
 
 The forward keeps the checkpoint states the backward needs (all T + 1 states,
 or every s-th with opts.recompute_every = s, the others being recomputed
-inside tnrd_backward).  f is treated as data: no gradient flows to it.
+inside tnrd_backward).  When f requires a gradient, dl/df comes from the same
+backward call in full (u_0 = f plus every reaction step's explicit f).  The
+reaction is the model's: "prox" (eq. diffusionprocessfinal) or "projected"
+(eq. diffusion_backP, threshold proj_c).
 """
 from __future__ import annotations
 
@@ -20,8 +23,7 @@ from . import tnrd
 class TNRDFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, filters, rbf_w, lam, meta):
-        dm = tnrd.DeviceModel(filters.detach(), rbf_w.detach(), lam.detach(), meta["mu0"],
-                              meta["step"], meta["sigma"], meta.get("L_model", 0))
+        dm = _model(filters, rbf_w, lam, meta)
         opts = meta.get("opts") or tnrd.default_opts()
         L = meta.get("L", 1)
         u, states = tnrd.forward(f.detach(), dm, L=L, want_states=True, opts=opts)
@@ -33,18 +35,29 @@ class TNRDFunction(torch.autograd.Function):
     def backward(ctx, grad_u):
         f, filters, rbf_w, lam, states = ctx.saved_tensors
         meta = ctx.meta
-        dm = tnrd.DeviceModel(filters.detach(), rbf_w.detach(), lam.detach(), meta["mu0"],
-                              meta["step"], meta["sigma"], meta.get("L_model", 0))
+        dm = _model(filters, rbf_w, lam, meta)
         opts = meta.get("opts") or tnrd.default_opts()
         g = grad_u.contiguous()
         if g.dim() == 2:
             g = g[None]
-        dK, dW, dl = tnrd.backward(f.detach(), dm, states, g, L=meta.get("L", 1), opts=opts)
-        return None, dK, dW, dl, None
+        want_f = ctx.needs_input_grad[0]
+        fd = f.detach() if f.dim() == 3 else f.detach()[None]
+        out = tnrd.backward(fd, dm, states, g, L=meta.get("L", 1), opts=opts, want_f=want_f)
+        dK, dW, dl = out[:3]
+        df = out[3].view_as(f) if want_f else None
+        return df, dK, dW, dl, None
 
 
-def tnrd_apply(f, filters, rbf_w, lam, mu0=-310.0, step=10.0, sigma=10.0, L=1, opts=None):
-    """u_T = TNRD(f) with autograd support for filters, rbf_w and lam."""
+def _model(filters, rbf_w, lam, meta):
+    return tnrd.DeviceModel(filters.detach(), rbf_w.detach(), lam.detach(), meta["mu0"],
+                            meta["step"], meta["sigma"], meta.get("L_model", 0),
+                            tnrd.REACTIONS[meta.get("reaction", "prox")],
+                            float(meta.get("proj_c", 1.0)))
+
+
+def tnrd_apply(f, filters, rbf_w, lam, mu0=-310.0, step=10.0, sigma=10.0, L=1, opts=None,
+               reaction="prox", proj_c=1.0):
+    """u_T = TNRD(f) with autograd support for f, filters, rbf_w and lam."""
     meta = {"mu0": float(mu0), "step": float(step), "sigma": float(sigma), "L": int(L),
-            "opts": opts}
+            "opts": opts, "reaction": reaction, "proj_c": float(proj_c)}
     return TNRDFunction.apply(f, filters, rbf_w, lam, meta)

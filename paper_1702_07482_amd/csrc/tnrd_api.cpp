@@ -45,6 +45,9 @@ int check_model(const tnrd_model *m)
     if (!(m->rbf_sigma > 0.f) || !isfinite(m->rbf_sigma)) return TNRD_ERR_ARG;
     if (!isfinite(m->rbf_mu0)) return TNRD_ERR_ARG;
     if (m->L < 0) return TNRD_ERR_ARG;
+    if (m->reaction != TNRD_REACT_PROX && m->reaction != TNRD_REACT_PROJECTED) return TNRD_ERR_ARG;
+    if (m->reaction == TNRD_REACT_PROJECTED && (!(m->proj_c > 0.f) || !isfinite(m->proj_c)))
+        return TNRD_ERR_ARG;
     if (m->ksize != 3 && m->ksize != 5 && m->ksize != 7) return TNRD_ERR_UNSUPPORTED;
     return TNRD_OK;
 }
@@ -174,6 +177,8 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
     s.tile_w = o.tile_w;
     s.waves = o.wg_waves;
     s.poly = o.rbf_window < 0;
+    s.react = m->reaction;
+    s.proj_c = m->proj_c;
     const float *cur = u_start;
     const size_t kk = (size_t)m->ksize * m->ksize;
     for (int t = t_begin; t < t_end; ++t) {

@@ -58,6 +58,10 @@ struct BwdParamsIO {
     float *za;            // z = K u_{t-1} and a = K e per pixel (za_index layout)
     float *dk_part;       // [tiles][Nk*KK]
     float *dl_part;       // [tiles]
+    float *gf;            // nullable [N*H*W]: dl/df, this stage's explicit term added
+    int gf_first;         // nonzero: write gf instead of adding to it
+    int react;            // tnrd_reaction
+    float proj_c;         // projected reaction: threshold c
 };
 
 struct BpLds {
@@ -175,13 +179,27 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
                     float u2 = uv[k] * uv[k], f2 = ff[k] * ff[k];
                     float den = fmaf(c1, u2, c2 * f2);  // u s
                     su[ly * L.ldw + lx] = uu[k];
-                    se[ly * L.ldw + lx] = u2 / den * gg[k];
-                    // dl/dlambda over the tile's own pixels: g * 2 (f - u)(f + u) / s
-                    // (the factored difference keeps its precision when u ~ f)
+                    const bool proj = io.react == 1;
+                    // e = y g: prox y = u_t^2 / (u_t s); projected y = [u_t > c]
+                    const float ev = proj ? (uv[k] > io.proj_c ? gg[k] : 0.f) : u2 / den * gg[k];
+                    se[ly * L.ldw + lx] = ev;
                     int yi = ty0 - R + ly, xi = tx0 - R + lx;
                     bool own = ly >= R && ly < R + Th && lx >= R && lx < R + Tw && yi < H && xi < W;
-                    if (own)
-                        dl_acc = fmaf(gg[k], 2.f * (ff[k] - uv[k]) * (ff[k] + uv[k]) * uv[k] / den, dl_acc);
+                    if (own) {
+                        // dl/dlambda over the tile's own pixels: prox g 2 (f - u)(f + u) / s (the
+                        // factored difference keeps its precision when u ~ f); projected
+                        // -e (d psi/dl)(u_{t-1})
+                        dl_acc = proj ? fmaf(-ev, proj_psi_dlam(uu[k], ff[k]), dl_acc)
+                                      : fmaf(gg[k], 2.f * (ff[k] - uv[k]) * (ff[k] + uv[k]) * uv[k] / den, dl_acc);
+                        if (io.gf) {
+                            // explicit f-dependence of u_t: prox du/df = 4 l f / s = 4 l f u / (u s);
+                            // projected -e (d psi/df)(u_{t-1})
+                            const float fx = proj ? -ev * proj_psi_df(uu[k], ff[k], lam)
+                                                  : gg[k] * (4.f * lam * ff[k] * uv[k] / den);
+                            float *gp = io.gf + img * plane + (size_t)yi * W + xi;
+                            *gp = io.gf_first ? fx : *gp + fx;
+                        }
+                    }
                 }
             }
         }
@@ -539,6 +557,14 @@ __global__ void __launch_bounds__(RED_E * RED_R) k_reduce_partials(RedJobs jobs)
     }
 }
 
+// acc += x elementwise (dl/df = explicit terms + dl/du_0).
+__global__ void __launch_bounds__(256) k_add_plane(float *__restrict__ acc, const float *__restrict__ x,
+                                                   size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) acc[i] += x[i];
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -704,6 +730,14 @@ hipError_t bwd_dw(const float *za, const BwdGeom &gm, int Nk,
     return launch_bwd_dw<1>(za, gm, Nk, grid, dw_part, stream);
 }
 
+// acc += x over n floats.
+hipError_t add_plane(float *acc, const float *x, size_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_plane, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, acc, x, n);
+    return hipGetLastError();
+}
+
 // One launch for the (up to RED_JOBS) reductions of a stage.
 hipError_t reduce_partials(const RedJob *jobs, int n, hipStream_t stream)
 {
@@ -742,7 +776,7 @@ using namespace tnrd;
 
 extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
                              const float *states, const float *grad_uT, float *grad_filters,
-                             float *grad_rbf_w, float *grad_lambda, float *grad_u0,
+                             float *grad_rbf_w, float *grad_lambda, float *grad_u0, float *grad_f,
                              const tnrd_opts *o, void *ws, size_t ws_bytes, void *stream_)
 {
     tnrd_opts oo;
@@ -750,6 +784,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     int st = check_image_args(f, N, H, W, L, m, grad_uT);
     if (st != TNRD_OK) return st;
     if (!states || !grad_filters || !grad_rbf_w || !grad_lambda) return TNRD_ERR_ARG;
+    if (grad_f && grad_f == grad_u0) return TNRD_ERR_ARG;
     if (oo.prec < TNRD_PREC_FP32 || oo.prec > TNRD_PREC_FP16) return TNRD_ERR_ARG;
     const int window = rbf_window_for(m, oo.rbf_window);
     if (!fused_supported(m->ksize, m->Nk, m->Nrbf, window, oo.prec) || !bwd_lds_ok(m))
@@ -798,6 +833,8 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     ia.tile_w = 0;
     ia.waves = 0;
     ia.poly = oo.rbf_window < 0;
+    ia.react = m->reaction;
+    ia.proj_c = m->proj_c;
 
     const float *g_cur = grad_uT;
     int ping = 0;
@@ -823,20 +860,24 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             const float *filt = m->filters + (size_t)ts * m->Nk * kk;
             const float *rbfw = m->rbf_w + (size_t)ts * m->Nk * m->Nrbf;
             const float *lam = m->lambda + ts;
-            BwdParamsIO io;
+            BwdParamsIO io{};
             io.u_prev = ut[t - 1];
             io.u_cur = ut[t];
             io.f = f;
             io.g_cur = g_cur;
             io.za = w.za;
+            io.gf = grad_f;
+            io.gf_first = t == T;
+            io.react = m->reaction;
+            io.proj_c = m->proj_c;
             io.dk_part = w.dk_part;
             io.dl_part = w.dl_part;
             // The input-gradient kernel (FP32) computes z = K u and a = K e at
             // every pixel anyway and exports them, so it runs first and the
             // parameter-gradient kernels load them instead of recomputing.
-            const bool need_g = t > 1 || grad_u0;
+            const bool need_g = t > 1 || grad_u0 || grad_f;
             const bool loadza = need_g && oo.prec == TNRD_PREC_FP32 && (long long)H * W <= INT_MAX;
-            float *g_next = (t == 1) ? grad_u0 : w.g[ping];
+            float *g_next = (t == 1 && grad_u0) ? grad_u0 : w.g[ping];
             if (need_g) {
                 ia.u_prev = ut[t - 1];
                 ia.u_cur = ut[t];
@@ -865,5 +906,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
         }
         seg_hi = seg_lo;
     }
+    // dl/df = the stages' explicit terms (accumulated by k_bwd_params) + dl/du_0 (u_0 = f)
+    if (grad_f && add_plane(grad_f, g_cur, img, stream) != hipSuccess) return TNRD_ERR_HIP;
     return TNRD_OK;
 }

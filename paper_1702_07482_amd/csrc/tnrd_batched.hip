@@ -124,6 +124,8 @@ void build_descriptors(int B, const tnrd_image *imgs, int n_models, const tnrd_m
         dm[k].filt = models[k].filters;
         dm[k].rbfw = models[k].rbf_w;
         dm[k].lam = models[k].lambda;
+        dm[k].react = models[k].reaction;
+        dm[k].proj_c = models[k].proj_c;
     }
 }
 

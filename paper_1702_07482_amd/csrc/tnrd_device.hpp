@@ -90,4 +90,37 @@ __device__ __forceinline__ float prox(float ut, float f, float lam)
     return num / (2.f * c1);
 }
 
+// Reaction of the projected variant (eq. diffusion_backP), psi(u) =
+// (l/u)(1 - f^2/u^2), evaluated as l (u - f)(u + f) / u^3 (no cancellation in
+// 1 - f^2/u^2 when u is close to f), and its partial derivatives
+// d psi/du = l (3 f^2 - u^2) / u^4, d psi/dl = (u - f)(u + f) / u^3,
+// d psi/df = -2 l f / u^3.
+__device__ __forceinline__ float proj_psi(float u, float f, float lam)
+{
+    return lam * ((u - f) * (u + f)) / (u * u * u);
+}
+__device__ __forceinline__ float proj_psi_du(float u, float f, float lam)
+{
+    const float u2 = u * u;
+    return lam * fmaf(3.f * f, f, -u2) / (u2 * u2);
+}
+__device__ __forceinline__ float proj_psi_dlam(float u, float f)
+{
+    return ((u - f) * (u + f)) / (u * u * u);
+}
+__device__ __forceinline__ float proj_psi_df(float u, float f, float lam)
+{
+    return -2.f * lam * f / (u * u * u);
+}
+
+// Reaction step of a stage from u_{t-1} and the diffusion force x = sum_i K_i^T v_i:
+// react 0: u_t = prox(u_{t-1} - x)                      (eq. diffusionprocessfinal)
+// react 1: u_t = max(u_{t-1} - (x + psi(u_{t-1})), c)   (eq. diffusion_backP)
+__device__ __forceinline__ float reaction_step(int react, float u_prev, float x, float f, float lam,
+                                               float c)
+{
+    if (react == 1) return fmaxf(u_prev - (x + proj_psi(u_prev, f, lam)), c);
+    return prox(u_prev - x, f, lam);
+}
+
 }  // namespace tnrd

@@ -95,6 +95,8 @@ struct FusedIO {
     const float *g_cur;   // input gradient: g_t = dl/du_t
     float *za;            // input gradient, optional: z = K u and a = K e at the tile's own
                           // pixels, layout of za_index()
+    int react;            // tnrd_reaction of the stage
+    float proj_c;         // projected reaction: threshold c
 };
 
 // Export of z = K u and a = K e for the parameter-gradient kernels: per pixel

@@ -159,7 +159,8 @@ __device__ __forceinline__ void fused_tile(
     }
     // (2b) input-gradient mode: e = y * g_t over the same region, where
     // y = du_t/d(ut_t) = u_t^2 / ((1+2l) u_t^2 + 2 l f^2) is the prox derivative
-    // written with the prox output (equal to the closed form of eq. derv2).
+    // written with the prox output (equal to the closed form of eq. derv2); for
+    // the projected reaction y is the projection's derivative, 1 where u_t > c.
     float emax = 0.f;  // largest |e| of the tile (input-gradient mode)
     if (BWD) {
         const float lam0 = lam_t[0];
@@ -186,7 +187,9 @@ __device__ __forceinline__ void fused_tile(
                 if (i < n) {
                     int ly = i / luw, lx = i - ly * luw;
                     float u2 = uu[k] * uu[k];
-                    float y = u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
+                    // prox: y = du_t/d(ut_t); projected: 1 where ut_t > c (u_t > c), else 0
+                    float y = io.react == 1 ? (uu[k] > io.proj_c ? 1.f : 0.f)
+                                            : u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
                     float ev = y * gg[k];
                     se[ly * L.ldw + lx] = ev;
                     emax = fmaxf(emax, fabsf(ev));
@@ -624,11 +627,16 @@ __device__ __forceinline__ void fused_tile(
                 }
             const size_t pix = (size_t)yi * W + xi;
             if (BWD) {
-                // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1)
-                uo[pix] = se[(y + 2 * R) * L.ldw + x + 2 * R] - xs * einv;
+                // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1);
+                // the projected reaction adds -(d psi/du)(u_{t-1}) e
+                const float ev = se[(y + 2 * R) * L.ldw + x + 2 * R];
+                float gv = ev - xs * einv;
+                if (io.react == 1)
+                    gv -= proj_psi_du(su[(y + 2 * R) * L.ldw + x + 2 * R], fn[pix], lam) * ev;
+                uo[pix] = gv;
             } else {
                 const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
-                uo[pix] = prox(uv - xs, fpre[p], lam);
+                uo[pix] = reaction_step(io.react, uv, xs, fpre[p], lam, io.proj_c);
             }
         }
     };
@@ -710,7 +718,7 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     const int trem = blockIdx.x - img * tiles_per_img;
     const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
     const size_t plane = (size_t)H * W;
-    FusedIO ii;
+    FusedIO ii = io;  // per-image pointers below; every other field as launched
     ii.u_prev = io.u_prev + img * plane;
     ii.f = io.f + img * plane;
     ii.out = io.out + img * plane;
@@ -737,7 +745,7 @@ __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
     const BatchImage im = a.imgs[it.image];
     const int ty = it.tile / im.tiles_x, tx = it.tile - ty * im.tiles_x;
     const bool to_out = ((a.T - 1 - t) & 1) == 0;
-    FusedIO io;
+    FusedIO io{};
     io.f = im.f;
     io.u_prev = t == 0 ? im.f : (to_out ? im.u_tmp : im.u_out);
     io.out = to_out ? im.u_out : im.u_tmp;
@@ -745,6 +753,8 @@ __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
     io.g_cur = nullptr;
     io.za = nullptr;
     const BatchModel md = a.models[im.model];
+    io.react = md.react;
+    io.proj_c = md.proj_c;
     fused_tile<KS, NMB, NB, NW, MODE_FWD, PREC_F32, RBFM>(
         io, im.H, im.W, a.Th, a.Tw, ty * a.Th, tx * a.Tw, md.filt + (size_t)t * a.Nk * KK, a.Nk,
         md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb, md.lam + t, lds);
@@ -766,13 +776,15 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     }
     if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     FusedRbf rb = make_fused_rbf(s.grid);
-    FusedIO io;
+    FusedIO io{};
     io.u_prev = s.u_prev;
     io.f = s.f;
     io.out = s.u_next;
     io.u_cur = s.u_cur;
     io.g_cur = s.g_cur;
     io.za = MODE == MODE_BWD_INPUT && PREC == PREC_F32 ? s.za : nullptr;
+    io.react = s.react;
+    io.proj_c = s.proj_c;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     dim3 grid(tiles * s.N);

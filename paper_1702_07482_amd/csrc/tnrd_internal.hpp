@@ -28,6 +28,8 @@ struct StageArgs {
     int tile_h, tile_w;   // 0 = automatic
     int waves;            // fused: waves per workgroup (4 or 8; 0 = automatic)
     int poly;             // fused kernel: the polynomial influence form may be used
+    int react = 0;        // tnrd_reaction of the model
+    float proj_c = 1.f;   // projected reaction: threshold c
     float *za = nullptr;  // input-gradient mode, FP32: if set, z = K u and a = K e at every
                           // pixel (za_index layout), the parameter-gradient kernels' input
 };
@@ -44,6 +46,8 @@ struct BatchModel {
     const float *filt;  // [T][Nk][KK]
     const float *rbfw;  // [T][Nk][Nrbf]
     const float *lam;   // [T]
+    int react;          // tnrd_reaction
+    float proj_c;       // projected reaction: threshold c
 };
 
 struct BatchItem {

@@ -68,7 +68,7 @@ template <int KS>
 __global__ void __launch_bounds__(256) k_split_adj_prox(
     const float *__restrict__ V, size_t v_filter_stride,
     const float *__restrict__ u, const float *__restrict__ f, int H, int W,
-    const float *__restrict__ filt, int Nk, const float *__restrict__ lam_t,
+    const float *__restrict__ filt, int Nk, const float *__restrict__ lam_t, int react, float proj_c,
     float *__restrict__ u_next)
 {
     constexpr int R = KS / 2;
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) k_split_adj_prox(
     }
     if (!inside) return;
     const size_t p = n * img + (size_t)y * W + x;
-    u_next[p] = prox(u[p] - acc, f[p], lam_t[0]);
+    u_next[p] = reaction_step(react, u[p], acc, f[p], lam_t[0], proj_c);
 }
 
 template <int KS>
@@ -135,7 +135,7 @@ static hipError_t split_stage_ks(const StageArgs &s, hipStream_t stream)
     hipLaunchKernelGGL(k_split_phi<KS>, grid, block, 0, stream, s.u_prev, s.H, s.W, s.filt,
                        s.rbfw, s.Nk, s.grid, s.scratch, vstride);
     hipLaunchKernelGGL(k_split_adj_prox<KS>, grid, block, 0, stream, s.scratch, vstride,
-                       s.u_prev, s.f, s.H, s.W, s.filt, s.Nk, s.lam, s.u_next);
+                       s.u_prev, s.f, s.H, s.W, s.filt, s.Nk, s.lam, s.react, s.proj_c, s.u_next);
     return hipGetLastError();
 }
 

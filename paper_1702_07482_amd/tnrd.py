@@ -29,6 +29,8 @@ TNRD_ERR_HIP = -4
 TNRD_ERR_UNSUPPORTED = -5
 
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+REACT_PROX, REACT_PROJECTED = 0, 1
+REACTIONS = {"prox": REACT_PROX, "projected": REACT_PROJECTED}
 IMPL_AUTO, IMPL_FUSED, IMPL_SPLIT = 0, 1, 2
 
 
@@ -38,6 +40,7 @@ class TnrdModel(ctypes.Structure):
         ("Nrbf", ctypes.c_int32), ("L", ctypes.c_int32),
         ("rbf_mu0", ctypes.c_float), ("rbf_step", ctypes.c_float), ("rbf_sigma", ctypes.c_float),
         ("filters", ctypes.c_void_p), ("rbf_w", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
+        ("reaction", ctypes.c_int32), ("proj_c", ctypes.c_float),
     ]
 
 
@@ -77,7 +80,7 @@ SIGNATURES = [
     ("tnrd_forward", _I, [_P, _I, _I, _I, _I, ctypes.POINTER(TnrdModel), _P, _P,
                           ctypes.POINTER(TnrdOpts), _P, _SZ, _P]),
     ("tnrd_backward", _I, [_P, _I, _I, _I, _I, ctypes.POINTER(TnrdModel), _P, _P, _P, _P, _P, _P,
-                           ctypes.POINTER(TnrdOpts), _P, _SZ, _P]),
+                           _P, ctypes.POINTER(TnrdOpts), _P, _SZ, _P]),
     ("tnrd_batched_workspace_bytes", _SZ, [_I, ctypes.POINTER(TnrdImage), _I,
                                            ctypes.POINTER(TnrdModel), ctypes.POINTER(TnrdOpts)]),
     ("tnrd_forward_batched", _I, [_I, ctypes.POINTER(TnrdImage), _I, ctypes.POINTER(TnrdModel),
@@ -151,11 +154,11 @@ def tnrd_forward(f, N, H, W, L, model: TnrdModel, u_out, states, opts: TnrdOpts,
 
 
 def tnrd_backward(f, N, H, W, L, model: TnrdModel, states, grad_uT, grad_filters, grad_rbf_w,
-                  grad_lambda, grad_u0, opts: TnrdOpts, ws, ws_bytes, stream=None) -> int:
+                  grad_lambda, grad_u0, grad_f, opts: TnrdOpts, ws, ws_bytes, stream=None) -> int:
     return int(load().tnrd_backward(_ptr(f), N, H, W, L, ctypes.byref(model), _ptr(states),
                                     _ptr(grad_uT), _ptr(grad_filters), _ptr(grad_rbf_w),
-                                    _ptr(grad_lambda), _ptr(grad_u0), ctypes.byref(opts),
-                                    _ptr(ws), ws_bytes, _stream(stream)))
+                                    _ptr(grad_lambda), _ptr(grad_u0), _ptr(grad_f),
+                                    ctypes.byref(opts), _ptr(ws), ws_bytes, _stream(stream)))
 
 
 def tnrd_batched_workspace_bytes(B, imgs, n_models, models, opts: TnrdOpts) -> int:
@@ -190,12 +193,17 @@ class DeviceModel:
     step: float
     sigma: float
     L: int = 0
+    reaction: int = REACT_PROX
+    proj_c: float = 1.0
 
     @classmethod
     def from_numpy(cls, m: dict, device="cuda", L: int = 0) -> "DeviceModel":
+        """From a model dict (filters, rbf_w, lam, mu0, step, sigma; optional
+        reaction "prox" or "projected" and proj_c)."""
         t = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
         return cls(t(m["filters"]), t(m["rbf_w"]), t(m["lam"]), float(m["mu0"]),
-                   float(m["step"]), float(m["sigma"]), L)
+                   float(m["step"]), float(m["sigma"]), L,
+                   REACTIONS[m.get("reaction", "prox")], float(m.get("proj_c", 1.0)))
 
     @property
     def T(self):
@@ -211,7 +219,7 @@ class DeviceModel:
         T, Nk, k, k2 = fi.shape
         assert k == k2 and rw.shape[:2] == (T, Nk) and la.shape == (T,)
         return TnrdModel(T, Nk, k, rw.shape[2], self.L, self.mu0, self.step, self.sigma,
-                         fi.data_ptr(), rw.data_ptr(), la.data_ptr())
+                         fi.data_ptr(), rw.data_ptr(), la.data_ptr(), self.reaction, self.proj_c)
 
 
 def _img3(f):
@@ -247,8 +255,9 @@ def forward(f, model: DeviceModel, L: int = 1, want_states: bool = False, opts: 
 
 
 def backward(f, model: DeviceModel, states, grad_uT, L: int = 1, opts: TnrdOpts = None,
-             want_u0: bool = False, filters=None, rbf_w=None, lam=None):
-    """(dK, dW, dlambda[, g0]) for dl/du_T = grad_uT."""
+             want_u0: bool = False, filters=None, rbf_w=None, lam=None, want_f: bool = False):
+    """(dK, dW, dlambda[, g0][, gf]) for dl/du_T = grad_uT (g0 = dl/du_0 through the
+    diffusion chain, gf = dl/df in full)."""
     f = _img3(f)
     grad_uT = _img3(grad_uT)
     N, H, W = f.shape
@@ -265,9 +274,11 @@ def backward(f, model: DeviceModel, states, grad_uT, L: int = 1, opts: TnrdOpts 
     dW = torch.empty_like(rw)
     dl = torch.empty_like(la)
     g0 = torch.empty_like(f) if want_u0 else None
-    _check(tnrd_backward(f, N, H, W, L, m, states, grad_uT, dK, dW, dl, g0, o, ws, nb),
+    gf = torch.empty_like(f) if want_f else None
+    _check(tnrd_backward(f, N, H, W, L, m, states, grad_uT, dK, dW, dl, g0, gf, o, ws, nb),
            "tnrd_backward")
-    return (dK, dW, dl, g0) if want_u0 else (dK, dW, dl)
+    out = (dK, dW, dl) + ((g0,) if want_u0 else ()) + ((gf,) if want_f else ())
+    return out
 
 
 def forward_batched(fs, looks, models, opts: TnrdOpts = None, outs=None, ws=None):

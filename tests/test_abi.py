@@ -31,9 +31,9 @@ def test_library_exports_every_declared_entry_point():
     assert {s[0] for s in tnrd.SIGNATURES} == set(names)
 
 
-def _model(T=2, Nk=4, ks=5, Nrbf=63, L=0, step=10.0, sigma=10.0):
+def _model(T=2, Nk=4, ks=5, Nrbf=63, L=0, step=10.0, sigma=10.0, reaction=0, proj_c=1.0):
     fake = 0x10000  # never dereferenced: every call below fails its host checks
-    return tnrd.TnrdModel(T, Nk, ks, Nrbf, L, -310.0, step, sigma, fake, fake, fake)
+    return tnrd.TnrdModel(T, Nk, ks, Nrbf, L, -310.0, step, sigma, fake, fake, fake, reaction, proj_c)
 
 
 FAKE_F = ctypes.c_void_p(0x20000)
@@ -62,6 +62,10 @@ def test_default_opts():
     (dict(step=-1.0), tnrd.TNRD_ERR_ARG),
     (dict(sigma=float("nan")), tnrd.TNRD_ERR_ARG),
     (dict(L=4), tnrd.TNRD_ERR_ARG),  # model for L = 4, image has L = 1
+    (dict(reaction=2), tnrd.TNRD_ERR_ARG),
+    (dict(reaction=-1), tnrd.TNRD_ERR_ARG),
+    (dict(reaction=1, proj_c=0.0), tnrd.TNRD_ERR_ARG),
+    (dict(reaction=1, proj_c=float("inf")), tnrd.TNRD_ERR_ARG),
 ])
 def test_model_errors(kw, bad):
     assert _fwd(_model(**kw)) == bad
@@ -96,6 +100,18 @@ def test_workspace_checks_happen_before_any_launch():
 
 def test_empty_batch_is_a_no_op():
     assert _fwd(_model(), N=0) == tnrd.TNRD_OK
+    assert _fwd(_model(reaction=1, proj_c=1.0), N=0) == tnrd.TNRD_OK
+
+
+def test_backward_rejects_grad_f_aliasing_grad_u0():
+    m = _model()
+    o = tnrd.default_opts()
+    lib = tnrd.load()
+    p = ctypes.c_void_p
+    g = p(0x50000)
+    st = lib.tnrd_backward(FAKE_F, 1, 32, 32, 1, ctypes.byref(m), p(0x60000), p(0x70000),
+                           p(0x80000), p(0x90000), p(0xA0000), g, g, ctypes.byref(o), None, 0, None)
+    assert st == tnrd.TNRD_ERR_ARG
 
 
 def test_num_checkpoints():

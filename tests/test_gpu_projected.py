@@ -1,0 +1,197 @@
+"""GPU parity of the projected variant (Sec. 3.1, eq. diffusion_backP) and of
+the full input gradient dl/df, against the FP64 oracle (via the C ABI).
+
+Bar: ||a - b||_inf / ||b||_inf <= 1e-4 per output tensor.  Workload of the
+paper's comparison: 5 stages of 24 5x5 filters, L = 1, clean images scaled to
+low peaks so that many pixels meet the projection u >= c = 1.
+
+The projection's derivative is discontinuous at ut = c, so the backward cases
+hand both sides the same FP32 states (the oracle's forward rounded to FP32)
+and check that no ut lies within 1e-5 of c, where FP32 and FP64 could take
+different sides.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1702_07482_amd import synth, tnrd
+from paper_1702_07482_amd.autograd import tnrd_apply
+from tests.helpers import oracle_uT_at, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _projected(m):
+    m = dict(m)
+    m["reaction"] = "projected"
+    m["proj_c"] = 1.0
+    return m
+
+
+def _fwd(f, m, impl=tnrd.IMPL_AUTO, L=1, want_states=False, **opt):
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(impl=impl, **opt)
+    out = tnrd.forward(_dev(f), dm, L=L, want_states=want_states, opts=o)
+    torch.cuda.synchronize()
+    if want_states:
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("impl", [tnrd.IMPL_FUSED, tnrd.IMPL_SPLIT])
+@pytest.mark.parametrize("peak", [6.0, 255.0])
+def test_projected_forward_128(impl, peak):
+    """128 x 128, 5 stages of 24 5x5 filters: every pixel of every state."""
+    print(f"[projected fwd impl={impl} peak={peak}]", flush=True)
+    m = synth.config_model(6)
+    _, f = synth.make_pair(128, 128, 1, config_id=6, peak=peak)
+    ref_uT, ref_states, ut = oracle.forward(f, m, want_states=True, want_utilde=True)
+    if peak < 10:
+        assert (ut < 1.0).mean() > 0.05  # the projection is active on many pixels
+    uT, states = _fwd(f, m, impl=impl, want_states=True)
+    assert rel_inf(uT, ref_uT) <= TOL
+    for t in range(ref_states.shape[0]):
+        assert rel_inf(states[t, 0], ref_states[t]) <= TOL, t
+    assert states[1:].min() >= 1.0
+
+
+@pytest.mark.parametrize("shape", [(97, 131), (7, 7)])
+def test_projected_forward_7x7_model_ragged(shape):
+    """48 7x7 filters, 8 stages (the plain model's shape) with the projected
+    reaction, on sizes that leave ragged tiles."""
+    m = _projected(synth.config_model(2))
+    _, f = synth.make_pair(*shape, 1, config_id=2, index=17, peak=20.0)
+    ref = oracle.forward(f, m)
+    assert rel_inf(_fwd(f, m), ref) <= TOL
+
+
+def test_projected_forward_512_sampled():
+    """512 x 512 with the 48 x 7x7 x 8-stage model: u_T at sampled pixels, each
+    from the oracle on a crop covering its receptive field."""
+    m = _projected(synth.config_model(2))
+    _, f = synth.make_pair(512, 512, 1, config_id=2, index=3, peak=8.0)
+    got = _fwd(f, m)
+    pts = [(0, 0), (511, 511), (0, 300), (255, 511), (260, 270), (130, 401)]
+    ref = oracle_uT_at(f, m, pts, m["T"] * (m["ks"] - 1))
+    g = np.array([got[0][p] for p in pts])
+    assert np.abs(g - ref).max() <= TOL * np.abs(ref).max(), (g, ref)
+
+
+def _bwd_case(m, f, gT, L=1, **opt):
+    """GPU and oracle gradients from the same FP32 states."""
+    _, st, ut = oracle.forward(f, m, want_states=True, want_utilde=True)
+    if m.get("reaction") == "projected":
+        assert np.abs(ut - 1.0).min() > 1e-5, "a state lies at the projection's kink"
+    st32 = st.astype(np.float32)
+    ref = oracle.backward(f, m, st32.astype(np.float64), gT, want_df=True)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(**opt)
+    states = _dev(st32)
+    dK, dW, dl, g0, gf = tnrd.backward(_dev(f), dm, states, _dev(gT), L=L, opts=o, want_u0=True,
+                                        want_f=True)
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy() for x in (dK, dW, dl, g0, gf)]
+    return got, ref
+
+
+def _check(got, ref, tol=TOL):
+    names = ["dK", "dW", "dlam", "g0", "gf"]
+    errs = {n: rel_inf(a, b) for n, a, b in zip(names, got, ref)}
+    print("rel errors", errs, flush=True)
+    for n in names:
+        assert errs[n] <= tol, (n, errs)
+
+
+@pytest.mark.parametrize("peak,index", [(6.0, 0), (255.0, 1)])
+def test_projected_backward(peak, index):
+    """Projected model (5 stages, 24 5x5): dK, dW, dlambda, dl/du_0 and dl/df."""
+    print(f"[projected bwd peak={peak}]", flush=True)
+    m = synth.config_model(6)
+    pairs = [synth.make_pair(40, 36, 1, config_id=6, index=index + 10 * n, peak=peak)
+             for n in range(2)]
+    f = np.stack([p[1] for p in pairs])
+    u = np.stack([p[0] for p in pairs])
+    uT = oracle.forward(f, m)
+    gT = (uT - u) * (2.0 / u.size)
+    _check(*_bwd_case(m, f, gT))
+
+
+def test_projected_backward_7x7_model():
+    m = _projected(synth.config_model(3))
+    pairs = [synth.make_pair(33, 41, 1, config_id=3, index=80 + n, peak=12.0) for n in range(2)]
+    f = np.stack([p[1] for p in pairs])
+    gT = np.random.default_rng(3).standard_normal(f.shape)
+    _check(*_bwd_case(m, f, gT))
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_full_input_gradient_prox_model(cfg):
+    """dl/df of the paper's (prox) model: u_0 = f plus each prox's explicit f,
+    for the training loss mean((u_T - u_gt)^2).  (With a random dl/du_T instead,
+    dlambda = <g, x_l> is about 100 times smaller than the sum of its terms'
+    magnitudes, 5 times more cancellation than for this loss, and FP32
+    rounding of the terms moves it by ~1e-4 of itself.)"""
+    m = synth.config_model(cfg)
+    pairs = [synth.make_pair(37, 45, 1, config_id=cfg, index=90 + n) for n in range(2)]
+    f = np.stack([p[1] for p in pairs])
+    u = np.stack([p[0] for p in pairs])
+    gT = (oracle.forward(f, m) - u) * (2.0 / u.size)
+    _check(*_bwd_case(m, f, gT))
+
+
+def test_grad_f_with_recompute_and_without_grad_u0():
+    """grad_f alone (no grad_u0 buffer) and with checkpointing gives the same bits."""
+    m = synth.config_model(1)
+    f = np.stack([synth.make_pair(30, 34, 1, config_id=1, index=95 + n)[1] for n in range(2)])
+    gT = np.random.default_rng(5).standard_normal(f.shape).astype(np.float32)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd, gd = _dev(f), _dev(gT)
+    outs = []
+    for s in (1, 2):
+        o = tnrd.default_opts(recompute_every=s)
+        _, states = tnrd.forward(fd, dm, want_states=True, opts=o)
+        outs.append([x.cpu() for x in tnrd.backward(fd, dm, states, gd, opts=o, want_f=True)])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_autograd_gradient_for_f():
+    """f.requires_grad: loss.backward() fills f.grad with dl/df from tnrd_backward."""
+    m = synth.config_model(6)
+    u, f = synth.make_pair(36, 40, 1, config_id=6, index=99, peak=30.0)
+    fd = _dev(f).requires_grad_(True)
+    filt, w, lam = _dev(m["filters"]), _dev(m["rbf_w"]), _dev(m["lam"])
+    uT = tnrd_apply(fd, filt, w, lam, reaction="projected", proj_c=1.0)
+    loss = ((uT - _dev(u)) ** 2).mean()
+    loss.backward()
+    gT = (2.0 / u.size) * (uT.detach() - _dev(u))
+    dm = tnrd.DeviceModel.from_numpy(m)
+    _, states = tnrd.forward(fd.detach()[None], dm, want_states=True)
+    *_, gf = tnrd.backward(fd.detach()[None], dm, states, gT[None].contiguous(), want_f=True)
+    torch.testing.assert_close(fd.grad, gf[0], rtol=0, atol=0)
+
+
+def test_batched_mixes_reactions():
+    """One uneven batch with a prox model (L = 1) and a projected model (L = 2):
+    each image equals its own single-image forward."""
+    mp = synth.config_model(1)
+    mq = _projected(synth.config_model(1, look=2))
+    dms = [tnrd.DeviceModel.from_numpy(mp, L=1), tnrd.DeviceModel.from_numpy(mq, L=2)]
+    sizes, looks = [(64, 70), (40, 90), (75, 33), (50, 50)], [1, 2, 2, 1]
+    fs = [_dev(synth.make_pair(h, w, L, config_id=1, index=120 + i, peak=8.0 if L == 2 else None)[1])
+          for i, ((h, w), L) in enumerate(zip(sizes, looks))]
+    outs, _ = tnrd.forward_batched(fs, looks, dms, opts=tnrd.default_opts(use_graph=0))
+    torch.cuda.synchronize()
+    fo = tnrd.default_opts(tile_h=32, tile_w=32, wg_waves=8, impl=tnrd.IMPL_FUSED)
+    for b, L in enumerate(looks):
+        ref = tnrd.forward(fs[b][None].contiguous(), dms[L - 1], L=L, opts=fo)
+        torch.testing.assert_close(outs[b], ref[0], rtol=0, atol=0)
+    # the projected images really are projected, the prox ones are not
+    assert outs[1].min().item() >= 1.0 and outs[2].min().item() >= 1.0
