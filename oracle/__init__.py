@@ -174,12 +174,13 @@ def prox_df(ut: float, f: float, lam: float) -> float:
     return float(_load().oracle_prox_df(float(ut), float(f), float(lam)))
 
 
-REACTIONS = {"prox": 0, "projected": 1}
+REACTIONS = {"prox": 0, "projected": 1, "l2": 2}
 
 
 def _reaction(model):
     """(reaction code, projection threshold c) of a model dict: reaction
-    "prox" (default, eq. diffusionprocessfinal) or "projected" (eq. diffusion_backP)."""
+    "prox" (default, eq. diffusionprocessfinal), "projected" (eq. diffusion_backP)
+    or "l2" (gradient step on (lambda/2)||u - f||^2, eq. diffusion with G = 0)."""
     return REACTIONS[model.get("reaction", "prox")], float(model.get("proj_c", 1.0))
 
 

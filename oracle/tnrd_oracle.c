@@ -24,6 +24,10 @@
  *     ut  = u_{t-1} - ( x + (l / u_{t-1}) (1 - f^2 / u_{t-1}^2) )
  *     u_t = max(ut, c)
  *
+ *   quadratic data term (Sec. 2.2.1, eq. diffusion with G = 0, D = l/2 ||u - f||^2,
+ *   psi = l (u - f): the Gaussian-denoising reaction of the TNRD framework):
+ *     u_t = u_{t-1} - ( x + l (u_{t-1} - f) )
+ *
  * Readings of points the paper leaves open (listed with reasons in the design notes):
  *   - u_0 = f (the paper leaves the initial state I_0 open);
  *   - K_i is a true convolution: the kernel is flipped (the paper defines k*u as
@@ -245,8 +249,9 @@ static const double *rbfw(const double *w, int t, int i, int Nk, int Nrbf)
 }
 
 /* Reaction of a stage: 0 = proximal step of eq. diffusionprocessfinal,
- * 1 = gradient step and projection max(., c) of eq. diffusion_backP. */
-enum { REACT_PROX = 0, REACT_PROJECTED = 1 };
+ * 1 = gradient step and projection max(., c) of eq. diffusion_backP,
+ * 2 = gradient step on the quadratic data term (l/2) ||u - f||^2. */
+enum { REACT_PROX = 0, REACT_PROJECTED = 1, REACT_L2 = 2 };
 
 /* One stage on one image: computes ut (length H*W) and u_next from u_prev. */
 static void stage_forward(const double *u_prev, const double *f, int H, int W, int t,
@@ -273,6 +278,9 @@ static void stage_forward(const double *u_prev, const double *f, int H, int W, i
         if (reaction == REACT_PROJECTED) {
             ut[p] = u_prev[p] - (x[p] + oracle_psi(u_prev[p], f[p], lam[t]));
             u_next[p] = ut[p] > cproj ? ut[p] : cproj;
+        } else if (reaction == REACT_L2) {
+            ut[p] = u_prev[p] - (x[p] + lam[t] * (u_prev[p] - f[p]));
+            u_next[p] = ut[p];
         } else {
             ut[p] = u_prev[p] - x[p];
             u_next[p] = oracle_prox(ut[p], f[p], lam[t]);
@@ -349,6 +357,8 @@ void oracle_forward(const double *f, int N, int H, int W, int T, int Nk, int ks,
  * Projected variant (eq. diffusion_backP): the projection's derivative is
  * m = 1 where ut > c and 0 elsewhere, e = m . g, dlam^t = -<e, d psi / d lambda>,
  * and the reaction adds -(d psi / du)(u_{t-1}) . e to g_{t-1}.
+ * Quadratic data term: e = g, dlam^t = -<e, u_{t-1} - f>, the reaction adds
+ * -lambda e to g_{t-1}, and u_t depends on f explicitly through +lambda f.
  */
 void oracle_backward_ex(const double *f, int N, int H, int W, int T, int Nk, int ks, int Nrbf,
                         double mu0, double step, double sigma,
@@ -392,6 +402,12 @@ void oracle_backward_ex(const double *f, int N, int H, int W, int T, int Nk, int
                     e[p] = ut[p] > cproj ? g[p] : 0.0;
                     dl -= e[p] * oracle_psi_dlam(uprev[p], fi[p]);
                     fexp[p] -= e[p] * oracle_psi_df(uprev[p], fi[p], lam[t]);
+                }
+            } else if (reaction == REACT_L2) {
+                for (size_t p = 0; p < n; ++p) {
+                    e[p] = g[p];
+                    dl -= e[p] * (uprev[p] - fi[p]);
+                    fexp[p] += e[p] * lam[t];
                 }
             } else {
                 /* prox backward */
@@ -448,6 +464,7 @@ void oracle_backward_ex(const double *f, int N, int H, int W, int T, int Nk, int
             for (size_t p = 0; p < n; ++p) {
                 g[p] = e[p] - gacc[p];
                 if (reaction == REACT_PROJECTED) g[p] -= oracle_psi_du(uprev[p], fi[p], lam[t]) * e[p];
+                if (reaction == REACT_L2) g[p] -= lam[t] * e[p];
             }
         }
         if (g0) memcpy(g0 + (size_t)img * n, g, sizeof(double) * n);

@@ -248,3 +248,80 @@ def test_full_input_gradient_zero_weights_prox_closed_form():
     _, states = oracle.forward(f, m, want_states=True)
     *_, gf = oracle.backward(f, m, states, gT, want_df=True)
     np.testing.assert_allclose(gf, gT, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- quadratic data term
+# The TNRD framework's Gaussian-denoising reaction (Sec. 2.2.1, eq. diffusion with
+# G = 0, D = (lambda/2) ||u - f||^2, psi = lambda (u - f)).
+def _l2(m):
+    m = {k: (np.array(v, dtype=np.float64) if isinstance(v, np.ndarray) else v) for k, v in m.items()}
+    m["reaction"] = "l2"
+    return m
+
+
+def test_l2_stage_is_gradient_step_on_full_energy():
+    """Stage 2 (from u_1, where the data term's gradient is not zero) is
+    u_1 - grad [E_filters + (lam/2)||u - f||^2](u_1), the gradient by central
+    differences of an energy built from scipy convolutions and erf."""
+    g = _rng(11)
+    H, W = 8, 7
+    m = _l2(_tiny(T=2, Nk=2, ks=5, seed=9, w_std=3.0))
+    f = g.uniform(0, 255, (H, W))
+    lam = float(m["lam"][1])
+    K, Wt = m["filters"][1], m["rbf_w"][1]
+
+    def energy(uu):
+        return (sum(_rho(ndi.convolve(uu, K[i], mode="reflect"), Wt[i], -310, 10, 10).sum()
+                    for i in range(K.shape[0])) + 0.5 * lam * ((uu - f) ** 2).sum())
+
+    uT, states = oracle.forward(f, m, want_states=True)
+    u1 = states[1]
+    assert np.abs(u1 - f).max() > 1e-3  # stage 1 moved away from f
+    h = 1e-3
+    grad = np.empty_like(f)
+    for idx in np.ndindex(H, W):
+        up, um = u1.copy(), u1.copy()
+        up[idx] += h
+        um[idx] -= h
+        grad[idx] = (energy(up) - energy(um)) / (2 * h)
+    np.testing.assert_allclose(uT, u1 - grad, rtol=0, atol=1e-6)
+
+
+def test_l2_zero_weights_closed_form():
+    """Zero weights from u_0 = f: psi(f) = 0, so u_t = f; the backward gives
+    dlambda = 0, g_{t-1} = (1 - lam_t) g_t and dl/df = g_0 + sum_t lam_t g_t."""
+    g = _rng(12)
+    f = g.uniform(0, 255, (1, 9, 8))
+    m = _l2(_tiny(T=3, Nk=2, ks=3, seed=10, lam=(0.05, 0.4)))
+    m["rbf_w"][:] = 0
+    gT = g.standard_normal(f.shape)
+    _, states = oracle.forward(f, m, want_states=True)
+    for t in range(4):
+        np.testing.assert_array_equal(states[t], f)
+    dK, dW, dl, g0, gf = oracle.backward(f, m, states, gT, want_df=True)
+    assert np.abs(dl).max() == 0.0 and np.abs(dK).max() == 0.0
+    gt, acc = gT[0].copy(), np.zeros_like(gT[0])
+    for t in range(2, -1, -1):
+        acc += m["lam"][t] * gt
+        gt = (1 - m["lam"][t]) * gt
+    np.testing.assert_allclose(g0[0], gt, rtol=1e-13)
+    np.testing.assert_allclose(gf[0], gt + acc, rtol=1e-13)
+
+
+def test_l2_backward_matches_finite_differences():
+    g = _rng(13)
+    f = g.uniform(0, 255, (2, 7, 8))
+    m = _l2(_tiny(T=2, Nk=2, ks=3, seed=11, w_std=2.0, lam=(0.05, 0.5)))
+    gT = g.standard_normal(f.shape)
+    d = g.standard_normal(f.shape)
+    _, states = oracle.forward(f, m, want_states=True)
+    dK, dW, dl, _, gf = oracle.backward(f, m, states, gT, want_df=True)
+    for which, idx, grad in [("filters", (0, 1, 0, 2), dK), ("rbf_w", (1, 1, 30), dW),
+                             ("lam", (0,), dl), ("lam", (1,), dl)]:
+        an = grad[idx]
+        e1 = abs(_fd_param(f, m, gT, which, idx, 1e-3) - an)
+        e2 = abs(_fd_param(f, m, gT, which, idx, 1e-4) - an)
+        assert e2 <= max(1e-7 * max(1.0, abs(an)), 2e-2 * e1 + 1e-9), (which, idx, an, e1, e2)
+    an = float((gf * d).sum())
+    fd = (_loss(f + 1e-4 * d, m, gT) - _loss(f - 1e-4 * d, m, gT)) / 2e-4
+    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
