@@ -12,6 +12,8 @@ Extra legs reported on the same JSON line (each its own workload):
   mixed    8 x 2048 x 2048 with BF16/FP16 filter-bank operands
   projected  the paper's comparison model (projection onto u >= 1), 8 x 512 x 512,
            5 stages of 24 5x5 filters, forward and forward + backward with dl/df
+  denoise  the framework's Gaussian-denoising reaction (quadratic data term),
+           8 x 512 x 512, 5 stages of 48 7x7 filters
   peaks    measured copy, matrix, vector-FMA and exp2 throughput; the legs' rates
            against them ("fractions")
 
@@ -48,7 +50,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--impl", default="auto", choices=["auto", "fused", "split"])
-    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed,projected,peaks")
+    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed,projected,denoise,peaks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of known "
@@ -382,6 +384,64 @@ def leg_projected(args):
     return res
 
 
+def leg_denoise(args):
+    """The framework's Gaussian-denoising reaction (quadratic data term, a gradient
+    step) at TNRD's own shape, 5 stages of 48 7x7 filters: 8 images of 512 x 512
+    with Gaussian noise of sigma 25, forward and forward + backward."""
+    import torch
+    from paper_1702_07482_amd import synth, tnrd
+
+    N, H, W = 8, 512, 512
+    m = synth.config_model(7)
+    T = m["filters"].shape[0]
+    pairs = [synth.make_gaussian_pair(H, W, 25.0, config_id=7, index=300 + n) for n in range(N)]
+    fd = torch.from_numpy(np.stack([p[1] for p in pairs])).cuda().contiguous()
+    ud = torch.from_numpy(np.stack([p[0] for p in pairs])).cuda().contiguous()
+    dm = tnrd.DeviceModel.from_numpy(m)
+    mm = dm.abi()
+    o = tnrd.default_opts()
+    nbf = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 0)
+    nbb = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 1)
+    wsf = torch.empty(nbf, dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(nbb, dtype=torch.uint8, device="cuda")
+    u = torch.empty_like(fd)
+    states = torch.empty((T + 1, N, H, W), dtype=torch.float32, device="cuda")
+    g = torch.empty_like(fd)
+    dK, dW, dl = torch.empty_like(dm.filters), torch.empty_like(dm.rbf_w), torch.empty_like(dm.lam)
+
+    def fwd(st=None):
+        r = tnrd.tnrd_forward(fd, N, H, W, 1, mm, u, st, o, wsf, nbf)
+        if r != 0:
+            raise RuntimeError(tnrd.status_str(r))
+
+    def fwd_bwd():
+        fwd(states)
+        torch.sub(u, ud, out=g)
+        g.mul_(2.0 / g.numel())
+        r = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, None, o, wsb, nbb)
+        if r != 0:
+            raise RuntimeError(tnrd.status_str(r))
+
+    res = {}
+    for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = _events()
+        reps = 5
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        res[f"{name}_mpst_s"] = N * H * W * T / 1e6 / (ms / 1e3)
+        res[f"{name}_ms"] = ms
+    res["workload"] = ("quadratic data term (Gaussian denoising reaction): 8 x 512 x 512, noise sigma 25, "
+                       "5 stages x 48 7x7, lambda 0.1, FP32")
+    return res
+
+
 def leg_peaks(args):
     """Measured throughput of the units the kernels run on (copy, FP32 and BF16
     matrix instructions, FP32 vector FMA, hardware exp2), from the library's probes."""
@@ -515,6 +575,8 @@ def main():
         out["mixed"] = leg_mixed(args)
     if "projected" in legs:
         out["projected"] = leg_projected(args)
+    if "denoise" in legs:
+        out["denoise"] = leg_denoise(args)
     if "peaks" in legs:
         out["peaks"] = leg_peaks(args)
         out["fractions"] = fractions(out)

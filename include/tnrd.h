@@ -77,10 +77,14 @@ typedef enum tnrd_impl {
  *                         step on the data term followed by the projection onto u >= c,
  *                         ut_t = u_{t-1} - (sum_i K_i^T v_i + (l/u_{t-1})(1 - f^2/u_{t-1}^2)),
  *                         u_t = max(ut_t, c), c = proj_c (the paper uses c = 1).  Its backward
- *                         takes the projection's derivative as 1 where ut_t > c, else 0. */
+ *                         takes the projection's derivative as 1 where ut_t > c, else 0.
+ *   TNRD_REACT_L2         the framework's Gaussian-denoising reaction (Sec. 2.2.1, eq. diffusion
+ *                         with G = 0 and D = (l/2)||u - f||^2): a gradient step,
+ *                         u_t = u_{t-1} - (sum_i K_i^T v_i + l (u_{t-1} - f)); f may be any sign. */
 typedef enum tnrd_reaction {
     TNRD_REACT_PROX = 0,
-    TNRD_REACT_PROJECTED = 1
+    TNRD_REACT_PROJECTED = 1,
+    TNRD_REACT_L2 = 2
 } tnrd_reaction;
 
 /* Per-stage parameters Theta^t = {lambda^t, phi_i^t, k_i^t} (Sec. 2.2.2, eq. learning). */
@@ -161,7 +165,7 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
  *                                       stage, dl/du_t times the reaction's explicit
  *                                       derivative in f (prox: 4 l f / s with
  *                                       s = sqrt(ut^2 + 8(1+2l) l f^2); projected:
- *                                       2 l f / u_{t-1}^3 where ut_t > c, else 0)
+ *                                       2 l f / u_{t-1}^3 where ut_t > c, else 0; l2: l)
  * lambda^t must be > 0.  Results are deterministic: the same inputs give the
  * same bits for every recompute_every.  Errors as tnrd_forward, and
  * TNRD_ERR_ARG for NULL states/grad pointers or grad_f aliasing grad_u0. */

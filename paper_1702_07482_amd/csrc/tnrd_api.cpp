@@ -45,7 +45,9 @@ int check_model(const tnrd_model *m)
     if (!(m->rbf_sigma > 0.f) || !isfinite(m->rbf_sigma)) return TNRD_ERR_ARG;
     if (!isfinite(m->rbf_mu0)) return TNRD_ERR_ARG;
     if (m->L < 0) return TNRD_ERR_ARG;
-    if (m->reaction != TNRD_REACT_PROX && m->reaction != TNRD_REACT_PROJECTED) return TNRD_ERR_ARG;
+    if (m->reaction != TNRD_REACT_PROX && m->reaction != TNRD_REACT_PROJECTED &&
+        m->reaction != TNRD_REACT_L2)
+        return TNRD_ERR_ARG;
     if (m->reaction == TNRD_REACT_PROJECTED && (!(m->proj_c > 0.f) || !isfinite(m->proj_c)))
         return TNRD_ERR_ARG;
     if (m->ksize != 3 && m->ksize != 5 && m->ksize != 7) return TNRD_ERR_UNSUPPORTED;

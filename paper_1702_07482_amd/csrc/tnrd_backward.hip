@@ -179,23 +179,26 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
                     float u2 = uv[k] * uv[k], f2 = ff[k] * ff[k];
                     float den = fmaf(c1, u2, c2 * f2);  // u s
                     su[ly * L.ldw + lx] = uu[k];
-                    const bool proj = io.react == 1;
-                    // e = y g: prox y = u_t^2 / (u_t s); projected y = [u_t > c]
-                    const float ev = proj ? (uv[k] > io.proj_c ? gg[k] : 0.f) : u2 / den * gg[k];
+                    const bool proj = io.react == 1, quad = io.react == 2;
+                    // e = y g: prox y = u_t^2 / (u_t s); projected y = [u_t > c]; quadratic y = 1
+                    const float ev = proj ? (uv[k] > io.proj_c ? gg[k] : 0.f)
+                                     : quad ? gg[k] : u2 / den * gg[k];
                     se[ly * L.ldw + lx] = ev;
                     int yi = ty0 - R + ly, xi = tx0 - R + lx;
                     bool own = ly >= R && ly < R + Th && lx >= R && lx < R + Tw && yi < H && xi < W;
                     if (own) {
                         // dl/dlambda over the tile's own pixels: prox g 2 (f - u)(f + u) / s (the
                         // factored difference keeps its precision when u ~ f); projected
-                        // -e (d psi/dl)(u_{t-1})
-                        dl_acc = proj ? fmaf(-ev, proj_psi_dlam(uu[k], ff[k]), dl_acc)
-                                      : fmaf(gg[k], 2.f * (ff[k] - uv[k]) * (ff[k] + uv[k]) * uv[k] / den, dl_acc);
+                        // -e (d psi/dl)(u_{t-1}); quadratic -e (u_{t-1} - f)
+                        dl_acc = proj   ? fmaf(-ev, proj_psi_dlam(uu[k], ff[k]), dl_acc)
+                                 : quad ? fmaf(-ev, uu[k] - ff[k], dl_acc)
+                                        : fmaf(gg[k], 2.f * (ff[k] - uv[k]) * (ff[k] + uv[k]) * uv[k] / den, dl_acc);
                         if (io.gf) {
                             // explicit f-dependence of u_t: prox du/df = 4 l f / s = 4 l f u / (u s);
-                            // projected -e (d psi/df)(u_{t-1})
-                            const float fx = proj ? -ev * proj_psi_df(uu[k], ff[k], lam)
-                                                  : gg[k] * (4.f * lam * ff[k] * uv[k] / den);
+                            // projected -e (d psi/df)(u_{t-1}); quadratic l e
+                            const float fx = proj   ? -ev * proj_psi_df(uu[k], ff[k], lam)
+                                             : quad ? lam * ev
+                                                    : gg[k] * (4.f * lam * ff[k] * uv[k] / den);
                             float *gp = io.gf + img * plane + (size_t)yi * W + xi;
                             *gp = io.gf_first ? fx : *gp + fx;
                         }

@@ -116,10 +116,12 @@ __device__ __forceinline__ float proj_psi_df(float u, float f, float lam)
 // Reaction step of a stage from u_{t-1} and the diffusion force x = sum_i K_i^T v_i:
 // react 0: u_t = prox(u_{t-1} - x)                      (eq. diffusionprocessfinal)
 // react 1: u_t = max(u_{t-1} - (x + psi(u_{t-1})), c)   (eq. diffusion_backP)
+// react 2: u_t = u_{t-1} - (x + l (u_{t-1} - f))         (eq. diffusion, quadratic data term)
 __device__ __forceinline__ float reaction_step(int react, float u_prev, float x, float f, float lam,
                                                float c)
 {
     if (react == 1) return fmaxf(u_prev - (x + proj_psi(u_prev, f, lam)), c);
+    if (react == 2) return u_prev - fmaf(lam, u_prev - f, x);
     return prox(u_prev - x, f, lam);
 }
 

@@ -187,9 +187,11 @@ __device__ __forceinline__ void fused_tile(
                 if (i < n) {
                     int ly = i / luw, lx = i - ly * luw;
                     float u2 = uu[k] * uu[k];
-                    // prox: y = du_t/d(ut_t); projected: 1 where ut_t > c (u_t > c), else 0
-                    float y = io.react == 1 ? (uu[k] > io.proj_c ? 1.f : 0.f)
-                                            : u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
+                    // prox: y = du_t/d(ut_t); projected: 1 where ut_t > c (u_t > c), else 0;
+                    // quadratic data term: 1
+                    float y = io.react == 1   ? (uu[k] > io.proj_c ? 1.f : 0.f)
+                              : io.react == 2 ? 1.f
+                                              : u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
                     float ev = y * gg[k];
                     se[ly * L.ldw + lx] = ev;
                     emax = fmaxf(emax, fabsf(ev));
@@ -628,11 +630,13 @@ __device__ __forceinline__ void fused_tile(
             const size_t pix = (size_t)yi * W + xi;
             if (BWD) {
                 // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1);
-                // the projected reaction adds -(d psi/du)(u_{t-1}) e
+                // the projected reaction adds -(d psi/du)(u_{t-1}) e, the quadratic one -l e
                 const float ev = se[(y + 2 * R) * L.ldw + x + 2 * R];
                 float gv = ev - xs * einv;
                 if (io.react == 1)
                     gv -= proj_psi_du(su[(y + 2 * R) * L.ldw + x + 2 * R], fn[pix], lam) * ev;
+                else if (io.react == 2)
+                    gv -= lam * ev;
                 uo[pix] = gv;
             } else {
                 const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];

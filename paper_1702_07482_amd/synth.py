@@ -75,6 +75,14 @@ def make_model(T: int, Nk: int, ks: int, rng: np.random.Generator, Nrbf: int = 6
     }
 
 
+def make_gaussian_pair(H: int, W: int, sigma: float, config_id: int, index: int = 0):
+    """(clean u_gt, noisy f = u_gt + N(0, sigma^2)) for one image, both FP32 H x W
+    (f may leave [0, 255] and take either sign)."""
+    u = make_clean(H, W, rng_for(config_id, 0, index))
+    n = rng_for(config_id, 1, index).normal(0.0, sigma, size=u.shape)
+    return u, (u.astype(np.float64) + n).astype(np.float32)
+
+
 def make_pair(H: int, W: int, L: int, config_id: int, index: int = 0, amplitude: bool = False,
               peak: float | None = None):
     """(clean u_gt, speckled f) for one image, both FP32 H x W.  With ``peak``
@@ -102,6 +110,9 @@ CONFIGS = {
     # the paper's comparison of the projected model: 5 stages of 5x5 filters, L = 1
     6: dict(name="projected variant 1x128x128, L=1, 5 stages x 24 5x5, c = 1", T=5, Nk=24, ks=5,
             sizes=[(128, 128)], looks=[1], reaction="projected"),
+    # the framework's Gaussian-denoising reaction: 5 stages of 48 7x7 filters, noise sigma 25
+    7: dict(name="quadratic data term (Gaussian denoising), 5 stages x 48 7x7, lambda = 0.1", T=5,
+            Nk=48, ks=7, sizes=[(512, 512)], looks=[1], reaction="l2", lam=0.1),
 }
 
 C4_SIZES = [(256, 256), (384, 512), (512, 512), (1024, 768)]
@@ -118,7 +129,7 @@ def c4_batch(n_images: int = 64):
 
 def config_model(config_id: int, look: int = 0) -> dict:
     c = CONFIGS[config_id]
-    m = make_model(c["T"], c["Nk"], c["ks"], rng_for(config_id, 2, look))
+    m = make_model(c["T"], c["Nk"], c["ks"], rng_for(config_id, 2, look), lam=c.get("lam", 1.0))
     if c.get("reaction", "prox") != "prox":
         m["reaction"] = c["reaction"]
         m["proj_c"] = 1.0

@@ -29,8 +29,8 @@ TNRD_ERR_HIP = -4
 TNRD_ERR_UNSUPPORTED = -5
 
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
-REACT_PROX, REACT_PROJECTED = 0, 1
-REACTIONS = {"prox": REACT_PROX, "projected": REACT_PROJECTED}
+REACT_PROX, REACT_PROJECTED, REACT_L2 = 0, 1, 2
+REACTIONS = {"prox": REACT_PROX, "projected": REACT_PROJECTED, "l2": REACT_L2}
 IMPL_AUTO, IMPL_FUSED, IMPL_SPLIT = 0, 1, 2
 
 

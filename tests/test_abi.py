@@ -62,7 +62,7 @@ def test_default_opts():
     (dict(step=-1.0), tnrd.TNRD_ERR_ARG),
     (dict(sigma=float("nan")), tnrd.TNRD_ERR_ARG),
     (dict(L=4), tnrd.TNRD_ERR_ARG),  # model for L = 4, image has L = 1
-    (dict(reaction=2), tnrd.TNRD_ERR_ARG),
+    (dict(reaction=3), tnrd.TNRD_ERR_ARG),
     (dict(reaction=-1), tnrd.TNRD_ERR_ARG),
     (dict(reaction=1, proj_c=0.0), tnrd.TNRD_ERR_ARG),
     (dict(reaction=1, proj_c=float("inf")), tnrd.TNRD_ERR_ARG),

@@ -195,3 +195,40 @@ def test_batched_mixes_reactions():
         torch.testing.assert_close(outs[b], ref[0], rtol=0, atol=0)
     # the projected images really are projected, the prox ones are not
     assert outs[1].min().item() >= 1.0 and outs[2].min().item() >= 1.0
+
+
+# ---------------------------------------------------------------- quadratic data term
+# The framework's Gaussian-denoising reaction (Sec. 2.2.1, eq. diffusion with G = 0,
+# D = (lambda/2)||u - f||^2): inputs with Gaussian noise of sigma 25, either sign.
+@pytest.mark.parametrize("impl", [tnrd.IMPL_FUSED, tnrd.IMPL_SPLIT])
+@pytest.mark.parametrize("shape", [(128, 128), (97, 131), (7, 7)])
+def test_l2_forward(impl, shape):
+    print(f"[l2 fwd impl={impl} shape={shape}]", flush=True)
+    m = synth.config_model(7)
+    _, f = synth.make_gaussian_pair(*shape, 25.0, config_id=7, index=shape[0])
+    ref_uT, ref_states = oracle.forward(f, m, want_states=True)
+    uT, states = _fwd(f, m, impl=impl, want_states=True)
+    assert rel_inf(uT, ref_uT) <= TOL
+    for t in range(ref_states.shape[0]):
+        assert rel_inf(states[t, 0], ref_states[t]) <= TOL, t
+
+
+def test_l2_forward_512_sampled():
+    m = synth.config_model(7)
+    _, f = synth.make_gaussian_pair(512, 512, 25.0, config_id=7, index=1)
+    got = _fwd(f, m)
+    pts = [(0, 0), (511, 511), (0, 300), (255, 511), (260, 270), (130, 401)]
+    ref = oracle_uT_at(f, m, pts, m["T"] * (m["ks"] - 1))
+    g = np.array([got[0][p] for p in pts])
+    assert np.abs(g - ref).max() <= TOL * np.abs(ref).max(), (g, ref)
+
+
+@pytest.mark.parametrize("shape,N", [((40, 36), 2), ((7, 9), 1)])
+def test_l2_backward(shape, N):
+    """dK, dW, dlambda, dl/du_0 and dl/df for mean((u_T - u_gt)^2)."""
+    m = synth.config_model(7)
+    pairs = [synth.make_gaussian_pair(*shape, 25.0, config_id=7, index=40 + n) for n in range(N)]
+    f = np.stack([p[1] for p in pairs])
+    u = np.stack([p[0] for p in pairs])
+    gT = (oracle.forward(f, m) - u) * (2.0 / u.size)
+    _check(*_bwd_case(m, f, gT))
