@@ -65,6 +65,9 @@ constexpr int POLY_MW = RBF_WIN + 1;      // centres on each side of j0 in the f
 constexpr int POLY_PAD = RBF_WIN + POLY_MW;  // zero padding of a weight row on each side
 
 __host__ __device__ inline int poly_intervals(int nrbf) { return nrbf + 2 * RBF_WIN + 2; }
+// Interval coordinate given to masked-off pixels: an integer far beyond every
+// table, so it clamps to the zero interval at the top end with d = 0.
+constexpr float POLY_OFF_MASKED = 1048576.f;
 
 // Influence evaluation of the fused stage kernel.
 enum RbfMethod { RBF_HORNER = 0, RBF_POLY = 1 };

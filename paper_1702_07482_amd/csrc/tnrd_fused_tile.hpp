@@ -41,9 +41,10 @@
 // in tile coordinates.  Shifting by b along the 16 pixels of a block is one DPP
 // row shift per register (row_shl b inside the block, row_shr 16 - b for the
 // part that lands in the block to the left), so the sum over b stays in
-// registers and each E row leaves P[e][a][qx + 2R] = sum_b Y_(a,b)[qx + b] in a
-// ring of LDS rows, every entry written once by the wave that owns row e (no
-// atomics, deterministic).  Output row y is X(y, x) = sum_a P[y + a][a][x + 2R].
+// registers and each E row e leaves its tap-row partials sum_b Y_(a,b)[qx + b] in a
+// ring of LDS rows indexed by the output row they feed, P[e - a][a][qx + 2R]; every
+// entry is written once, by the wave that owns row e (no atomics, deterministic).
+// Output row y is X(y, x) = sum_a P[y][a][x + 2R]: KS words of one ring slot.
 //
 // The border fold (K^T is the exact adjoint of "reflect, then convolve"): an
 // output pixel within R of the image border also receives X at its mirror
@@ -66,7 +67,7 @@ struct FusedLds {
     int tf_pitch;                // polynomial form: floats per filter (8 ni, padded to 4 mod 16 so
                                  // that the 4 filters a wave's lane groups read start in distinct banks)
     int w_pitch;                 // polynomial form: padded weight row staged in the P area
-    int p_off, pw, ring, p_size; // row partials: ring of `ring` E rows x KS tap rows x pw
+    int p_off, pw, ring, p_size; // row partials: ring of `ring` output rows x KS tap rows x pw
     int red_off;                 // 8 floats for workgroup reductions
     int dummy_off;               // 64 floats: target of the stores of masked-off lanes
     int total;
@@ -124,6 +125,7 @@ __device__ __forceinline__ void fused_tile(
     constexpr int KS2 = 4 * NMB;  // GEMM2 k-steps (4 filters each)
     constexpr int THREADS = 64 * NW;
     constexpr int RING = 2 * NW + 2 * R;
+    constexpr int PW = 16 * NB + 2 * R;  // P row pitch (fused_lds().pw)
     // output values a thread produces per round, at most: (NW + R) rows of a tile at most
     // 16 NB - 2R wide
     constexpr int PF = ((NW + R) * (16 * NB - 2 * R) + THREADS - 1) / THREADS;
@@ -428,16 +430,19 @@ __device__ __forceinline__ void fused_tile(
     };
 
     // Polynomial form: table reads of one filter group (the four filters of an
-    // accumulator register quad) into one of two buffers.
+    // accumulator register quad) into one of two buffers.  The interval index is
+    // s = z / step - mu0 / step + W + 1 rounded; a lane whose pixel is masked off
+    // takes scale 0 and offset POLY_OFF_MASKED instead, which selects the all-zero
+    // last interval, so its influence comes out exactly 0 with no select.
     float dq[2][4];
     floatx4 lo[2][4], hi[2][4];
-    auto fetch = [&](const floatx4 *acc1, int mb, int slot) {
+    auto fetch = [&](const floatx4 *acc1, int mb, int slot, float sscale, float soff) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float s = fmaf(acc1[mb][r], rb.inv_step, -rb.mu0_over_step);
+            const float s = fmaf(acc1[mb][r], sscale, soff);
             const float jr = rintf(s);
             dq[slot][r] = s - jr;
-            const int q = (int)__builtin_amdgcn_fmed3f(jr + (float)(RBF_WIN + 1), 0.f, (float)(L.ni - 1));
+            const int q = (int)__builtin_amdgcn_fmed3f(jr, 0.f, (float)(L.ni - 1));
             const float *cp = stab + (16 * mb + r) * L.tf_pitch + tab_g + 4 * q;
             lo[slot][r] = *reinterpret_cast<const floatx4 *>(cp);
             hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * L.ni);
@@ -461,7 +466,7 @@ __device__ __forceinline__ void fused_tile(
                 p = fmaf(p, d, l[0]);
                 // input-gradient mode: p = d phi / ds, so phi'(z) a = p a / step
                 if (BWD) p *= rb.inv_step * acca[mb][r];
-                acc1[mb][r] = valid ? p : 0.f;
+                acc1[mb][r] = p;  // 0 for a masked-off pixel (see fetch)
             }
         } else {
 #pragma unroll
@@ -513,8 +518,8 @@ __device__ __forceinline__ void fused_tile(
     // GEMM1 of the next block (en, cbn) into n1/na: influence, K^T GEMM and
     // the x-direction col2im.  xa[h] enters holding block cb-1's partial X (tap
     // rows a = 4h + g) and leaves holding block cb's; block cb-1 is complete
-    // then and goes to the P ring:
-    //   P[e mod RING][a][qx + 2R] = sum_b Y_(a,b)[qx + b]   (qx relative to the E row)
+    // then and goes to the P ring slot of output row e - a:
+    //   P[(e - a) mod RING][a][qx + 2R] = sum_b Y_(a,b)[qx + b]   (qx relative to the E row)
     // The scheduling fences split the work into NMB + 1 segments; in each, the
     // table reads of the next filter group and a third of the next GEMM1 are
     // in flight while the current group's influence and GEMM2 run.
@@ -543,13 +548,17 @@ __device__ __forceinline__ void fused_tile(
         floatx4 acc2[MB2];
 #pragma unroll
         for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // polynomial form: interval coordinate of this lane's pixel, or the
+        // masked-off coordinate
+        const float sscale = valid ? rb.inv_step : 0.f;
+        const float soff = valid ? (float)(RBF_WIN + 1) - rb.mu0_over_step : POLY_OFF_MASKED;
         gemm1_load(en, cbn);
-        if (POLY) fetch(c1, 0, 0);
+        if (POLY) fetch(c1, 0, 0, sscale, soff);
         gemm1_steps(0, K1 / NMB, n1, na);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int m = 1; m <= NMB; ++m) {
-            if (POLY && m < NMB) fetch(c1, m, m & 1);
+            if (POLY && m < NMB) fetch(c1, m, m & 1, sscale, soff);
             influence(c1, ca, m - 1, valid);
             gemm2_group(c1, m - 1, acc2);
             if (m < NMB) gemm1_steps(m * K1 / NMB, (m + 1) * K1 / NMB, n1, na);
@@ -576,57 +585,75 @@ __device__ __forceinline__ void fused_tile(
                 }
             }
         // branch-free stores: masked-off lanes write their own dummy word
-        const int prow = L.p_off + (e % RING) * KS * L.pw;
+        const int em = e % RING;  // wave-uniform
         const int dummy = L.dummy_off + lane;
 #pragma unroll
         for (int h = 0; h < HB; ++h) {
             const int a = 4 * h + g;
+            const int sl = em - a < 0 ? em - a + RING : em - a;
+            const int prow = L.p_off + (sl * KS + a) * PW;
             // block cb-1: output columns 16 (cb-1) + j; block -1 only reaches j >= 16 - 2R
             const bool ok_a = a < KS && (cb > 0 || j >= 16 - 2 * R);
-            lds[ok_a ? prow + a * L.pw + 16 * (cb - 1) + j + 2 * R : dummy] = xa[h];
-            if (cb == NB - 1) lds[a < KS ? prow + a * L.pw + 16 * cb + j + 2 * R : dummy] = xb[h];
+            lds[ok_a ? prow + 16 * (cb - 1) + j + 2 * R : dummy] = xa[h];
+            if (cb == NB - 1) lds[a < KS ? prow + 16 * cb + j + 2 * R : dummy] = xb[h];
             xa[h] = xb[h];
         }
     };
 
     // ---- gather X over the tap rows, fold the border ring, prox, store.
-    // Output row y needs the partials of E rows y .. y + 2R (the rows of its
-    // mirror position at a border lie in the same range).
+    // Output row y sums the KS tap rows of its ring slot.  Near the image border
+    // the pixel also receives X at its mirror position (a ring slot of the same
+    // round), and tap rows written by E rows outside the image count as zero.
     const float *fn = f;
     float *uo = io.out;
     const int y_lim = min(Th, H - ty0);
-    auto out_index = [&](int i, int y0, int &y, int &x) {
-        y = y0 + i / Tw;
-        x = i - (i / Tw) * Tw;
+    const int e_lo = max(0, R - ty0), e_hi = min(Eh, H - ty0 + R);
+    // the thread's p-th output of a round: row y0 + pdy[p], column pdx[p]
+    int pdy[PF], pdx[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+        const int i = tid + p * THREADS;
+        pdy[p] = i / Tw;
+        pdx[p] = i - pdy[p] * Tw;
+    }
+    auto slot_of = [&](int qy) {  // ring slot of output row qy (-RING < qy)
+        const int m = (qy + RING) % RING;
+        return sp + m * KS * PW;
     };
     auto produce = [&](int y0, int y1, const float *fpre) {
-        const int n = (y1 - y0) * Tw;
 #pragma unroll
         for (int p = 0; p < PF; ++p) {
-            const int i = tid + p * THREADS;
-            if (i >= n) break;
-            int y, x;
-            out_index(i, y0, y, x);
+            if (pdy[p] >= y1 - y0) break;
+            const int y = y0 + pdy[p], x = pdx[p];
             const int yi = ty0 + y, xi = tx0 + x;
             if (xi >= W) continue;
-            int qy[2] = {y, 0}, qx[2] = {x, 0};
-            int nqy = 1, nqx = 1;
-            if (yi < R) qy[nqy++] = -yi - 1 - ty0;
-            else if (yi >= H - R) qy[nqy++] = 2 * H - 1 - yi - ty0;
-            if (xi < R) qx[nqx++] = -xi - 1 - tx0;
-            else if (xi >= W - R) qx[nqx++] = 2 * W - 1 - xi - tx0;
             float xs = 0.f;
-            for (int iy = 0; iy < nqy; ++iy)
-                for (int ix = 0; ix < nqx; ++ix) {
-                    const int col = qx[ix] + 2 * R;
+            const bool fy = yi < R || yi >= H - R, fx = xi < R || xi >= W - R;
+            if (!(fy || fx)) {
+                // interior: every tap row of the slot comes from an E row inside the image
+                const float *b = slot_of(y) + x + 2 * R;
 #pragma unroll
-                    for (int a = 0; a < KS; ++a) {
-                        const int e = qy[iy] + a;
-                        const int ye = ty0 - R + e;
-                        if (e >= 0 && e < Eh && ye >= 0 && ye < H)
-                            xs += sp[((e % RING) * KS + a) * L.pw + col];
+                for (int a = 0; a < KS; ++a) xs += b[a * PW];
+            } else {
+                int qy[2] = {y, 0}, qx[2] = {x, 0};
+                int nqy = 1, nqx = 1;
+                if (yi < R) qy[nqy++] = -yi - 1 - ty0;
+                else if (yi >= H - R) qy[nqy++] = 2 * H - 1 - yi - ty0;
+                if (xi < R) qx[nqx++] = -xi - 1 - tx0;
+                else if (xi >= W - R) qx[nqx++] = 2 * W - 1 - xi - tx0;
+                for (int iy = 0; iy < nqy; ++iy) {
+                    const float *srow = slot_of(qy[iy]);
+                    for (int ix = 0; ix < nqx; ++ix) {
+                        const float *b = srow + qx[ix] + 2 * R;
+#pragma unroll
+                        for (int a = 0; a < KS; ++a) {
+                            const int e = qy[iy] + a;  // the E row that wrote tap row a
+                            const float v = b[a * PW];
+                            xs += (e >= e_lo && e < e_hi) ? v : 0.f;
+                        }
                     }
                 }
+            }
             const size_t pix = (size_t)yi * W + xi;
             if (BWD) {
                 // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1);
@@ -651,7 +678,6 @@ __device__ __forceinline__ void fused_tile(
     // ring holds 2 NW + 2R rows, so the rows one round writes never share a
     // slot with the rows the previous round's outputs still read.  GEMM1 of
     // the wave's next block is issued before the influence of the current one.
-    const int e_lo = max(0, R - ty0), e_hi = min(Eh, H - ty0 + R);
     const int rounds = (e_hi + NW - 1) / NW;
     int y_done = 0;
     bool have = false;
@@ -668,16 +694,11 @@ __device__ __forceinline__ void fused_tile(
         // f of this round's outputs, loaded ahead of the round's compute
         float fpre[PF];
         if (!BWD) {
-            const int n = (y_end - y0) * Tw;
 #pragma unroll
             for (int p = 0; p < PF; ++p) {
-                const int i = tid + p * THREADS;
                 fpre[p] = 0.f;
-                if (i < n) {
-                    int y, x;
-                    out_index(i, y0, y, x);
-                    if (tx0 + x < W) fpre[p] = fn[(size_t)(ty0 + y) * W + tx0 + x];
-                }
+                if (pdy[p] < y_end - y0 && tx0 + pdx[p] < W)
+                    fpre[p] = fn[(size_t)(ty0 + y0 + pdy[p]) * W + tx0 + pdx[p]];
             }
         }
         const int e = NW * k + wave;
