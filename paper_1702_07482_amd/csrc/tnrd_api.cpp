@@ -131,7 +131,15 @@ int checkpoint_slot(int t, int T, int s)
     return -1;
 }
 
-// Forward workspace: [flags 256 B][scratch][ping A][ping B]
+size_t prep_region_floats(const tnrd_model *m, const tnrd_opts &o, int impl, int window,
+                          int stages)
+{
+    if (impl != TNRD_IMPL_FUSED || o.prec != TNRD_PREC_FP32 || o.rbf_window >= 0) return 0;
+    if (!poly_form_ok(make_grid(m, window), 1)) return 0;
+    return (size_t)stages * fused_prep_floats(m->ksize, m->Nk, m->Nrbf);
+}
+
+// Forward workspace: [flags 256 B][scratch][ping A][ping B][prepared stage blocks]
 size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int impl)
 {
     size_t img = (size_t)N * H * W;
@@ -139,6 +147,8 @@ size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opt
                                              : fused_scratch_floats(N, H, W, m->Nk, o.prec);
     size_t bytes = WS_ALIGN + align_up(scratch * sizeof(float));
     if (m->T > 1) bytes += 2 * align_up(img * sizeof(float));
+    const int window = rbf_window_for(m, o.rbf_window);
+    bytes += align_up(prep_region_floats(m, o, impl, window, m->T) * sizeof(float));
     return bytes;
 }
 
@@ -161,7 +171,7 @@ int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream)
 // starting from u_start = u_{t_begin}; the output of stage t goes to dst(t).
 int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const tnrd_opts &o,
                int impl, int window, int t_begin, int t_end, const float *u_start,
-               float *const *dst, float *scratch, hipStream_t stream)
+               float *const *dst, float *scratch, float *prep, hipStream_t stream)
 {
     StageArgs s;
     s.u_cur = nullptr;
@@ -183,12 +193,23 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
     s.proj_c = m->proj_c;
     const float *cur = u_start;
     const size_t kk = (size_t)m->ksize * m->ksize;
+    // the fused FP32 form reads its stage constants ready-made: one launch
+    // prepares the blocks of all stages of this call
+    const bool use_prep = impl == TNRD_IMPL_FUSED && fused_uses_prep(s) && t_end > t_begin;
+    const size_t prep_sf = use_prep ? fused_prep_floats(m->ksize, m->Nk, m->Nrbf) : 0;
+    if (use_prep) {
+        if (!prep) return TNRD_ERR_WORKSPACE;
+        if (fused_prep(m->filters + (size_t)t_begin * m->Nk * kk, m->rbf_w + (size_t)t_begin * m->Nk * m->Nrbf,
+                       t_end - t_begin, m->ksize, m->Nk, s.grid, 0, prep, stream) != hipSuccess)
+            return TNRD_ERR_HIP;
+    }
     for (int t = t_begin; t < t_end; ++t) {
         s.u_prev = cur;
         s.u_next = dst[t - t_begin];
         s.filt = m->filters + (size_t)t * m->Nk * kk;
         s.rbfw = m->rbf_w + (size_t)t * m->Nk * m->Nrbf;
         s.lam = m->lambda + t;
+        s.prep = use_prep ? prep + (size_t)(t - t_begin) * prep_sf : nullptr;
         hipError_t e = impl == TNRD_IMPL_SPLIT ? split_stage(s, stream) : fused_stage(s, stream);
         if (e != hipSuccess) return TNRD_ERR_HIP;
         cur = s.u_next;
@@ -263,10 +284,13 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
                                                     : fused_scratch_floats(N, H, W, m->Nk, oo.prec);
     float *scratch = (float *)(base + WS_ALIGN);
     float *ping[2] = {nullptr, nullptr};
+    char *after = base + WS_ALIGN + align_up(scratch_floats * sizeof(float));
     if (m->T > 1) {
-        ping[0] = (float *)(base + WS_ALIGN + align_up(scratch_floats * sizeof(float)));
+        ping[0] = (float *)after;
         ping[1] = (float *)((char *)ping[0] + align_up(img * sizeof(float)));
+        after += 2 * align_up(img * sizeof(float));
     }
+    float *prep = prep_region_floats(m, oo, impl, window, m->T) ? (float *)after : nullptr;
 
     if (oo.validate) {
         st = run_domain_check(f, img, dflag, stream);
@@ -292,7 +316,7 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
             hipSuccess)
             return TNRD_ERR_HIP;
     }
-    st = run_stages(f, N, H, W, m, oo, impl, window, 0, T, f, dsts.data(), scratch, stream);
+    st = run_stages(f, N, H, W, m, oo, impl, window, 0, T, f, dsts.data(), scratch, prep, stream);
     if (st != TNRD_OK) return st;
     if (states) {
         float *last = states + (size_t)(tnrd_num_checkpoints(T, s) - 1) * img;

@@ -631,10 +631,13 @@ size_t al(size_t x) { return (x + AL - 1) / AL * AL; }
 
 struct BwdWs {
     float *g[2], *za, *dk_part, *dl_part, *dw_part, *seg;
+    float *prep_b;  // prepared blocks of the input-gradient stages (d phi / ds tables)
+    float *prep_f;  // prepared blocks of the recomputed forward stages (phi tables)
     size_t bytes;
 };
 
-BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s)
+// prep: floats of T stages' prepared blocks (0: the kernels build them)
+BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s, size_t prep)
 {
     BwdGeom gm = bwd_geom(N, H, W, BP_TH_MIN);  // the most tiles any launch uses
     const size_t kk = (size_t)m->ksize * m->ksize;
@@ -652,6 +655,8 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s)
     w.dl_part = take((size_t)gm.tiles);
     w.dw_part = take((size_t)gm.dw_grid * m->Nk * m->Nrbf);
     w.seg = s > 1 ? take(gm.img * (size_t)(s + 1)) : nullptr;
+    w.prep_b = prep ? take(prep) : nullptr;
+    w.prep_f = prep && s > 1 ? take(prep) : nullptr;
     w.bytes = off;
     return w;
 }
@@ -770,7 +775,8 @@ size_t backward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_op
 {
     if (!fused_supported(m->ksize, m->Nk, m->Nrbf, window, o.prec) || !bwd_lds_ok(m)) return 0;
     const int s = o.recompute_every < 1 ? 1 : o.recompute_every;
-    return bwd_ws_layout(nullptr, N, H, W, m, s).bytes;
+    return bwd_ws_layout(nullptr, N, H, W, m, s,
+                         prep_region_floats(m, o, TNRD_IMPL_FUSED, window, m->T)).bytes;
 }
 
 }  // namespace tnrd
@@ -798,7 +804,8 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
         return TNRD_ERR_UNSUPPORTED;
     const int T = m->T;
     const int s = oo.recompute_every < 1 ? 1 : oo.recompute_every;
-    const size_t need = bwd_ws_layout(nullptr, N, H, W, m, s).bytes;
+    const size_t prep = prep_region_floats(m, oo, TNRD_IMPL_FUSED, window, T);
+    const size_t need = bwd_ws_layout(nullptr, N, H, W, m, s, prep).bytes;
     if (N > 0 && (!ws || ws_bytes < need)) return TNRD_ERR_WORKSPACE;
     hipStream_t stream = (hipStream_t)stream_;
     const size_t kk = (size_t)m->ksize * m->ksize;
@@ -810,7 +817,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             return TNRD_ERR_HIP;
         return TNRD_OK;
     }
-    BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s);
+    BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep);
     BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W));
     const size_t img = gm.img;
     if (oo.validate) {
@@ -838,6 +845,12 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     ia.poly = oo.rbf_window < 0;
     ia.react = m->reaction;
     ia.proj_c = m->proj_c;
+    // the input-gradient stages' d phi / ds tables and filter operands, all stages at once
+    const bool use_prep = fused_uses_prep(ia);
+    const size_t prep_sf = use_prep ? fused_prep_floats(m->ksize, m->Nk, m->Nrbf) : 0;
+    if (use_prep && fused_prep(m->filters, m->rbf_w, T, m->ksize, m->Nk, ia.grid, 1, w.prep_b, stream) !=
+                        hipSuccess)
+        return TNRD_ERR_HIP;
 
     const float *g_cur = grad_uT;
     int ping = 0;
@@ -855,7 +868,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
                 ut[t] = dst[t - seg_lo - 1];
             }
             st = run_stages(f, N, H, W, m, oo, TNRD_IMPL_FUSED, window, seg_lo, seg_hi - 1,
-                            ut[seg_lo], dst.data(), nullptr, stream);
+                            ut[seg_lo], dst.data(), nullptr, w.prep_f, stream);
             if (st != TNRD_OK) return st;
         }
         for (int t = seg_hi; t > seg_lo; --t) {
@@ -890,6 +903,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
                 ia.rbfw = rbfw;
                 ia.lam = lam;
                 ia.za = loadza ? w.za : nullptr;
+                ia.prep = use_prep ? w.prep_b + (size_t)ts * prep_sf : nullptr;
                 if (fused_stage_input_grad(ia, stream) != hipSuccess) return TNRD_ERR_HIP;
             }
             if (bwd_params(loadza, io, gm, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) !=

@@ -25,7 +25,9 @@ size_t al(size_t x) { return (x + AL - 1) / AL * AL; }
 struct BatchPlan {
     int th, tw, nw;
     int ntiles;                  // items per stage
-    size_t off_imgs, off_models, off_items, off_tmp, desc_bytes, total;
+    int n_models;
+    size_t prep_stage;           // floats per prepared stage block (0: none)
+    size_t off_imgs, off_models, off_items, off_tmp, off_prep, desc_bytes, total;
     std::vector<size_t> tmp_off; // per image, from the workspace base
 };
 
@@ -91,6 +93,13 @@ int check_batch(int B, const tnrd_image *imgs, int n_models, const tnrd_model *m
         tmp_total += (size_t)imgs[b].H * imgs[b].W;
     }
     (void)tmp_total;
+    // prepared stage blocks of the polynomial form, [model][T][prep_stage]
+    plan.n_models = n_models;
+    plan.prep_stage = o.rbf_window < 0 && poly_form_ok(make_grid(&m, window), 1)
+                          ? fused_prep_floats(m.ksize, m.Nk, m.Nrbf)
+                          : 0;
+    plan.off_prep = off;
+    off += al((size_t)n_models * m.T * plan.prep_stage * sizeof(float));
     plan.total = off;
     return TNRD_OK;
 }
@@ -126,6 +135,9 @@ void build_descriptors(int B, const tnrd_image *imgs, int n_models, const tnrd_m
         dm[k].lam = models[k].lambda;
         dm[k].react = models[k].reaction;
         dm[k].proj_c = models[k].proj_c;
+        dm[k].prep = plan.prep_stage
+                         ? (float *)(ws + plan.off_prep) + (size_t)k * models[k].T * plan.prep_stage
+                         : nullptr;
     }
 }
 
@@ -144,7 +156,9 @@ BatchArgs make_args(const BatchPlan &plan, const tnrd_model &m, int window, int 
     a.Nrbf = m.Nrbf;
     const RbfGrid grid = make_grid(&m, window);
     a.rb = make_fused_rbf(grid);
-    a.poly = poly_form_ok(grid, automatic_window);
+    a.poly = poly_form_ok(grid, automatic_window) && plan.prep_stage > 0;
+    a.prep_stage = plan.prep_stage;
+    a.n_models = plan.n_models;
     return a;
 }
 

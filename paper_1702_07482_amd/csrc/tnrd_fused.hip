@@ -208,6 +208,11 @@ bool fused_supported(int ks, int nk, int nrbf, int window, int prec)
 
 size_t fused_scratch_floats(int, int, int, int, int) { return 0; }
 
+bool fused_uses_prep(const StageArgs &s)
+{
+    return s.prec == PREC_F32 && s.poly && poly_form_ok(s.grid, 1);
+}
+
 hipError_t fused_stage(const StageArgs &s, hipStream_t stream)
 {
     return fused_dispatch<MODE_FWD>(s, stream);
@@ -231,6 +236,10 @@ hipError_t batched_launch(const BatchArgs &a, int ks, int nw, hipStream_t stream
     const int rbfm = a.poly && lds_fits(ks, a.Nk, a.Nrbf, a.Th, a.Tw, nb, nw, MODE_FWD, RBF_POLY)
                          ? RBF_POLY
                          : RBF_HORNER;
+    if (rbfm == RBF_POLY) {
+        hipError_t e = batched_prep(a, ks, a.n_models, stream);
+        if (e != hipSuccess) return e;
+    }
     return batched_launch_impl(a, ks, nb, nw, rbfm, stream);
 }
 

@@ -100,6 +100,8 @@ struct FusedIO {
                           // pixels, layout of za_index()
     int react;            // tnrd_reaction of the stage
     float proj_c;         // projected reaction: threshold c
+    const float *prep;    // FP32 polynomial form: the stage's prepared table and operands
+                          // (k_prep_stage layout)
 };
 
 // Export of z = K u and a = K e for the parameter-gradient kernels: per pixel

@@ -116,6 +116,9 @@ __device__ __forceinline__ void fused_tile(
 {
     constexpr bool BWD = MODE == MODE_BWD_INPUT;
     constexpr bool POLY = RBFM == RBF_POLY;
+    // FP32 operands with the polynomial form: the coefficient table and the
+    // per-lane filter operands come ready-made from io.prep (k_prep_stage)
+    constexpr bool PREP = POLY && PREC == PREC_F32;
     const float *__restrict__ u_prev = io.u_prev;
     const float *__restrict__ f = io.f;
     using G = Geo<KS>;
@@ -148,7 +151,7 @@ __device__ __forceinline__ void fused_tile(
     // (1) the stage's filters: into the table area (polynomial form, whose
     // table is built only after the filters sit in registers) or the P area
     float *sf = POLY ? stab : sp;
-    {
+    if (!PREP) {
         const int nf = Nk * KK;
         for (int base = 0; base < nf; base += 8 * THREADS) {
             float v[8];
@@ -204,7 +207,7 @@ __device__ __forceinline__ void fused_tile(
     // (3) RBF weights.  Gaussian form: the table itself, rows zero padded by 2W
     // on both sides.  Polynomial form: rows zero padded by POLY_PAD, staged in
     // the P area for the coefficient build below.
-    {
+    if (!PREP) {
         float *dst = POLY ? sp : stab;
         const int pitch = POLY ? L.w_pitch : L.t_pitch;
         const int pad = POLY ? POLY_PAD : 2 * RBF_WIN;
@@ -239,7 +242,15 @@ __device__ __forceinline__ void fused_tile(
             __builtin_amdgcn_global_load_lds(u_prev + (size_t)yy * W + xx, su + c * 64, 4, 0, 0);
         }
     }
-    __syncthreads();
+    // (2c) prepared form: the coefficient table straight into LDS in 256-float
+    // chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk)
+    if (PREP) {
+        for (int c = wave; c * 256 < L.t_size; c += NW) {
+            const int k = c * 256 + 4 * lane;
+            if (k < L.t_size) __builtin_amdgcn_global_load_lds(io.prep + k, stab + c * 256, 16, 0, 0);
+        }
+    }
+    if (!PREP) __syncthreads();
 
     // Mixed-precision input gradient: e, a = K e and phi' a go through BF16/FP16
     // operands with a power-of-two tile scale that puts max|e| at 2^10 (FP16's
@@ -262,14 +273,29 @@ __device__ __forceinline__ void fused_tile(
         }
     }
 
-    // ---- filter operands in registers (from the staged copy)
+    // ---- filter operands in registers (from the staged copy, or the prepared
+    // per-lane operands: quad k4 of lane l at floats 4 (64 k4 + l) .. +3 after
+    // the table, GEMM1's a1[mb][s] first, then GEMM2's a2[mb2][s])
     float a1[NMB][KS1];
+    float a2[MB2][KS2];
+    if (PREP) {
+        constexpr int NA1 = NMB * KS1, NOPS = NA1 + MB2 * KS2, NQ = (NOPS + 3) / 4;
+        const floatx4 *opq = reinterpret_cast<const floatx4 *>(io.prep + L.t_size) + lane;
+        floatx4 q[NQ];
+#pragma unroll
+        for (int k4 = 0; k4 < NQ; ++k4) q[k4] = opq[64 * k4];
+#pragma unroll
+        for (int k = 0; k < NOPS; ++k) {
+            if (k < NA1) a1[k / KS1][k % KS1] = q[k >> 2][k & 3];
+            else a2[(k - NA1) / KS2][(k - NA1) % KS2] = q[k >> 2][k & 3];
+        }
+    }
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
         for (int s = 0; s < KS1; ++s) {
             int fi = 16 * mb + j, t = 4 * s + g;
-            a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
+            if (!PREP) a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
         }
     // GEMM2 A operand: lane (g, j) supplies slot row j of block mb2, i.e.
     // register R' = 4 mb2 + (j & 3) in lane group j >> 2, and k-row g of k-step s,
@@ -281,14 +307,13 @@ __device__ __forceinline__ void fused_tile(
         slot_b[mb2] = Rr < NREG ? Rr / HB : KS;
         slot_a[mb2] = 4 * (Rr % HB) + (j >> 2);
     }
-    float a2[MB2][KS2];
 #pragma unroll
     for (int mb2 = 0; mb2 < MB2; ++mb2)
 #pragma unroll
         for (int s = 0; s < KS2; ++s) {
             int fi = 16 * (s >> 2) + 4 * g + (s & 3);
             const int ta = slot_a[mb2], tb = slot_b[mb2];
-            a2[mb2][s] = (fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f;
+            if (!PREP) a2[mb2][s] = (fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f;
         }
 
     // mixed precision: 16-wide k-steps, operands converted once to BF16/FP16
@@ -321,9 +346,9 @@ __device__ __forceinline__ void fused_tile(
                         MX::cvt((fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f);
                 }
     }
-    __syncthreads();  // the staged filters are consumed
+    if (!PREP) __syncthreads();  // the staged filters are consumed
 
-    if (POLY) {
+    if (POLY && !PREP) {
         // (4) coefficient table of the polynomial form from the staged weights:
         // phi:        c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} + (-1)^k w_{j0-m})
         // d phi / ds: c_k = Md[k][0] w_j0 + sum_{m>=1} Md[k][m] (w_{j0+m} - (-1)^k w_{j0-m})
@@ -780,6 +805,7 @@ __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
     const BatchModel md = a.models[im.model];
     io.react = md.react;
     io.proj_c = md.proj_c;
+    io.prep = md.prep + (size_t)t * a.prep_stage;
     fused_tile<KS, NMB, NB, NW, MODE_FWD, PREC_F32, RBFM>(
         io, im.H, im.W, a.Th, a.Tw, ty * a.Th, tx * a.Tw, md.filt + (size_t)t * a.Nk * KK, a.Nk,
         md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb, md.lam + t, lds);
@@ -810,6 +836,8 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     io.za = MODE == MODE_BWD_INPUT && PREC == PREC_F32 ? s.za : nullptr;
     io.react = s.react;
     io.proj_c = s.proj_c;
+    io.prep = s.prep;
+    if (RBFM == RBF_POLY && PREC == PREC_F32 && !s.prep) return hipErrorInvalidValue;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     dim3 grid(tiles * s.N);

@@ -32,6 +32,9 @@ struct StageArgs {
     float proj_c = 1.f;   // projected reaction: threshold c
     float *za = nullptr;  // input-gradient mode, FP32: if set, z = K u and a = K e at every
                           // pixel (za_index layout), the parameter-gradient kernels' input
+    const float *prep = nullptr;  // FP32 polynomial form: this stage's block written by
+                                  // fused_prep (phi table in the forward, d phi / ds in the
+                                  // input-gradient mode); required there
 };
 
 // Batched forward (device descriptors, filled on the host).
@@ -48,6 +51,7 @@ struct BatchModel {
     const float *lam;   // [T]
     int react;          // tnrd_reaction
     float proj_c;       // projected reaction: threshold c
+    float *prep;        // [T][BatchArgs::prep_stage] prepared stage blocks (polynomial form)
 };
 
 struct BatchItem {
@@ -60,12 +64,26 @@ struct BatchArgs {
     const BatchItem *items;  // one stage's items, image-major
     int items_per_stage, T, Th, Tw, Nk, Nrbf;
     int poly;  // the polynomial influence form may be used
+    size_t prep_stage;  // floats per prepared stage block
+    int n_models;
     FusedRbf rb;
 };
 
 // Runs the T stages of a batch: one launch per stage over all (image, tile) items.
 hipError_t batched_launch(const BatchArgs &a, int ks, int nw, hipStream_t stream);
 bool batched_config_ok(int ks, int nk, int nrbf, int th, int tw, int nw);
+
+// Prepared stage blocks of the fused kernel (FP32 operands, polynomial form):
+// floats per stage, and the build of T stages' blocks (stage t at
+// prep + t * fused_prep_floats) from [T][Nk][ks*ks] filters and [T][Nk][Nrbf]
+// weights; deriv selects the d phi / ds table of the input-gradient mode.
+size_t fused_prep_floats(int ks, int nk, int nrbf);
+hipError_t fused_prep(const float *filt, const float *rbfw, int T, int ks, int nk, const RbfGrid &grid,
+                      int deriv, float *prep, hipStream_t stream);
+// The same for stage 0 .. T-1 of every model of a batch (into BatchModel::prep).
+hipError_t batched_prep(const BatchArgs &a, int ks, int n_models, hipStream_t stream);
+// Whether a stage with these options runs the fused kernel's prepared form.
+bool fused_uses_prep(const StageArgs &s);
 
 hipError_t split_stage(const StageArgs &s, hipStream_t stream);
 size_t split_scratch_floats(int N, int H, int W, int Nk);
