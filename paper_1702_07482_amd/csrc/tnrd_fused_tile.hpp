@@ -73,7 +73,9 @@ struct FusedLds {
     int total;
 };
 
-__host__ __device__ inline int fused_ring(int ks, int nw) { return 2 * nw + 2 * (ks / 2); }
+// Rows of a last round that join the round before it (see fused_tile).
+constexpr int FUSED_MERGE = 2;
+__host__ __device__ inline int fused_ring(int ks, int nw) { return 2 * nw + 2 * (ks / 2) + FUSED_MERGE; }
 
 __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, int tw, int nrbf,
                                               int nw, int mode, int rbfm)
@@ -127,11 +129,12 @@ __device__ __forceinline__ void fused_tile(
     constexpr int HB = G2::HB, NREG = G2::NREG, MB2 = G2::MB2;
     constexpr int KS2 = 4 * NMB;  // GEMM2 k-steps (4 filters each)
     constexpr int THREADS = 64 * NW;
-    constexpr int RING = 2 * NW + 2 * R;
+    constexpr int RING = 2 * NW + 2 * R + FUSED_MERGE;
+    static_assert(FUSED_MERGE <= R, "the output-pass size PF assumes FUSED_MERGE <= R");
     constexpr int PW = 16 * NB + 2 * R;  // P row pitch (fused_lds().pw)
-    // output values a thread produces per round, at most: (NW + R) rows of a tile at most
-    // 16 NB - 2R wide
-    constexpr int PF = ((NW + R) * (16 * NB - 2 * R) + THREADS - 1) / THREADS;
+    // output values a thread produces per round, at most: NW + R + FUSED_MERGE rows (a
+    // merged last round of a tile at the bottom border) of a tile at most 16 NB - 2R wide
+    constexpr int PF = ((NW + R + FUSED_MERGE) * (16 * NB - 2 * R) + THREADS - 1) / THREADS;
 
     const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW, MODE, RBFM);
     float *su = lds + L.u_off;
@@ -699,11 +702,16 @@ __device__ __forceinline__ void fused_tile(
 
     // ---- main loop: rounds of NW E rows, one per wave.  After round k the
     // partials of every E row below NW (k+1) are in the ring; the output rows
-    // they complete are produced before the next round's rows are stored.  The
-    // ring holds 2 NW + 2R rows, so the rows one round writes never share a
-    // slot with the rows the previous round's outputs still read.  GEMM1 of
-    // the wave's next block is issued before the influence of the current one.
+    // they complete are produced after its barrier, before the next round's
+    // rows are stored.  A last round of at most FUSED_MERGE rows follows the
+    // round before it without a barrier between them, instead of running as a
+    // round of its own in which most waves wait.  The ring holds
+    // 2 NW + 2R + FUSED_MERGE rows, so the rows written between two barriers
+    // never share a slot with the rows the previous round's outputs still read.
+    // GEMM1 of the wave's next block is issued before the influence of the
+    // current one.
     const int rounds = (e_hi + NW - 1) / NW;
+    const bool merge = rounds >= 2 && e_hi - NW * (rounds - 1) <= FUSED_MERGE;
     int y_done = 0;
     bool have = false;
     floatx4 c1[NMB], ca[NMB];
@@ -713,6 +721,7 @@ __device__ __forceinline__ void fused_tile(
         ca[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     for (int k = 0; k < rounds; ++k) {
+        const bool sync = !(merge && k == rounds - 2);
         int y_end = e_hi <= NW * (k + 1) ? Th : max(0, NW * (k + 1) - 2 * R);
         y_end = min(y_end, y_lim);
         const int y0 = min(y_done, y_end);
@@ -722,7 +731,7 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
             for (int p = 0; p < PF; ++p) {
                 fpre[p] = 0.f;
-                if (pdy[p] < y_end - y0 && tx0 + pdx[p] < W)
+                if (sync && pdy[p] < y_end - y0 && tx0 + pdx[p] < W)
                     fpre[p] = fn[(size_t)(ty0 + y0 + pdy[p]) * W + tx0 + pdx[p]];
             }
         }
@@ -750,6 +759,7 @@ __device__ __forceinline__ void fused_tile(
         } else {
             have = false;
         }
+        if (!sync) continue;
         __syncthreads();
         produce(y0, y_end, fpre);
         y_done = max(y_done, y_end);
