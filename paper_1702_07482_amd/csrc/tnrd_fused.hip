@@ -77,7 +77,7 @@ FusedRbf make_fused_rbf(const RbfGrid &grid)
 // rho = 1) and below 1e-6 of it for d phi / ds (1.8e-7 at rho = 1).
 bool poly_form_ok(const RbfGrid &grid, int automatic_window)
 {
-    if (!automatic_window || grid.window != RBF_WIN) return false;
+    if (!automatic_window || grid.window != RBF_WIN || grid.nrbf > POLY_NRBF_MAX) return false;
     const double sigma = 1.0 / sqrt(-2.0 * (double)grid.neg_half_inv_var);
     const double rho = ((double)grid.step / sigma) * ((double)grid.step / sigma);
     return rho > 0.0 && rho < 1.4;

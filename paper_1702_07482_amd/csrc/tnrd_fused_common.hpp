@@ -65,6 +65,14 @@ constexpr int POLY_MW = RBF_WIN + 1;      // centres on each side of j0 in the f
 constexpr int POLY_PAD = RBF_WIN + POLY_MW;  // zero padding of a weight row on each side
 
 __host__ __device__ inline int poly_intervals(int nrbf) { return nrbf + 2 * RBF_WIN + 2; }
+// The table is laid out for at most POLY_NRBF_MAX centres (intervals past a
+// smaller model's last one are zero), so its geometry is known at compile
+// time and the kernel's table reads take immediate offsets.  Rows are padded
+// to 4 mod 16 floats per filter, so the four filters a register quad's lane
+// groups read start in distinct banks.
+constexpr int POLY_NRBF_MAX = 63;
+constexpr int POLY_NI = POLY_NRBF_MAX + 2 * RBF_WIN + 2;  // intervals per filter
+constexpr int POLY_TFP = POLY_NC * POLY_NI + ((4 - POLY_NC * POLY_NI % 16) + 16) % 16;
 // Interval coordinate given to masked-off pixels: an integer far beyond every
 // table, so it clamps to the zero interval at the top end with d = 0.
 constexpr float POLY_OFF_MASKED = 1048576.f;

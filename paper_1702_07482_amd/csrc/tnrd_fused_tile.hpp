@@ -89,8 +89,8 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     l.e_off = l.u_off + l.u_size;
     l.t_off = l.e_off + (mode == MODE_BWD_INPUT ? l.u_size : 0);
     l.t_pitch = nrbf + 4 * RBF_WIN + 1;
-    l.ni = poly_intervals(nrbf);
-    l.tf_pitch = POLY_NC * l.ni + ((4 - POLY_NC * l.ni % 16) + 16) % 16;
+    l.ni = POLY_NI;
+    l.tf_pitch = POLY_TFP;
     l.w_pitch = nrbf + 2 * POLY_PAD;
     l.t_size = rbfm == RBF_POLY ? 16 * nmb * l.tf_pitch : ((16 * nmb * l.t_pitch + 3) & ~3);
     l.p_off = l.t_off + l.t_size;
@@ -356,7 +356,7 @@ __device__ __forceinline__ void fused_tile(
         // phi:        c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} + (-1)^k w_{j0-m})
         // d phi / ds: c_k = Md[k][0] w_j0 + sum_{m>=1} Md[k][m] (w_{j0+m} - (-1)^k w_{j0-m})
         // (the even-in-d part of a term centred at j0 vanishes for the derivative)
-        const int ni = L.ni;
+        const int ni = POLY_NI, ni_used = poly_intervals(Nrbf);
         const float(*pm)[POLY_MW + 1] = BWD ? rb.pmd : rb.pm;
         constexpr int par = BWD ? 1 : 0;  // parity of k whose terms are sums
         for (int idx = tid; idx < 16 * NMB * ni; idx += THREADS) {
@@ -364,7 +364,7 @@ __device__ __forceinline__ void fused_tile(
             float c[POLY_NC];
 #pragma unroll
             for (int k = 0; k < POLY_NC; ++k) c[k] = 0.f;
-            if (fi < Nk && q >= 1 && q <= ni - 2) {
+            if (fi < Nk && q >= 1 && q <= ni_used - 2) {
                 const float *wc = sp + fi * L.w_pitch + (q - 1 - RBF_WIN) + POLY_PAD;  // w_j0
                 const float w0 = wc[0];
 #pragma unroll
@@ -376,7 +376,7 @@ __device__ __forceinline__ void fused_tile(
                     for (int k = 0; k < POLY_NC; ++k) c[k] = fmaf(pm[k][m], ((k & 1) == par) ? sum : dif, c[k]);
                 }
             }
-            float *dst = stab + fi * L.tf_pitch + 4 * q;
+            float *dst = stab + fi * POLY_TFP + 4 * q;
             *reinterpret_cast<floatx4 *>(dst) = floatx4{c[0], c[1], c[2], c[3]};
             *reinterpret_cast<floatx4 *>(dst + 4 * ni) = floatx4{c[4], c[5], c[6], c[7]};
         }
@@ -403,7 +403,7 @@ __device__ __forceinline__ void fused_tile(
 
     const float lam = lam_t[0];
     // per-lane part of the polynomial table address: filter 16 mb + 4 g + r
-    const int tab_g = 4 * g * L.tf_pitch;
+    const int tab_g = 4 * g * POLY_TFP;
 
     // GEMM1 of block (E row e, 16-pixel block cb): z = K u (and a = K e in
     // input-gradient mode).  The B operands are read first (gemm1_load), the
@@ -470,10 +470,10 @@ __device__ __forceinline__ void fused_tile(
             const float s = fmaf(acc1[mb][r], sscale, soff);
             const float jr = rintf(s);
             dq[slot][r] = s - jr;
-            const int q = (int)__builtin_amdgcn_fmed3f(jr, 0.f, (float)(L.ni - 1));
-            const float *cp = stab + (16 * mb + r) * L.tf_pitch + tab_g + 4 * q;
+            const int q = (int)__builtin_amdgcn_fmed3f(jr, 0.f, (float)(POLY_NI - 1));
+            const float *cp = stab + (16 * mb + r) * POLY_TFP + tab_g + 4 * q;
             lo[slot][r] = *reinterpret_cast<const floatx4 *>(cp);
-            hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * L.ni);
+            hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * POLY_NI);
         }
     };
     // influence of filter group mb, in place: v = phi(z) (times phi' and a in

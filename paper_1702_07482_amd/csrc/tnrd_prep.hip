@@ -49,7 +49,7 @@ __device__ void prep_stage_body(const float *__restrict__ filt, const float *__r
     using P = PrepGeo<KS, NMB>;
     constexpr int KK = G::KK, KS1 = G::KS1, HB = G2::HB, NREG = G2::NREG;
     const FusedLds L = fused_lds(KS, NMB, 2, KS, KS, Nrbf, 8, MODE_FWD, RBF_POLY);
-    const int ni = L.ni;
+    const int ni = L.ni, ni_used = poly_intervals(Nrbf);
     const int ntab = 16 * NMB * ni;
     if (idx < ntab) {
         // c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} +- w_{j0-m}), j0 = q - 1 - W,
@@ -61,7 +61,7 @@ __device__ void prep_stage_body(const float *__restrict__ filt, const float *__r
         float c[POLY_NC];
 #pragma unroll
         for (int k = 0; k < POLY_NC; ++k) c[k] = 0.f;
-        if (fi < Nk && q >= 1 && q <= ni - 2) {
+        if (fi < Nk && q >= 1 && q <= ni_used - 2) {
             const int j0 = q - 1 - RBF_WIN;
             auto w = [&](int jj) { return (jj >= 0 && jj < Nrbf) ? rbfw[fi * Nrbf + jj] : 0.f; };
             const float w0 = w(j0);
@@ -139,9 +139,9 @@ __global__ void __launch_bounds__(256) k_prep_batched(BatchArgs a)
 }
 
 template <int KS, int NMB>
-static int prep_threads(int nrbf)
+static int prep_threads(int)
 {
-    return 16 * NMB * poly_intervals(nrbf) + PrepGeo<KS, NMB>::NQ * 64;
+    return 16 * NMB * POLY_NI + PrepGeo<KS, NMB>::NQ * 64;
 }
 
 static int prep_nmb(int nk) { return (nk + 15) / 16 <= 2 ? 2 : 3; }

@@ -151,3 +151,17 @@ def test_autograd_function_matches_backward():
     torch.testing.assert_close(filt.grad, dK, rtol=0, atol=0)
     torch.testing.assert_close(w.grad, dW, rtol=0, atol=0)
     torch.testing.assert_close(lam.grad, dl, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("nrbf,mu0", [(31, -150.0), (80, -395.0)])
+def test_backward_other_rbf_counts(nrbf, mu0):
+    """Gradients with 31 centres (zero intervals past the model's last one in the prepared
+    d phi / ds table) and 80 (the Gaussian form), against the oracle."""
+    print(f"[bwd rbf count {nrbf}]", flush=True)
+    g = np.random.default_rng(4200 + nrbf)
+    m = synth.make_model(3, 24, 7, g, Nrbf=nrbf, mu0=mu0)
+    u, f = _case(2, (41, 38), 2, index=nrbf)
+    uT, st = oracle.forward(f, m, want_states=True)
+    gT = uT - u
+    ref = oracle.backward(f, m, st, gT)
+    _check(_gpu_grads(f, m, gT), ref)

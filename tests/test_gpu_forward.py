@@ -166,3 +166,16 @@ def test_split_and_fused_agree():
     a = _run(f, m, tnrd.IMPL_SPLIT)
     b = _run(f, m, tnrd.IMPL_FUSED)
     assert rel_inf(b, a) <= 2e-5
+
+
+@pytest.mark.parametrize("nrbf,mu0", [(31, -150.0), (80, -395.0)])
+def test_other_rbf_counts(nrbf, mu0):
+    """31 centres (the polynomial table laid out for 63 carries zero intervals past the
+    model's last one) and 80 centres (more than the table holds: the Gaussian form)."""
+    print(f"[rbf count {nrbf}]", flush=True)
+    g = np.random.default_rng(4100 + nrbf)
+    m = synth.make_model(3, 24, 7, g, Nrbf=nrbf, mu0=mu0)
+    _, f = synth.make_pair(70, 61, 1, config_id=2, index=nrbf)
+    ref = oracle.forward(f, m)
+    got = _run(f, m, tnrd.IMPL_FUSED)
+    assert rel_inf(got, ref) <= TOL
