@@ -63,7 +63,8 @@ def parse():
 FUSED_SOURCES = ["paper_1702_07482_amd/csrc/tnrd_fused_tile.hpp",
                  "paper_1702_07482_amd/csrc/tnrd_fused.hip",
                  "paper_1702_07482_amd/csrc/tnrd_fused_common.hpp",
-                 "paper_1702_07482_amd/csrc/tnrd_device.hpp"]
+                 "paper_1702_07482_amd/csrc/tnrd_device.hpp",
+                 "paper_1702_07482_amd/csrc/tnrd_prep.hip"]
 FUSED_PROFILE = "profiles/fused_stage_fwd_512x512_48x7x7.md"
 
 
