@@ -49,6 +49,8 @@ constexpr int BP_TH_MAX = 64;  // for the smallest, i.e. the most tiles)
 constexpr int BP_NBW = 2;   // 16-pixel blocks per tile row (tile width 32)
 constexpr int BP_NW = 4;    // waves per workgroup
 constexpr int DW_U = 16;    // k_bwd_dw pixels per wave step
+constexpr int ZA_PAD = 128; // slack after the z/a export: a filter block past Nk read at the
+                            // last pixel stays inside the buffer (32 NMB - 1 < ZA_PAD words)
 
 struct BwdParamsIO {
     const float *u_prev;  // u_{t-1}
@@ -289,21 +291,31 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
         const int ylim = min(Th, H - ty0);
         const int nrows = ylim > wave ? (ylim - wave + NW - 1) / NW : 0;
         const int nblk = nrows * NBW;
-        const float *zaimg = io.za + img * plane * za_stride(Nk);
+        const int zst = za_stride(Nk);
+        // filter 16 nb + j of pixel p sits at p zst + 32 nb + 8 (j >> 2) + (j & 3) (z; a four
+        // words on): one address per pixel, the filter blocks at immediate offsets.  The
+        // address of a pixel past the image row or of a row past the tile is clamped into
+        // the image (its values are dropped); a filter block past Nk may read into the next
+        // pixel, and the export buffer carries ZA_PAD floats of slack for the last one.
+        const float *zaimg = io.za + img * plane * zst + 8 * (j >> 2) + (j & 3);
         float zn[NMB][4], an[NMB][4];
         auto load = [&](int b) {
             const int y = wave + NW * (b / NBW), cb = b % NBW;
+            const int yy = b < nblk ? ty0 + y : ty0;
+            const float *rowp = zaimg + (size_t)yy * W * zst;
+            const int xb = tx0 + 16 * cb + 4 * g;
 #pragma unroll
-            for (int nb = 0; nb < NMB; ++nb)
+            for (int r = 0; r < 4; ++r) {
+                const float *pp = rowp + (size_t)(min(xb + r, W - 1) * zst);
+                const bool okr = b < nblk && xb + r < W;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int xi = tx0 + 16 * cb + 4 * g + r, fi = 16 * nb + j;
-                    const bool ok = b < nblk && xi < W && fi < Nk;
-                    const size_t q = ok ? za_index((size_t)(ty0 + y) * W + xi, Nk, fi) : 0;
-                    const float zz = zaimg[q], aa = zaimg[q + 4];
+                for (int nb = 0; nb < NMB; ++nb) {
+                    const bool ok = okr && 16 * nb + j < Nk;
+                    const float zz = pp[32 * nb], aa = pp[32 * nb + 4];
                     zn[nb][r] = ok ? zz : 0.f;
                     an[nb][r] = ok ? aa : 0.f;
                 }
+            }
         };
         load(0);
 #pragma unroll 1
@@ -650,7 +662,7 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s,
     };
     w.g[0] = take(gm.img);
     w.g[1] = take(gm.img);
-    w.za = take(gm.img * za_stride(m->Nk));
+    w.za = take(gm.img * za_stride(m->Nk) + ZA_PAD);
     w.dk_part = take((size_t)gm.tiles * m->Nk * kk);
     w.dl_part = take((size_t)gm.tiles);
     w.dw_part = take((size_t)gm.dw_grid * m->Nk * m->Nrbf);
