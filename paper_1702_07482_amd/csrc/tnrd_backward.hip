@@ -78,7 +78,7 @@ __host__ __device__ inline BpLds bp_lds(int ks, int nmb, int th, int tw, int nrb
     l.tile_size = (th + 2 * R) * l.ldw;
     l.u_off = 0;
     l.e_off = l.tile_size;
-    l.t_pitch = (nrbf + 4 * RBF_WIN + 1) | 1;  // odd: the rows of 16 filters start in distinct banks
+    l.t_pitch = nrbf + 4 * RBF_WIN + 1;  // weight positions per filter (zero padded by 2W)
     l.t_off = 2 * l.tile_size;
     l.red_off = l.t_off + 16 * nmb * l.t_pitch;
     l.red_size = 16 * nmb * ks * ks;
@@ -87,22 +87,26 @@ __host__ __device__ inline BpLds bp_lds(int ks, int nmb, int th, int tw, int nrb
     return l;
 }
 
-// Horner evaluation of phi(z) and phi'(z) from the LDS weight table row.
-__device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__restrict__ row,
+// Horner evaluation of phi(z) and phi'(z) from the LDS weight table: the
+// weights of a block of 16 filters are position-major, [position][16]; col
+// points at the lane's filter in position 0.  Lanes of one read hold 16
+// different filters (distinct banks whatever their positions, up to a multiple
+// of 16) and four pixels each.
+__device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__restrict__ col,
                                                     const FusedRbf &rb, float &phi, float &dphi)
 {
     float s = fmaf(z, rb.inv_step, -rb.mu0_over_step);
     float jr = fminf(fmaxf(rintf(s), -(float)RBF_WIN), rb.jmax);
     float d = s - jr;
-    const float *w = row + (int)jr + RBF_WIN;
+    const float *w = col + ((int)jr + RBF_WIN) * 16;
     float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
     float E = __builtin_amdgcn_exp2f(-rb.rho_log2e * d * fmaf(0.5f, d, (float)RBF_WIN));
-    float acc = w[2 * RBF_WIN] * rb.c[2 * RBF_WIN];
+    float acc = w[16 * 2 * RBF_WIN] * rb.c[2 * RBF_WIN];
     float accd = 0.f;
 #pragma unroll
     for (int n = 2 * RBF_WIN - 1; n >= 0; --n) {
         accd = fmaf(accd, q, acc);
-        acc = fmaf(acc, q, w[n] * rb.c[n]);
+        acc = fmaf(acc, q, w[16 * n] * rb.c[n]);
     }
     const bool in = fabsf(d) <= 0.5f;
     phi = in ? E * acc : 0.f;
@@ -217,7 +221,9 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 int i = base + k * THREADS + tid;
-                int fi = i / L.t_pitch, jj = i - fi * L.t_pitch - 2 * RBF_WIN;
+                // table word i = (nb t_pitch + position) 16 + filter-in-block
+                const int blk = i / (16 * L.t_pitch), rem = i - blk * 16 * L.t_pitch;
+                const int pos = rem >> 4, fi = 16 * blk + (rem & 15), jj = pos - 2 * RBF_WIN;
                 float w = rbfw[min(max(fi * Nrbf + jj, 0), nw - 1)];
                 v[k] = (fi < Nk && jj >= 0 && jj < Nrbf) ? w : 0.f;
             }
@@ -332,7 +338,7 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
             const int y = wave + NW * (b / NBW), cb = b % NBW;
 #pragma unroll
             for (int nb = 0; nb < NMB; ++nb) {
-                const float *row = stab + (16 * nb + j) * L.t_pitch;
+                const float *row = stab + nb * 16 * L.t_pitch + j;
                 floatx4 vz, vh;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -371,7 +377,7 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
                     acca = __builtin_amdgcn_mfma_f32_16x16x4f32(be[s], bf[nb][s], acca, 0, 0, 0);
                 }
                 // influence, export, and the two dK operands (v, h) in place
-                const float *row = stab + (16 * nb + j) * L.t_pitch;
+                const float *row = stab + nb * 16 * L.t_pitch + j;
                 const int fi = 16 * nb + j;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
