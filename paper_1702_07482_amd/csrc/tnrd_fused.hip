@@ -1,6 +1,8 @@
 // Host side of the fused stage kernel: influence-form constants, tile and
 // form selection, configuration checks.  The kernels are instantiated in
 // tnrd_fused_{fwd,mixed,bwd,batched}.hip.
+#include <string.h>
+
 #include "tnrd_fused_tile.hpp"
 
 namespace tnrd {
@@ -45,7 +47,30 @@ static void poly_gauss_coeffs(double rho, bool deriv, double M[POLY_NC][POLY_MW 
     }
 }
 
+static FusedRbf make_fused_rbf_uncached(const RbfGrid &grid);
+
+// The constants depend on the grid only; the two 8 x 8 solves per centre
+// offset are done once per grid and thread, not once per stage launch.
 FusedRbf make_fused_rbf(const RbfGrid &grid)
+{
+    static thread_local bool have = false;
+    static thread_local float key[4];
+    static thread_local int key_n = 0;
+    static thread_local FusedRbf last;
+    if (!have || key[0] != grid.mu0 || key[1] != grid.step || key[2] != grid.neg_half_inv_var ||
+        key[3] != grid.inv_step || key_n != grid.nrbf) {
+        last = make_fused_rbf_uncached(grid);
+        key[0] = grid.mu0;
+        key[1] = grid.step;
+        key[2] = grid.neg_half_inv_var;
+        key[3] = grid.inv_step;
+        key_n = grid.nrbf;
+        have = true;
+    }
+    return last;
+}
+
+static FusedRbf make_fused_rbf_uncached(const RbfGrid &grid)
 {
     FusedRbf rb;
     const double step = grid.step;
@@ -175,12 +200,37 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
     return p;
 }
 
+// plan_tile scans a few hundred candidate tiles; every stage of a call asks the
+// same question, so the answers are kept per thread (the last few shapes).
+static TilePlan plan_tile_cached(int ks, int nk, int nrbf, int N, int H, int W, int req_h, int req_w,
+                                 int waves, int mode, bool poly)
+{
+    struct Entry {
+        int key[12];
+        TilePlan plan;
+    };
+    constexpr int SLOTS = 8;
+    static thread_local Entry cache[SLOTS];
+    static thread_local int used = 0, next = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const int key[12] = {ks, nk, nrbf, N, H, W, req_h, req_w, waves, mode, poly ? 1 : 0, dev};
+    for (int i = 0; i < used; ++i)
+        if (memcmp(cache[i].key, key, sizeof(key)) == 0) return cache[i].plan;
+    const TilePlan p = plan_tile(ks, nk, nrbf, N, H, W, req_h, req_w, waves, mode, poly);
+    memcpy(cache[next].key, key, sizeof(key));
+    cache[next].plan = p;
+    next = (next + 1) % SLOTS;
+    if (used < SLOTS) ++used;
+    return p;
+}
+
 template <int MODE>
 static hipError_t fused_dispatch(const StageArgs &s, hipStream_t stream)
 {
     const bool poly = s.poly && poly_form_ok(s.grid, 1);
-    const TilePlan p = plan_tile(s.ks, s.Nk, s.grid.nrbf, s.N, s.H, s.W, s.tile_h, s.tile_w, s.waves,
-                                 MODE, poly);
+    const TilePlan p = plan_tile_cached(s.ks, s.Nk, s.grid.nrbf, s.N, s.H, s.W, s.tile_h, s.tile_w,
+                                        s.waves, MODE, poly);
     if (!p.ok) return hipErrorInvalidValue;
     if (MODE == MODE_BWD_INPUT) return fused_launch_bwd(s, p.th, p.tw, p.nb, p.nw, p.rbfm, stream);
     if (s.prec == PREC_BF16 || s.prec == PREC_F16)
