@@ -14,6 +14,9 @@ Extra legs reported on the same JSON line (each its own workload):
            5 stages of 24 5x5 filters, forward and forward + backward with dl/df
   denoise  the framework's Gaussian-denoising reaction (quadratic data term),
            8 x 512 x 512, 5 stages of 48 7x7 filters
+  train    joint L-BFGS training (train.py) on the fwd_bwd workload: loss evaluations
+           (forward + backward) per second, and the quality indexes (PSNR, MSSIM, EC,
+           ratio image, coefficient of variation) of the model before and after
   peaks    measured copy, matrix, vector-FMA and exp2 throughput; the legs' rates
            against them ("fractions")
 
@@ -50,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--impl", default="auto", choices=["auto", "fused", "split"])
-    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed,projected,denoise,peaks")
+    ap.add_argument("--legs", default="fwd,fwd_bwd,batched,mixed,projected,denoise,train,peaks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a kernel of known "
@@ -205,6 +208,50 @@ def leg_fwd_bwd(args):
             "workload": "forward (states kept) + backward, 16 x 180 x 180 FP32, L=1, 8 stages x "
                         "48 7x7 filters, loss mean((u_T - u_gt)^2); gradients for all filters, "
                         "RBF weights and lambda"}
+
+
+def leg_train(args):
+    """Joint L-BFGS training on 16 x 180 x 180 pairs (8 stages x 48 7x7): evaluation rate
+    and the quality indexes of u_T before and after."""
+    import torch
+    from paper_1702_07482_amd import metrics, synth
+    from paper_1702_07482_amd.train import TrainableModel, train_joint
+
+    N, H, W = 16, 180, 180
+    m = synth.config_model(3)
+    pairs = [synth.make_pair(H, W, 1, config_id=3, index=i) for i in range(N)]
+    fd = torch.from_numpy(np.stack([p[1] for p in pairs])).cuda().contiguous()
+    ud = torch.from_numpy(np.stack([p[0] for p in pairs])).cuda().contiguous()
+    model = TrainableModel.from_dict(m)
+
+    def quality():
+        with torch.no_grad():
+            u = model(fd)
+        ri = metrics.ratio_image_stats(fd, torch.clamp(u, min=1e-3))
+        return {"psnr_db": metrics.psnr(u, ud), "mssim": metrics.mssim(u, ud),
+                "ec": metrics.edge_correlation(u, ud), "ri_mean": ri[0], "ri_var": ri[1],
+                "cv": metrics.coeff_variation(u), "cv_clean": metrics.coeff_variation(ud)}
+
+    q0 = quality()
+    # warm-up evaluation: the first backward call loads its kernels
+    loss = 0.5 * ((model(fd) - ud) ** 2).sum()
+    loss.backward()
+    model.zero_grad()
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    log = train_joint(model, fd, ud, iters=max(2, args.steps // 10))
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    ev = len(log.losses)
+    return {"evals_per_s": ev / (ms / 1e3), "mpst_s": ev * N * H * W * m["T"] / 1e6 / (ms / 1e3),
+            "unit": "megapixel-stages/s of forward + backward inside L-BFGS",
+            "evaluations": ev, "ms": ms, "loss_first": log.losses[0], "loss_last": log.losses[-1],
+            "quality_before": q0, "quality_after": quality(),
+            "workload": "joint L-BFGS (strong Wolfe) over all filters, RBF weights and "
+                        "beta = log lambda, loss 1/2 sum ||u_T - u_gt||^2, 16 x 180 x 180 FP32, "
+                        "L=1, 8 stages x 48 7x7"}
 
 
 def leg_batched(args):
@@ -578,6 +625,8 @@ def main():
         out["projected"] = leg_projected(args)
     if "denoise" in legs:
         out["denoise"] = leg_denoise(args)
+    if "train" in legs:
+        out["train"] = leg_train(args)
     if "peaks" in legs:
         out["peaks"] = leg_peaks(args)
         out["fractions"] = fractions(out)

@@ -1,0 +1,87 @@
+"""The training driver (paper_1702_07482_amd/train.py) on the GPU: its gradients
+against the FP64 oracle, and L-BFGS joint and greedy schedules lowering the loss
+of eq. learning on synthetic pairs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1702_07482_amd import synth, tnrd
+from paper_1702_07482_amd.train import TrainableModel, loss_fn, train_greedy, train_joint
+from tests.helpers import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(T=2, n=2, shape=(40, 36), seed=31):
+    g = np.random.default_rng(seed)
+    m = synth.make_model(T, 24, 5, g)
+    pairs = [synth.make_pair(*shape, 1, config_id=1, index=seed + i) for i in range(n)]
+    u = np.stack([p[0] for p in pairs])
+    f = np.stack([p[1] for p in pairs])
+    return m, u, f
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_driver_gradients_match_oracle():
+    """dl/dK, dl/dW and dl/dbeta = lambda dl/dlambda of the loss 1/2 ||u_T - u_gt||^2
+    against the oracle, and dl/dbeta against lambda times the C ABI's dl/dlambda on
+    the same inputs (the driver's chain rule)."""
+    print("[train grads]", flush=True)
+    m, u, f = _problem(seed=31)
+    m["lam"] = np.array([1.0, 1.0], dtype=np.float32)
+    model = TrainableModel.from_dict(m)
+    fd, ud = _cuda(f), _cuda(u)
+    loss = loss_fn(model(fd), ud)
+    loss.backward()
+    uT, st = oracle.forward(f, m, want_states=True)
+    dK, dW, dl, _ = oracle.backward(f, m, st, uT - u)
+    ref_loss = 0.5 * np.sum((uT - u) ** 2)
+    assert float(loss) == pytest.approx(ref_loss, rel=1e-5)
+    lam = model.lam().detach().cpu().numpy()
+    errs = {"dK": rel_inf(model.filters.grad.cpu().numpy(), dK),
+            "dW": rel_inf(model.rbf_w.grad.cpu().numpy(), dW),
+            "dbeta": rel_inf(model.beta.grad.cpu().numpy(), lam * dl)}
+    print("rel errors", errs, flush=True)
+    for k, e in errs.items():
+        assert e <= 1e-4, (k, errs)
+    # the same backward through the C ABI: dbeta must be lambda dlambda to rounding
+    dm = tnrd.DeviceModel(model.filters.detach(), model.rbf_w.detach(), model.lam().detach(),
+                          m["mu0"], m["step"], m["sigma"])
+    uT_g, states = tnrd.forward(fd, dm, L=1, want_states=True)
+    _, _, dl_abi = tnrd.backward(fd, dm, states, (uT_g - ud).contiguous(), L=1)[:3]
+    np.testing.assert_allclose(model.beta.grad.cpu().numpy(), lam * dl_abi.cpu().numpy(), rtol=1e-6)
+
+
+def test_joint_lbfgs_lowers_the_loss():
+    print("[train joint]", flush=True)
+    m, u, f = _problem(seed=41)
+    model = TrainableModel.from_dict(m)
+    log = train_joint(model, _cuda(f), _cuda(u), iters=6)
+    assert len(log.losses) >= 6
+    # the untrained model is far from the optimum (loss ~3e7): L-BFGS's first steps
+    # are short, so the bar is a steady decrease, not a large one
+    assert log.losses[-1] <= log.losses[0], log.losses
+    assert min(log.losses) < 0.995 * log.losses[0], log.losses
+    for p in model.parameters():
+        assert torch.isfinite(p).all()
+
+
+def test_greedy_trains_every_stage():
+    print("[train greedy]", flush=True)
+    m, u, f = _problem(seed=51)
+    model = TrainableModel.from_dict(m)
+    fd, ud = _cuda(f), _cuda(u)
+    with torch.no_grad():
+        before = float(loss_fn(model(fd), ud))
+    k0 = model.filters.detach().clone()
+    log = train_greedy(model, fd, ud, iters=4)
+    assert sorted(set(log.stages)) == [1, 2]
+    with torch.no_grad():
+        after = float(loss_fn(model(fd), ud))
+    assert after < before
+    for t in range(2):
+        assert not torch.equal(model.filters.detach()[t], k0[t]), t
