@@ -124,7 +124,12 @@ typedef struct tnrd_opts {
 void tnrd_default_opts(tnrd_opts *o);
 
 /* Bytes of workspace a call needs for N images of H x W (which = 0: forward,
- * 1: backward).  Returns 0 on invalid arguments. */
+ * 1: backward).  Returns 0 on invalid arguments.  The workspace holds the
+ * ping-pong image planes, the stage constants prepared once per call for the
+ * fused FP32 kernel (influence coefficient tables and lane-ordered filters,
+ * about 134 KB per stage for 48 filters of 7x7), and in the backward the z/a
+ * export and the per-tile gradient partials.  Its contents are scratch: no
+ * call reads what an earlier call left there. */
 size_t tnrd_workspace_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts *o,
                             int which);
 
