@@ -233,10 +233,11 @@ def leg_train(args):
                 "cv": metrics.coeff_variation(u), "cv_clean": metrics.coeff_variation(ud)}
 
     q0 = quality()
-    # warm-up evaluation: the first backward call loads its kernels
-    loss = 0.5 * ((model(fd) - ud) ** 2).sum()
-    loss.backward()
-    model.zero_grad()
+    # warm-up on a copy: the first backward call and the optimiser's first use of
+    # each torch operation load their GPU code (a few hundred ms, once per process)
+    warm = TrainableModel.from_dict(m)
+    train_joint(warm, fd, ud, iters=2)
+    del warm
     torch.cuda.synchronize()
     a, b = _events()
     a.record()
