@@ -134,7 +134,7 @@ int checkpoint_slot(int t, int T, int s)
 size_t prep_region_floats(const tnrd_model *m, const tnrd_opts &o, int impl, int window,
                           int stages)
 {
-    if (impl != TNRD_IMPL_FUSED || o.prec != TNRD_PREC_FP32 || o.rbf_window >= 0) return 0;
+    if (impl != TNRD_IMPL_FUSED || o.rbf_window >= 0) return 0;
     if (!poly_form_ok(make_grid(m, window), 1)) return 0;
     return (size_t)stages * fused_prep_floats(m->ksize, m->Nk, m->Nrbf);
 }

@@ -260,7 +260,7 @@ size_t fused_scratch_floats(int, int, int, int, int) { return 0; }
 
 bool fused_uses_prep(const StageArgs &s)
 {
-    return s.prec == PREC_F32 && s.poly && poly_form_ok(s.grid, 1);
+    return s.poly && poly_form_ok(s.grid, 1);
 }
 
 hipError_t fused_stage(const StageArgs &s, hipStream_t stream)

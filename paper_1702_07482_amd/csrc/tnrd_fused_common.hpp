@@ -51,7 +51,7 @@ constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
 //   phi(j0 + d) ~ sum_k c_k d^k,  c_k = sum_{|m| <= POLY_MW} M[k][|m|] sgn(m)^k w_{j0+m},
 // where M[k][m] are the monomial coefficients of the interpolant of the single
 // Gaussian exp(-rho (d - m)^2 / 2) (rho = (step/sigma)^2), so the table of c_k
-// is rebuilt from the weights in LDS at the start of every tile.  Intervals run
+// is built from the weights once per call (k_prep_stage).  Intervals run
 // over j0 = -W .. Nrbf-1+W (W = RBF_WIN) with one zero interval at each end;
 // beyond them phi is taken as 0, the same cut as the window of the Gaussian
 // form.  Centres farther than POLY_MW spacings from the interval contribute
@@ -62,7 +62,6 @@ constexpr int RBF_TERMS = 2 * RBF_WIN + 1;
 constexpr int POLY_DEG = 7;
 constexpr int POLY_NC = POLY_DEG + 1;     // coefficients per interval
 constexpr int POLY_MW = RBF_WIN + 1;      // centres on each side of j0 in the fit
-constexpr int POLY_PAD = RBF_WIN + POLY_MW;  // zero padding of a weight row on each side
 
 __host__ __device__ inline int poly_intervals(int nrbf) { return nrbf + 2 * RBF_WIN + 2; }
 // The table is laid out for at most POLY_NRBF_MAX centres (intervals past a
@@ -108,8 +107,8 @@ struct FusedIO {
                           // pixels, layout of za_index()
     int react;            // tnrd_reaction of the stage
     float proj_c;         // projected reaction: threshold c
-    const float *prep;    // FP32 polynomial form: the stage's prepared table and operands
-                          // (k_prep_stage layout)
+    const float *prep;    // polynomial form: the stage's prepared table (and FP32 operands),
+                          // k_prep_stage layout
 };
 
 // Export of z = K u and a = K e for the parameter-gradient kernels: per pixel

@@ -4,10 +4,11 @@
 // Fused stage: one kernel per stage computes, for a tile of output pixels,
 //
 //   z_i = K_i u        filter bank as an implicit GEMM on MFMA (v_mfma_f32_16x16x4_f32)
-//   v_i = phi_i(z_i)   influence on the vector ALUs: in the forward, a piecewise
-//                      degree-7 polynomial per unit interval of the RBF grid whose
-//                      coefficients are built in LDS from the weights; in the
-//                      input-gradient mode (which also needs phi'), the windowed
+//   v_i = phi_i(z_i)   influence on the vector ALUs: a piecewise degree-7
+//                      polynomial per unit interval of the RBF grid (of phi in the
+//                      forward, of d phi / ds in the input-gradient mode) whose
+//                      coefficient table is prepared once per call and copied
+//                      into LDS; or, for explicit RBF windows, the windowed
 //                      Gaussian sum evaluated with Horner's rule
 //   Y   = K^T-GEMM     [tap slots x pixels] = [tap slots x filters] . [filters x pixels] on MFMA
 //   x   = col2im(Y)    x-direction shift-add of the tap columns with DPP row shifts,
@@ -66,7 +67,6 @@ struct FusedLds {
     int ni;                      // polynomial form: intervals per filter
     int tf_pitch;                // polynomial form: floats per filter (8 ni, padded to 4 mod 16 so
                                  // that the 4 filters a wave's lane groups read start in distinct banks)
-    int w_pitch;                 // polynomial form: padded weight row staged in the P area
     int p_off, pw, ring, p_size; // row partials: ring of `ring` output rows x KS tap rows x pw
     int red_off;                 // 8 floats for workgroup reductions
     int dummy_off;               // 64 floats: target of the stores of masked-off lanes
@@ -91,15 +91,13 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     l.t_pitch = nrbf + 4 * RBF_WIN + 1;
     l.ni = POLY_NI;
     l.tf_pitch = POLY_TFP;
-    l.w_pitch = nrbf + 2 * POLY_PAD;
     l.t_size = rbfm == RBF_POLY ? 16 * nmb * l.tf_pitch : ((16 * nmb * l.t_pitch + 3) & ~3);
     l.p_off = l.t_off + l.t_size;
     l.pw = 16 * nb + 2 * R;
     l.ring = fused_ring(ks, nw);
     l.p_size = l.ring * ks * l.pw;
-    // the prologue stages the filters (Gaussian form) or the padded weights
-    // (polynomial form) in the P area
-    const int stage = rbfm == RBF_POLY ? 16 * nmb * l.w_pitch : 16 * nmb * ks * ks;
+    // the prologue stages the filters in the P area (unless they come prepared)
+    const int stage = 16 * nmb * ks * ks;
     if (l.p_size < stage) l.p_size = stage;
     l.red_off = l.p_off + l.p_size;
     l.dummy_off = l.red_off + 8;
@@ -118,9 +116,10 @@ __device__ __forceinline__ void fused_tile(
 {
     constexpr bool BWD = MODE == MODE_BWD_INPUT;
     constexpr bool POLY = RBFM == RBF_POLY;
-    // FP32 operands with the polynomial form: the coefficient table and the
-    // per-lane filter operands come ready-made from io.prep (k_prep_stage)
-    constexpr bool PREP = POLY && PREC == PREC_F32;
+    // Polynomial form: the coefficient table comes ready-made from io.prep
+    // (k_prep_stage); with FP32 operands the per-lane filter operands too
+    constexpr bool PREP_TAB = POLY;
+    constexpr bool PREP_OPS = POLY && PREC == PREC_F32;
     const float *__restrict__ u_prev = io.u_prev;
     const float *__restrict__ f = io.f;
     using G = Geo<KS>;
@@ -151,10 +150,10 @@ __device__ __forceinline__ void fused_tile(
 
     // ---- prologue: every global load of a thread is issued before the first
     // use, so the workgroup pays one memory latency, not one per element.
-    // (1) the stage's filters: into the table area (polynomial form, whose
-    // table is built only after the filters sit in registers) or the P area
-    float *sf = POLY ? stab : sp;
-    if (!PREP) {
+    // (1) the stage's filters, staged in the P area (free until the first
+    // block's partials), unless the operands come prepared
+    float *sf = sp;
+    if (!PREP_OPS) {
         const int nf = Nk * KK;
         for (int base = 0; base < nf; base += 8 * THREADS) {
             float v[8];
@@ -207,13 +206,12 @@ __device__ __forceinline__ void fused_tile(
             }
         }
     }
-    // (3) RBF weights.  Gaussian form: the table itself, rows zero padded by 2W
-    // on both sides.  Polynomial form: rows zero padded by POLY_PAD, staged in
-    // the P area for the coefficient build below.
-    if (!PREP) {
-        float *dst = POLY ? sp : stab;
-        const int pitch = POLY ? L.w_pitch : L.t_pitch;
-        const int pad = POLY ? POLY_PAD : 2 * RBF_WIN;
+    // (3) Gaussian form: the RBF weights are the table itself, rows zero padded
+    // by 2W on both sides
+    if (!POLY) {
+        float *dst = stab;
+        const int pitch = L.t_pitch;
+        const int pad = 2 * RBF_WIN;
         const int n = 16 * NMB * pitch;
         const int nw = Nk * Nrbf;
         for (int base = 0; base < n; base += 8 * THREADS) {
@@ -245,15 +243,15 @@ __device__ __forceinline__ void fused_tile(
             __builtin_amdgcn_global_load_lds(u_prev + (size_t)yy * W + xx, su + c * 64, 4, 0, 0);
         }
     }
-    // (2c) prepared form: the coefficient table straight into LDS in 256-float
-    // chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk)
-    if (PREP) {
+    // (2c) polynomial form: the prepared coefficient table straight into LDS in
+    // 256-float chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk)
+    if (PREP_TAB) {
         for (int c = wave; c * 256 < L.t_size; c += NW) {
             const int k = c * 256 + 4 * lane;
             if (k < L.t_size) __builtin_amdgcn_global_load_lds(io.prep + k, stab + c * 256, 16, 0, 0);
         }
     }
-    if (!PREP) __syncthreads();
+    if (!PREP_OPS) __syncthreads();  // the staged filters (and Gaussian table)
 
     // Mixed-precision input gradient: e, a = K e and phi' a go through BF16/FP16
     // operands with a power-of-two tile scale that puts max|e| at 2^10 (FP16's
@@ -281,7 +279,7 @@ __device__ __forceinline__ void fused_tile(
     // the table, GEMM1's a1[mb][s] first, then GEMM2's a2[mb2][s])
     float a1[NMB][KS1];
     float a2[MB2][KS2];
-    if (PREP) {
+    if (PREP_OPS) {
         constexpr int NA1 = NMB * KS1, NOPS = NA1 + MB2 * KS2, NQ = (NOPS + 3) / 4;
         const floatx4 *opq = reinterpret_cast<const floatx4 *>(io.prep + L.t_size) + lane;
         floatx4 q[NQ];
@@ -298,7 +296,7 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
         for (int s = 0; s < KS1; ++s) {
             int fi = 16 * mb + j, t = 4 * s + g;
-            if (!PREP) a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
+            if (!PREP_OPS) a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
         }
     // GEMM2 A operand: lane (g, j) supplies slot row j of block mb2, i.e.
     // register R' = 4 mb2 + (j & 3) in lane group j >> 2, and k-row g of k-step s,
@@ -316,7 +314,7 @@ __device__ __forceinline__ void fused_tile(
         for (int s = 0; s < KS2; ++s) {
             int fi = 16 * (s >> 2) + 4 * g + (s & 3);
             const int ta = slot_a[mb2], tb = slot_b[mb2];
-            if (!PREP) a2[mb2][s] = (fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f;
+            if (!PREP_OPS) a2[mb2][s] = (fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f;
         }
 
     // mixed precision: 16-wide k-steps, operands converted once to BF16/FP16
@@ -349,40 +347,8 @@ __device__ __forceinline__ void fused_tile(
                         MX::cvt((fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f);
                 }
     }
-    if (!PREP) __syncthreads();  // the staged filters are consumed
-
-    if (POLY && !PREP) {
-        // (4) coefficient table of the polynomial form from the staged weights:
-        // phi:        c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} + (-1)^k w_{j0-m})
-        // d phi / ds: c_k = Md[k][0] w_j0 + sum_{m>=1} Md[k][m] (w_{j0+m} - (-1)^k w_{j0-m})
-        // (the even-in-d part of a term centred at j0 vanishes for the derivative)
-        const int ni = POLY_NI, ni_used = poly_intervals(Nrbf);
-        const float(*pm)[POLY_MW + 1] = BWD ? rb.pmd : rb.pm;
-        constexpr int par = BWD ? 1 : 0;  // parity of k whose terms are sums
-        for (int idx = tid; idx < 16 * NMB * ni; idx += THREADS) {
-            const int fi = idx / ni, q = idx - fi * ni;
-            float c[POLY_NC];
-#pragma unroll
-            for (int k = 0; k < POLY_NC; ++k) c[k] = 0.f;
-            if (fi < Nk && q >= 1 && q <= ni_used - 2) {
-                const float *wc = sp + fi * L.w_pitch + (q - 1 - RBF_WIN) + POLY_PAD;  // w_j0
-                const float w0 = wc[0];
-#pragma unroll
-                for (int k = par; k < POLY_NC; k += 2) c[k] = pm[k][0] * w0;
-#pragma unroll
-                for (int m = 1; m <= POLY_MW; ++m) {
-                    const float sum = wc[m] + wc[-m], dif = wc[m] - wc[-m];
-#pragma unroll
-                    for (int k = 0; k < POLY_NC; ++k) c[k] = fmaf(pm[k][m], ((k & 1) == par) ? sum : dif, c[k]);
-                }
-            }
-            float *dst = stab + fi * POLY_TFP + 4 * q;
-            *reinterpret_cast<floatx4 *>(dst) = floatx4{c[0], c[1], c[2], c[3]};
-            *reinterpret_cast<floatx4 *>(dst + 4 * ni) = floatx4{c[4], c[5], c[6], c[7]};
-        }
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // the direct-to-LDS u tile loads have landed
-    __syncthreads();  // u tile and table complete; the staged weights are dead
+    __builtin_amdgcn_s_waitcnt(0);  // the direct-to-LDS u tile and table loads have landed
+    __syncthreads();  // u tile and table complete; the staged filters have been read
 
     // GEMM1 B-operand offsets: tap t = 4 s + g -> (a, b) = (t / KS, t % KS)
     int off1[KS1];
@@ -847,7 +813,7 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     io.react = s.react;
     io.proj_c = s.proj_c;
     io.prep = s.prep;
-    if (RBFM == RBF_POLY && PREC == PREC_F32 && !s.prep) return hipErrorInvalidValue;
+    if (RBFM == RBF_POLY && !s.prep) return hipErrorInvalidValue;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     dim3 grid(tiles * s.N);

@@ -32,9 +32,9 @@ struct StageArgs {
     float proj_c = 1.f;   // projected reaction: threshold c
     float *za = nullptr;  // input-gradient mode, FP32: if set, z = K u and a = K e at every
                           // pixel (za_index layout), the parameter-gradient kernels' input
-    const float *prep = nullptr;  // FP32 polynomial form: this stage's block written by
-                                  // fused_prep (phi table in the forward, d phi / ds in the
-                                  // input-gradient mode); required there
+    const float *prep = nullptr;  // polynomial form: this stage's block written by fused_prep
+                                  // (phi table in the forward, d phi / ds in the input-gradient
+                                  // mode; FP32 operands use its filter block too); required there
 };
 
 // Batched forward (device descriptors, filled on the host).

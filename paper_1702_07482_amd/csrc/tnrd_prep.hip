@@ -1,5 +1,5 @@
-// Per-call preparation of the fused stage kernel's stage constants (FP32
-// operands, polynomial influence form).
+// Per-call preparation of the fused stage kernel's stage constants
+// (polynomial influence form).
 //
 // Every workgroup of a stage launch needs the same two things, which depend
 // only on the stage's parameters, not on the image:
@@ -12,8 +12,9 @@
 // layout the fused kernel copies: per stage,
 //   [16 NMB filters][tf_pitch]      table (fused_lds().t_size floats)
 //   [ceil(NOPS / 4)][64 lanes][4]   operands, quad k4 of lane l
-// so a workgroup's prologue is a straight copy (table into LDS, operands into
-// registers) instead of ~1200 VALU instructions per wave.
+// so a workgroup's prologue is a straight copy (table into LDS, FP32 operands
+// into registers) instead of ~1200 VALU instructions per wave.  The BF16/FP16
+// kernels copy the table and stage their own operands.
 #include "tnrd_fused_tile.hpp"
 
 namespace tnrd {
@@ -53,8 +54,7 @@ __device__ void prep_stage_body(const float *__restrict__ filt, const float *__r
     const int ntab = 16 * NMB * ni;
     if (idx < ntab) {
         // c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} +- w_{j0-m}), j0 = q - 1 - W,
-        // weights outside [0, Nrbf) taken as 0 (the same sums, in the same
-        // order, as the in-kernel build of the polynomial form)
+        // weights outside [0, Nrbf) taken as 0
         const int fi = idx / ni, q = idx - fi * ni;
         const float(*pm)[POLY_MW + 1] = deriv ? rb.pmd : rb.pm;
         const int par = deriv ? 1 : 0;  // parity of k whose terms are sums
