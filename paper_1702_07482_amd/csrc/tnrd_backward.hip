@@ -619,16 +619,56 @@ BwdGeom bwd_geom(int N, int H, int W, int th)
     return gm;
 }
 
-// Tile height of k_bwd_params: the kernel holds two 4-wave workgroups per
-// compute unit (its register footprint), so n tiles run in ceil(n / (2 CUs))
-// rounds of th rows of BP_NBW blocks each (plus a fixed cost of ~4 blocks).
-int bwd_tile_h(int N, int H, int W)
+// Workgroups per compute unit that the k_bwd_params tile plan assumes for one
+// variant (loadza: z and a loaded from the export; else computed): the runtime's
+// occupancy for its register and LDS footprint, but at least 2 (with a single
+// resident workgroup the taller tiles of a 1-per-CU plan ran slower than the
+// 2-per-CU plan's); cached per thread.
+static int bp_per_cu(int ks, int nk, int nrbf, bool loadza)
+{
+    const int nmb = (nk + 15) / 16 <= 2 ? 2 : 3;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    static thread_local int key[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    static thread_local int cached[2] = {0, 0};
+    const int v = loadza ? 1 : 0;
+    if (key[v][0] == ks && key[v][1] == nmb && key[v][2] == nrbf && key[v][3] == dev) return cached[v];
+    const BpLds L = bp_lds(ks, nmb, BP_TH_MAX, 16 * BP_NBW, nrbf, BP_NW);
+    const void *k = nullptr;
+    if (ks == 7)
+        k = nmb == 2 ? (loadza ? (const void *)k_bwd_params<7, 2, BP_NBW, BP_NW, true>
+                               : (const void *)k_bwd_params<7, 2, BP_NBW, BP_NW, false>)
+                     : (loadza ? (const void *)k_bwd_params<7, 3, BP_NBW, BP_NW, true>
+                               : (const void *)k_bwd_params<7, 3, BP_NBW, BP_NW, false>);
+    else
+        k = nmb == 2 ? (loadza ? (const void *)k_bwd_params<5, 2, BP_NBW, BP_NW, true>
+                               : (const void *)k_bwd_params<5, 2, BP_NBW, BP_NW, false>)
+                     : (loadza ? (const void *)k_bwd_params<5, 3, BP_NBW, BP_NW, true>
+                               : (const void *)k_bwd_params<5, 3, BP_NBW, BP_NW, false>);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * BP_NW, (size_t)L.total * sizeof(float)) !=
+            hipSuccess ||
+        n < 2)
+        n = 2;
+    (void)hipGetLastError();
+    key[v][0] = ks;
+    key[v][1] = nmb;
+    key[v][2] = nrbf;
+    key[v][3] = dev;
+    cached[v] = n;
+    return n;
+}
+
+// Tile height of k_bwd_params: with p workgroups resident per compute unit, n
+// tiles run in ceil(n / (p CUs)) rounds of th rows of BP_NBW blocks each (plus a
+// fixed cost of ~4 blocks).
+int bwd_tile_h(int N, int H, int W, int ks, int nk, int nrbf, bool loadza)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    const long slots = 2L * cus;
+    const long slots = (long)bp_per_cu(ks, nk, nrbf, loadza) * cus;
     int best_th = BP_TH_MIN;
     double best = 0.0;
     for (int th = BP_TH_MIN; th <= BP_TH_MAX; ++th) {
@@ -836,7 +876,10 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
         return TNRD_OK;
     }
     BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep);
-    BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W));
+    // the two variants of k_bwd_params hold different numbers of workgroups per
+    // compute unit, so each gets its own tile height (gm: loading z and a)
+    BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, true));
+    const BwdGeom gm_own = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, false));
     const size_t img = gm.img;
     if (oo.validate) {
         st = run_domain_check(f, img, (int *)ws, stream);
@@ -924,15 +967,16 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
                 ia.prep = use_prep ? w.prep_b + (size_t)ts * prep_sf : nullptr;
                 if (fused_stage_input_grad(ia, stream) != hipSuccess) return TNRD_ERR_HIP;
             }
-            if (bwd_params(loadza, io, gm, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) !=
+            const BwdGeom &gp = loadza ? gm : gm_own;
+            if (bwd_params(loadza, io, gp, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) !=
                 hipSuccess)
                 return TNRD_ERR_HIP;
             if (bwd_dw(w.za, gm, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
                 return TNRD_ERR_HIP;
             const RedJob jobs[RED_JOBS] = {
-                {w.dk_part, grad_filters + (size_t)ts * m->Nk * kk, gm.tiles, (int)(m->Nk * kk), -1.f, 0},
+                {w.dk_part, grad_filters + (size_t)ts * m->Nk * kk, gp.tiles, (int)(m->Nk * kk), -1.f, 0},
                 {w.dw_part, grad_rbf_w + (size_t)ts * m->Nk * m->Nrbf, gm.dw_grid, m->Nk * m->Nrbf, -1.f, 0},
-                {w.dl_part, grad_lambda + ts, gm.tiles, 1, 1.f, 0}};
+                {w.dl_part, grad_lambda + ts, gp.tiles, 1, 1.f, 0}};
             if (reduce_partials(jobs, RED_JOBS, stream) != hipSuccess) return TNRD_ERR_HIP;
             if (need_g) {
                 g_cur = g_next;
