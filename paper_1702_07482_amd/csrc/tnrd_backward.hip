@@ -28,9 +28,10 @@
 // When it computes z and a itself, the filter-bank GEMM runs transposed
 // (rows = 16 pixels, columns = 16 filters) to leave them in that layout.
 //
-// k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms with one lane per
-// filter (each lane owns its column, each wave its histogram), so no two lanes
-// ever update the same word and no atomics are needed.
+// k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms, each lane working
+// on one filter and owning its column (a filter has several lanes, each with a
+// share of the pixels), so no two lanes ever update the same word and no
+// atomics are needed.
 #include <limits.h>
 #include <math.h>
 
@@ -446,9 +447,9 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
     }
 }
 
-// k_bwd_dw histograms are bin-major, [bin][64 lanes]: lane = filter, bin b of
-// filter i at word (b + 2W) * 64 + i.  Every lane of a wave owns a bank of its
-// own, so the 48 lanes of an update never conflict whatever bins their z
+// k_bwd_dw histograms are bin-major, [bin][64 lanes]: bin b of the lane's
+// filter at word (b + 2W) * 64 + lane.  Every lane of a wave owns a bank of its
+// own, so the 64 lanes of an update never conflict whatever bins their z
 // values fall in (a filter-major layout, [filter][bins], puts lanes whose
 // bins differ by a multiple of the bank count on one bank).  Updates are
 // plain read-modify-writes: the LDS float atomic add measured over ten times
@@ -470,30 +471,38 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
     float *hist = lds + wave * hsize + 2 * RBF_WIN * 64 + lane;
     const long long p0 = (long long)blockIdx.x * per_wg;
     const long long p1 = min(P, p0 + per_wg);
-    if (lane < Nk) {
+    // slot sl = 64 wave + lane bins filter sl mod Nk for every ns-th pixel of
+    // [p0, p1) from p0 + sl / Nk on, ns being the number of slots of that
+    // filter (every lane works, whatever Nk; the final sum adds a filter's slots)
+    const int sl = 64 * wave + lane;
+    const int fi = sl % Nk, sub = sl / Nk;
+    const int ns = (64 * NW - 1 - fi) / Nk + 1;
+    const long long npix = p1 - p0;
+    const long long steps = npix > 0 ? (npix + 64 * NW / Nk - 1) / (64 * NW / Nk) : 0;
+    if (steps > 0) {
         // DW_U pixels per step; the z and a of the next step are loaded while
         // this step's are binned (an element past p1 carries a = 0 and adds 0)
         constexpr int U = DW_U;
         float zn[U], an[U];
-        auto load = [&](long long pb) {
+        auto load = [&](long long kb) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const long long p = pb + (long long)u * NW;
+                const long long p = p0 + sub + (long long)ns * (kb + u);
                 const long long pc = p < p1 ? p : p0;
-                const size_t q = za_index((size_t)pc, Nk, lane);
+                const size_t q = za_index((size_t)pc, Nk, fi);
                 zn[u] = za[q];
                 an[u] = p < p1 ? za[q + 4] : 0.f;
             }
         };
-        load(p0 + wave);
-        for (long long pb = p0 + wave; pb < p1; pb += (long long)U * NW) {
+        load(0);
+        for (long long kb = 0; kb < steps; kb += U) {
             float zc[U], ac[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 zc[u] = zn[u];
                 ac[u] = an[u];
             }
-            load(pb + (long long)U * NW);
+            load(kb + U);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const float z = zc[u];
@@ -522,9 +531,9 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
     __syncthreads();
     float *dst = dw_part + (size_t)blockIdx.x * Nk * Nrbf;
     for (int i = tid; i < Nk * Nrbf; i += 64 * NW) {
-        int fi = i / Nrbf, jj = i - fi * Nrbf;
+        const int f = i / Nrbf, jj = i - f * Nrbf;
         float sum = 0.f;
-        for (int w = 0; w < NW; ++w) sum += lds[w * hsize + (jj + 2 * RBF_WIN) * 64 + fi];
+        for (int s2 = f; s2 < 64 * NW; s2 += Nk) sum += lds[(s2 >> 6) * hsize + (jj + 2 * RBF_WIN) * 64 + (s2 & 63)];
         dst[i] = sum;
     }
 }
