@@ -477,25 +477,29 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
     const int sl = 64 * wave + lane;
     const int fi = sl % Nk, sub = sl / Nk;
     const int ns = (64 * NW - 1 - fi) / Nk + 1;
-    const long long npix = p1 - p0;
-    const long long steps = npix > 0 ? (npix + 64 * NW / Nk - 1) / (64 * NW / Nk) : 0;
+    const int npix = (int)(p1 - p0);  // per_wg < 2^30 (host check)
+    const int steps = npix > 0 ? (npix + 64 * NW / Nk - 1) / (64 * NW / Nk) : 0;
     if (steps > 0) {
         // DW_U pixels per step; the z and a of the next step are loaded while
-        // this step's are binned (an element past p1 carries a = 0 and adds 0)
+        // this step's are binned.  Both loads always run (a pixel past p1 reads
+        // pixel p0 instead), and its a is replaced by 0, so it adds 0.
         constexpr int U = DW_U;
         float zn[U], an[U];
-        auto load = [&](long long kb) {
+        const float *zl = za + za_index((size_t)p0, Nk, fi);
+        const unsigned zst = (unsigned)za_stride(Nk);
+        auto load = [&](int kb) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const long long p = p0 + sub + (long long)ns * (kb + u);
-                const long long pc = p < p1 ? p : p0;
-                const size_t q = za_index((size_t)pc, Nk, fi);
-                zn[u] = za[q];
-                an[u] = p < p1 ? za[q + 4] : 0.f;
+                const int pl = sub + ns * (kb + u);
+                const bool in = pl < npix;
+                const float *qp = zl + (size_t)((unsigned)(in ? pl : 0) * zst);
+                const float zz = qp[0], aa = qp[4];
+                zn[u] = zz;
+                an[u] = in ? aa : 0.f;
             }
         };
         load(0);
-        for (long long kb = 0; kb < steps; kb += U) {
+        for (int kb = 0; kb < steps; kb += U) {
             float zc[U], ac[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -788,6 +792,9 @@ hipError_t launch_bwd_dw(const float *za, const BwdGeom &gm, int Nk,
         (void)hipGetLastError();
         attr_set = true;
     }
+    // the kernel indexes a workgroup's pixels with 32-bit offsets
+    if (gm.dw_per_wg >= (1LL << 30) || (long long)gm.dw_per_wg * za_stride(Nk) >= (1LL << 32))
+        return hipErrorInvalidValue;
     FusedRbf rb = make_fused_rbf(grid);
     hipLaunchKernelGGL((k_bwd_dw<NW>), dim3(gm.dw_grid), dim3(64 * NW), lds_bytes, stream,
                        za, (long long)gm.img, gm.dw_per_wg, Nk, grid.nrbf, rb, dw_part);
