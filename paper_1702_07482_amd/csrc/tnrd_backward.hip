@@ -114,8 +114,11 @@ __device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__rest
     dphi = in ? rb.rho_over_step * E * fmaf(q, accd, -(d + (float)RBF_WIN) * acc) : 0.f;
 }
 
+// The variant loading z and a is held to 128 registers (4 waves per SIMD when
+// the LDS allows it); it loads each block's z and a right before using them.
 template <int KS, int NMB, int NBW, int NW, bool LOADZA>
-__global__ void __launch_bounds__(64 * NW) k_bwd_params(
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LOADZA ? 4 : 1, 8)))
+k_bwd_params(
     BwdParamsIO io, int H, int W, int Th, int tiles_x, int tiles_per_img,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf, FusedRbf rb,
     const float *__restrict__ lam_t)
@@ -293,8 +296,8 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
 
     if constexpr (LOADZA) {
         // z and a exported by the input-gradient kernel, pixel 4 g + r of the
-        // block and filter 16 nb + j per lane; the next block's are loaded
-        // while this one is processed
+        // block and filter 16 nb + j per lane, loaded at the start of the block
+        // (the other waves of the SIMD cover the wait)
         const int ylim = min(Th, H - ty0);
         const int nrows = ylim > wave ? (ylim - wave + NW - 1) / NW : 0;
         const int nblk = nrows * NBW;
@@ -324,18 +327,11 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_params(
                 }
             }
         };
-        load(0);
 #pragma unroll 1
         for (int b = 0; b < nblk; ++b) {
-            float zc[NMB][4], ac[NMB][4];
-#pragma unroll
-            for (int nb = 0; nb < NMB; ++nb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    zc[nb][r] = zn[nb][r];
-                    ac[nb][r] = an[nb][r];
-                }
-            load(b + 1);
+            load(b);
+            const float(&zc)[NMB][4] = zn;
+            const float(&ac)[NMB][4] = an;
             const int y = wave + NW * (b / NBW), cb = b % NBW;
 #pragma unroll
             for (int nb = 0; nb < NMB; ++nb) {
@@ -633,20 +629,28 @@ BwdGeom bwd_geom(int N, int H, int W, int th)
 }
 
 // Workgroups per compute unit that the k_bwd_params tile plan assumes for one
-// variant (loadza: z and a loaded from the export; else computed): the runtime's
-// occupancy for its register and LDS footprint, but at least 2 (with a single
-// resident workgroup the taller tiles of a 1-per-CU plan ran slower than the
-// 2-per-CU plan's); cached per thread.
-static int bp_per_cu(int ks, int nk, int nrbf, bool loadza)
+// variant (loadza: z and a loaded from the export; else computed) and tile
+// height th: the runtime's occupancy for its register footprint and the LDS of
+// that tile, but at least 2 (with a single resident workgroup the taller tiles
+// of a 1-per-CU plan ran slower than the 2-per-CU plan's); cached per thread.
+static int bp_per_cu(int ks, int nk, int nrbf, bool loadza, int th)
 {
     const int nmb = (nk + 15) / 16 <= 2 ? 2 : 3;
     int dev = 0;
     (void)hipGetDevice(&dev);
     static thread_local int key[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
-    static thread_local int cached[2] = {0, 0};
+    static thread_local int cached[2][BP_TH_MAX + 1];
     const int v = loadza ? 1 : 0;
-    if (key[v][0] == ks && key[v][1] == nmb && key[v][2] == nrbf && key[v][3] == dev) return cached[v];
-    const BpLds L = bp_lds(ks, nmb, BP_TH_MAX, 16 * BP_NBW, nrbf, BP_NW);
+    th = th < BP_TH_MIN ? BP_TH_MIN : (th > BP_TH_MAX ? BP_TH_MAX : th);
+    if (!(key[v][0] == ks && key[v][1] == nmb && key[v][2] == nrbf && key[v][3] == dev)) {
+        for (int i = 0; i <= BP_TH_MAX; ++i) cached[v][i] = 0;
+        key[v][0] = ks;
+        key[v][1] = nmb;
+        key[v][2] = nrbf;
+        key[v][3] = dev;
+    }
+    if (cached[v][th] > 0) return cached[v][th];
+    const BpLds L = bp_lds(ks, nmb, th, 16 * BP_NBW, nrbf, BP_NW);
     const void *k = nullptr;
     if (ks == 7)
         k = nmb == 2 ? (loadza ? (const void *)k_bwd_params<7, 2, BP_NBW, BP_NW, true>
@@ -664,27 +668,23 @@ static int bp_per_cu(int ks, int nk, int nrbf, bool loadza)
         n < 2)
         n = 2;
     (void)hipGetLastError();
-    key[v][0] = ks;
-    key[v][1] = nmb;
-    key[v][2] = nrbf;
-    key[v][3] = dev;
-    cached[v] = n;
+    cached[v][th] = n;
     return n;
 }
 
-// Tile height of k_bwd_params: with p workgroups resident per compute unit, n
-// tiles run in ceil(n / (p CUs)) rounds of th rows of BP_NBW blocks each (plus a
-// fixed cost of ~4 blocks).
+// Tile height of k_bwd_params: with p(th) workgroups resident per compute unit,
+// n tiles run in ceil(n / (p CUs)) rounds of th rows of BP_NBW blocks each (plus
+// a fixed cost of ~4 blocks).
 int bwd_tile_h(int N, int H, int W, int ks, int nk, int nrbf, bool loadza)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    const long slots = (long)bp_per_cu(ks, nk, nrbf, loadza) * cus;
     int best_th = BP_TH_MIN;
     double best = 0.0;
     for (int th = BP_TH_MIN; th <= BP_TH_MAX; ++th) {
+        const long slots = (long)bp_per_cu(ks, nk, nrbf, loadza, th) * cus;
         const long tiles = (long)N * ((H + th - 1) / th) * ((W + 16 * BP_NBW - 1) / (16 * BP_NBW));
         const long rounds = (tiles + slots - 1) / slots;
         const double cost = (double)rounds * (th * BP_NBW + 4) + 1e-6 * th;
