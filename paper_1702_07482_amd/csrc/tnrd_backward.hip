@@ -116,8 +116,10 @@ __device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__rest
 
 // The variant loading z and a is held to 128 registers (4 waves per SIMD when
 // the LDS allows it); it loads each block's z and a right before using them.
+// The one computing them is held to 256 (2 waves per SIMD); it reads a filter
+// block's GEMM operands from the LDS copy of the bank when it starts the block.
 template <int KS, int NMB, int NBW, int NW, bool LOADZA>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LOADZA ? 4 : 1, 8)))
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LOADZA ? 4 : 2, 8)))
 k_bwd_params(
     BwdParamsIO io, int H, int W, int Th, int tiles_x, int tiles_per_img,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf, FusedRbf rb,
@@ -239,14 +241,14 @@ k_bwd_params(
     __syncthreads();
 
     // filter bank as the B operand of the transposed GEMM: B[k=g][n=j] = k_{16 nb + j}[tap 4 s + g]
-    float bf[NMB][KS1];
-#pragma unroll
-    for (int nb = 0; nb < NMB; ++nb)
+    // (block nb read from the staged bank in red when it is used)
+    auto load_bf = [&](int nb, float *bf) {
 #pragma unroll
         for (int s = 0; s < KS1; ++s) {
-            int fi = 16 * nb + j, t = 4 * s + g;
-            bf[nb][s] = (!LOADZA && fi < Nk && t < KK) ? red[fi * KK + t] : 0.f;
+            const int fi = 16 * nb + j, t = 4 * s + g;
+            bf[s] = (fi < Nk && t < KK) ? red[fi * KK + t] : 0.f;
         }
+    };
     int off1[KS1];
 #pragma unroll
     for (int s = 0; s < KS1; ++s) {
@@ -368,10 +370,12 @@ k_bwd_params(
 #pragma unroll
             for (int nb = 0; nb < NMB; ++nb) {
                 floatx4 accz = floatx4{0.f, 0.f, 0.f, 0.f}, acca = floatx4{0.f, 0.f, 0.f, 0.f};
+                float bf[KS1];
+                load_bf(nb, bf);
 #pragma unroll
                 for (int s = 0; s < KS1; ++s) {
-                    accz = __builtin_amdgcn_mfma_f32_16x16x4f32(bu[s], bf[nb][s], accz, 0, 0, 0);
-                    acca = __builtin_amdgcn_mfma_f32_16x16x4f32(be[s], bf[nb][s], acca, 0, 0, 0);
+                    accz = __builtin_amdgcn_mfma_f32_16x16x4f32(bu[s], bf[s], accz, 0, 0, 0);
+                    acca = __builtin_amdgcn_mfma_f32_16x16x4f32(be[s], bf[s], acca, 0, 0, 0);
                 }
                 // influence, export, and the two dK operands (v, h) in place
                 const float *row = stab + nb * 16 * L.t_pitch + j;
