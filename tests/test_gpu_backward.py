@@ -165,3 +165,32 @@ def test_backward_other_rbf_counts(nrbf, mu0):
     gT = uT - u
     ref = oracle.backward(f, m, st, gT)
     _check(_gpu_grads(f, m, gT), ref)
+
+
+@pytest.mark.parametrize("nk,ks", [(13, 5), (40, 7)])
+@pytest.mark.parametrize("want_u0", [True, False])
+def test_backward_uneven_filter_counts(nk, ks, want_u0):
+    """Filter counts that fill neither a 16-filter block nor the last 4-filter quad of the
+    z/a export and give the dW kernel's filters unequal numbers of lanes (13 filters: 34 or
+    35 of the 448 lanes), against the oracle.  Without dl/du_0 the first stage's B2 computes
+    z and a itself."""
+    print(f"[bwd nk {nk} ks {ks} want_u0 {want_u0}]", flush=True)
+    g = np.random.default_rng(4300 + nk)
+    m = synth.make_model(3, nk, ks, g)
+    u, f = _case(2, (37, 45), 2, index=nk)
+    uT, st = oracle.forward(f, m, want_states=True)
+    gT = uT - u
+    ref = oracle.backward(f, m, st, gT)
+    if want_u0:
+        _check(_gpu_grads(f, m, gT), ref)
+        return
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd = _dev(f)
+    _, states = tnrd.forward(fd, dm, want_states=True)
+    dK, dW, dl = tnrd.backward(fd, dm, states, _dev(gT))
+    torch.cuda.synchronize()
+    got = [dK.cpu().numpy(), dW.cpu().numpy(), dl.cpu().numpy()]
+    errs = {n: rel_inf(a, b) for n, a, b in zip(["dK", "dW", "dlam"], got, ref)}
+    print("rel errors", errs, flush=True)
+    for n, e in errs.items():
+        assert e <= TOL, (n, errs)
