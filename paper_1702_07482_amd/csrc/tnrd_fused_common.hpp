@@ -12,16 +12,28 @@ namespace tnrd {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short short4v __attribute__((ext_vector_type(4)));
 typedef _Float16 half4v __attribute__((ext_vector_type(4)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef int int2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 // Operand types of the 16x16x16 MFMAs used by the mixed-precision path
 // (v_mfma_f32_16x16x16_{bf16,f16}): lane l holds A[l % 16][4 (l / 16) + i]
 // and B[4 (l / 16) + i][l % 16], i = 0..3; D is laid out as for 16x16x4 f32.
-// Conversions round to nearest even.
+// Conversions round to nearest even.  The BF16 cvt4 converts four values as
+// two packed pairs joined as 32-bit words: converting element by element into
+// the operand vector compiled to one conversion per value plus a repacking
+// permute per pair (FP16 pairs them either way).
 enum Prec { PREC_F32 = 0, PREC_BF16 = 1, PREC_F16 = 2 };
 template <int P> struct Mix;
 template <> struct Mix<PREC_BF16> {
     typedef short4v V;
     static __device__ __forceinline__ short cvt(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+    static __device__ __forceinline__ V cvt4(floatx4 x)
+    {
+        const int lo = __builtin_bit_cast(int, __builtin_convertvector(float2v{x[0], x[1]}, bf16x2v));
+        const int hi = __builtin_bit_cast(int, __builtin_convertvector(float2v{x[2], x[3]}, bf16x2v));
+        return __builtin_bit_cast(V, int2v{lo, hi});
+    }
     static __device__ __forceinline__ floatx4 mfma(V a, V b, floatx4 c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -30,6 +42,10 @@ template <> struct Mix<PREC_BF16> {
 template <> struct Mix<PREC_F16> {
     typedef half4v V;
     static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+    static __device__ __forceinline__ V cvt4(floatx4 x)  // element-wise compiles well for FP16
+    {
+        return V{(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3]};
+    }
     static __device__ __forceinline__ floatx4 mfma(V a, V b, floatx4 c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
@@ -38,6 +54,7 @@ template <> struct Mix<PREC_F16> {
 template <> struct Mix<PREC_F32> {  // placeholder so templates instantiate; never used
     typedef short4v V;
     static __device__ __forceinline__ short cvt(float) { return 0; }
+    static __device__ __forceinline__ V cvt4(floatx4) { return V{0, 0, 0, 0}; }
     static __device__ __forceinline__ floatx4 mfma(V, V, floatx4 c) { return c; }
 };
 

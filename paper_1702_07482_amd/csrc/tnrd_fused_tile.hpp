@@ -384,12 +384,16 @@ __device__ __forceinline__ void fused_tile(
         const float *eb = se + (e + 2 * R) * L.ldw + cc + 2 * R;
         if (MIXED) {
 #pragma unroll
-            for (int s = 0; s < KSH; ++s)
+            for (int s = 0; s < KSH; ++s) {
+                floatx4 xu, xe;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    bum[s][i] = MX::cvt(ub[-offm[s][i]]);
-                    if (BWD) bem[s][i] = MX::cvt(escale * eb[-offm[s][i]]);
+                    xu[i] = ub[-offm[s][i]];
+                    xe[i] = BWD ? escale * eb[-offm[s][i]] : 0.f;
                 }
+                bum[s] = MX::cvt4(xu);
+                if (BWD) bem[s] = MX::cvt4(xe);
+            }
         } else {
 #pragma unroll
             for (int s = 0; s < KS1; ++s) {
@@ -493,9 +497,7 @@ __device__ __forceinline__ void fused_tile(
     // GEMM2 k-steps of filter group mb: Y += K^T-slots . v
     auto gemm2_group = [&](const floatx4 *acc1, int mb, floatx4 *acc2) {
         if (MIXED) {
-            MV vb;  // filters 16 mb + 4 g + i of pixel j: GEMM1's register quad
-#pragma unroll
-            for (int i = 0; i < 4; ++i) vb[i] = MX::cvt(acc1[mb][i]);
+            const MV vb = MX::cvt4(acc1[mb]);  // filters 16 mb + 4 g + i of pixel j: GEMM1's quad
 #pragma unroll
             for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = MX::mfma(a2m[mb2][mb], vb, acc2[mb2]);
         } else {
