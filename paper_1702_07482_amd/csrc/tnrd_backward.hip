@@ -796,8 +796,10 @@ hipError_t launch_bwd_dw(const float *za, const BwdGeom &gm, int Nk,
         (void)hipGetLastError();
         attr_set = true;
     }
-    // the kernel indexes a workgroup's pixels with 32-bit offsets
-    if (gm.dw_per_wg >= (1LL << 30) || (long long)gm.dw_per_wg * za_stride(Nk) >= (1LL << 32))
+    // the kernel indexes a workgroup's pixels with 32-bit offsets and gives
+    // every filter at least one of its 64 NW lanes
+    if (gm.dw_per_wg >= (1LL << 30) || (long long)gm.dw_per_wg * za_stride(Nk) >= (1LL << 32) ||
+        Nk < 1 || Nk > 64 * NW)
         return hipErrorInvalidValue;
     FusedRbf rb = make_fused_rbf(grid);
     hipLaunchKernelGGL((k_bwd_dw<NW>), dim3(gm.dw_grid), dim3(64 * NW), lds_bytes, stream,
