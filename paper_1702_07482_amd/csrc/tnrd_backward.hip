@@ -628,6 +628,7 @@ BwdGeom bwd_geom(int N, int H, int W, int th)
     if (grid > 256) grid = 256;
     if (grid < 1) grid = 1;
     gm.dw_per_wg = (P + grid - 1) / grid;
+    if (gm.dw_per_wg < 1) gm.dw_per_wg = 1;  // no pixels: an empty dW grid
     gm.dw_grid = (int)((P + gm.dw_per_wg - 1) / gm.dw_per_wg);
     return gm;
 }

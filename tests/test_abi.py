@@ -101,6 +101,13 @@ def test_workspace_checks_happen_before_any_launch():
 def test_empty_batch_is_a_no_op():
     assert _fwd(_model(), N=0) == tnrd.TNRD_OK
     assert _fwd(_model(reaction=1, proj_c=1.0), N=0) == tnrd.TNRD_OK
+    m = _model()
+    o = tnrd.default_opts()
+    # the backward's workspace size for no images (its dW grid is empty)
+    assert tnrd.tnrd_workspace_bytes(0, 32, 32, m, o, 1) > 0
+    # an uneven batch of no images: no workspace, no launch
+    lib = tnrd.load()
+    assert lib.tnrd_forward_batched(0, None, 1, ctypes.byref(m), ctypes.byref(o), None, 0, None) == tnrd.TNRD_OK
 
 
 def test_backward_rejects_grad_f_aliasing_grad_u0():

@@ -194,3 +194,22 @@ def test_backward_uneven_filter_counts(nk, ks, want_u0):
     print("rel errors", errs, flush=True)
     for n, e in errs.items():
         assert e <= TOL, (n, errs)
+
+
+def test_backward_of_an_empty_batch_zeroes_the_gradients():
+    """N = 0: the call succeeds without a workspace and leaves every parameter
+    gradient at zero (the sum over no images)."""
+    print("[bwd empty batch]", flush=True)
+    m = synth.config_model(1)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    T, Nk, ks, Nrbf = m["T"], m["Nk"], m["ks"], m["Nrbf"]
+    dK = torch.full((T, Nk, ks, ks), float("nan"), device="cuda")
+    dW = torch.full((T, Nk, Nrbf), float("nan"), device="cuda")
+    dl = torch.full((T,), float("nan"), device="cuda")
+    dummy = torch.ones(1, device="cuda")
+    st = tnrd.tnrd_backward(dummy, 0, 32, 32, 1, dm.abi(), dummy, dummy, dK, dW, dl, None, None,
+                            tnrd.default_opts(), None, 0)
+    torch.cuda.synchronize()
+    assert st == tnrd.TNRD_OK, tnrd.status_str(st)
+    for g in (dK, dW, dl):
+        assert torch.count_nonzero(g).item() == 0
