@@ -599,6 +599,13 @@ __global__ void __launch_bounds__(256) k_add_plane(float *__restrict__ acc, cons
     if (i < n) acc[i] += x[i];
 }
 
+// p[0 .. n) = 0 (a kernel, not a memset, so that a captured graph replays it correctly)
+__global__ void __launch_bounds__(256) k_zero(float *__restrict__ p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -820,6 +827,13 @@ hipError_t bwd_dw(const float *za, const BwdGeom &gm, int Nk,
 }
 
 // acc += x over n floats.
+hipError_t zero_floats(float *p, size_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
 hipError_t add_plane(float *acc, const float *x, size_t n, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
@@ -892,9 +906,9 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     const size_t kk = (size_t)m->ksize * m->ksize;
     if (N == 0) {
         // empty batch: every gradient is zero
-        if (hipMemsetAsync(grad_filters, 0, (size_t)T * m->Nk * kk * sizeof(float), stream) != hipSuccess ||
-            hipMemsetAsync(grad_rbf_w, 0, (size_t)T * m->Nk * m->Nrbf * sizeof(float), stream) != hipSuccess ||
-            hipMemsetAsync(grad_lambda, 0, (size_t)T * sizeof(float), stream) != hipSuccess)
+        if (zero_floats(grad_filters, (size_t)T * m->Nk * kk, stream) != hipSuccess ||
+            zero_floats(grad_rbf_w, (size_t)T * m->Nk * m->Nrbf, stream) != hipSuccess ||
+            zero_floats(grad_lambda, (size_t)T, stream) != hipSuccess)
             return TNRD_ERR_HIP;
         return TNRD_OK;
     }
