@@ -172,7 +172,8 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
  *                                       s = sqrt(ut^2 + 8(1+2l) l f^2); projected:
  *                                       2 l f / u_{t-1}^3 where ut_t > c, else 0; l2: l)
  * lambda^t must be > 0.  Results are deterministic: the same inputs give the
- * same bits for every recompute_every.  Errors as tnrd_forward, and
+ * same bits for every recompute_every.  N = 0 needs no workspace and writes
+ * zeros to the three parameter gradients.  Errors as tnrd_forward, and
  * TNRD_ERR_ARG for NULL states/grad pointers or grad_f aliasing grad_u0. */
 int tnrd_backward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
                   const float *states, const float *grad_uT,
