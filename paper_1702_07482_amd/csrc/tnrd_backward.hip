@@ -457,7 +457,8 @@ k_bwd_params(
 __host__ __device__ inline int dw_bins(int nrbf) { return nrbf + 4 * RBF_WIN; }
 __host__ __device__ inline size_t dw_wave_bytes(int nrbf) { return (size_t)dw_bins(nrbf) * 64 * sizeof(float); }
 
-// dW partial sums: lane = filter, each wave its own histogram.
+// dW partial sums: each wave its own histogram, each lane one filter and a share
+// of the workgroup's pixels.
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
     const float *__restrict__ za, long long P, long long per_wg,
