@@ -196,9 +196,15 @@ typedef struct tnrd_image {
  * uses the model whose L equals its own, else one with L == 0.  Workspace from
  * tnrd_batched_workspace_bytes.  With opts->use_graph (default) and a non-null
  * stream, the descriptor upload and the T launches are recorded once into a HIP
- * graph per (stream, workspace, batch signature: pointers, sizes, looks,
- * models, tiles) and replayed on later calls; the pinned copy of the
- * descriptors stays alive as long as the graph.  Tiles: opts->tile_h/tile_w
+ * graph per (stream, workspace, batch signature: image pointers, sizes and
+ * looks; every model field, parameter pointers, reaction and proj_c included;
+ * tiles) and replayed on later calls.  Host resources of that path, the one
+ * exception to "allocates nothing": the first call of a new signature records
+ * the graph and allocates one pinned host buffer holding the descriptors (a
+ * few bytes per tile, the source of the recorded upload); both live until the
+ * entry is evicted.  The cache holds 8 entries across all callers; evicting
+ * the oldest waits for the stream it was recorded on.  The cache is guarded
+ * by a mutex, so concurrent calls are safe.  Tiles: opts->tile_h/tile_w
  * (default 32 x 32; both must be >= ksize - 1) and opts->wg_waves.  Errors as
  * tnrd_forward, plus TNRD_ERR_ARG for an image whose L matches no model or
  * models that disagree in shape. */

@@ -68,6 +68,8 @@ def _load():
                                        _D, _D, _D, i]
         lib.oracle_forward_ex.argtypes = [_D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D, i, d,
                                           _D, _D, _D, i]
+        lib.oracle_stage_ex.argtypes = [_D, _D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D, i, d,
+                                        _D, _D, i]
         lib.oracle_backward.argtypes = [_D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D,
                                         _D, _D, _D, _D, _D, _D, i]
         lib.oracle_backward_ex.argtypes = [_D, i, i, i, i, i, i, i, d, d, d, _D, _D, _D, i, d,
@@ -219,6 +221,27 @@ def forward(f, model, want_states: bool = False, want_utilde: bool = False,
     if want_utilde:
         out.append(utilde[:, 0] if squeeze else utilde)
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def stage(u_prev, f, model, t: int, nthreads: int = 0):
+    """Stage t (0-based) alone: u_t from u_prev [N][H][W] (or [H][W]) with data
+    f.  Returns (u_t, ut_t)."""
+    u_prev, f = _f64(u_prev), _f64(f)
+    squeeze = f.ndim == 2
+    if squeeze:
+        f, u_prev = f[None], u_prev[None]
+    assert u_prev.shape == f.shape
+    N, H, W = f.shape
+    filters, rbf_w, lam, T, Nk, ks, Nrbf = _model_args(model)
+    assert 0 <= t < T
+    ut = np.empty_like(f)
+    un = np.empty_like(f)
+    react, cproj = _reaction(model)
+    _load().oracle_stage_ex(_p(u_prev), _p(f), N, H, W, int(t), Nk, ks, Nrbf,
+                            float(model["mu0"]), float(model["step"]), float(model["sigma"]),
+                            _p(filters), _p(rbf_w), _p(lam), react, cproj, _p(ut), _p(un),
+                            int(nthreads))
+    return (un[0], ut[0]) if squeeze else (un, ut)
 
 
 def backward(f, model, states, gT, nthreads: int = 0, want_df: bool = False):

@@ -289,6 +289,22 @@ static void stage_forward(const double *u_prev, const double *f, int H, int W, i
     free(z); free(v); free(xi); free(x);
 }
 
+/* Stage t alone (0-based) on N images: u_next = stage_t(u_prev) with data f,
+ * and the pre-reaction values ut.  The same routine the forward chains; it lets
+ * a caller start a stage from states of its own. */
+void oracle_stage_ex(const double *u_prev, const double *f, int N, int H, int W, int t,
+                     int Nk, int ks, int Nrbf, double mu0, double step, double sigma,
+                     const double *filters, const double *rbf_w, const double *lam,
+                     int reaction, double cproj, double *ut, double *u_next, int nthreads)
+{
+    set_threads(nthreads);
+    size_t n = (size_t)H * W;
+    for (int img = 0; img < N; ++img)
+        stage_forward(u_prev + (size_t)img * n, f + (size_t)img * n, H, W, t, Nk, ks, Nrbf,
+                      mu0, step, sigma, filters, rbf_w, lam, reaction, cproj,
+                      ut + (size_t)img * n, u_next + (size_t)img * n);
+}
+
 /* Forward pass of the T-stage filter over N images of H x W.
  *   uT      [N][H][W]               output u_T
  *   states  [T+1][N][H][W] or NULL  u_0 .. u_T

@@ -5,7 +5,6 @@
 #include <math.h>
 #include <string.h>
 
-#include <vector>
 
 #include "tnrd.h"
 #include "tnrd_api_internal.hpp"
@@ -31,6 +30,9 @@ __global__ void k_check_domain(const float *__restrict__ f, size_t n, int *flag)
     }
     if (bad) atomicOr(flag, 1);
 }
+
+// flag[0] = 0 (a kernel rather than a memset node, safe where callers capture graphs)
+__global__ void k_clear_flag(int *flag) { flag[0] = 0; }
 
 }  // namespace
 
@@ -154,7 +156,8 @@ size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opt
 
 int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream)
 {
-    if (hipMemsetAsync(dflag, 0, sizeof(int), stream) != hipSuccess) return TNRD_ERR_HIP;
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, stream, dflag);
+    if (hipGetLastError() != hipSuccess) return TNRD_ERR_HIP;
     int blocks = (int)((n + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
@@ -217,6 +220,88 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
     return TNRD_OK;
 }
 
+int plan_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                 const float *u_out, const float *states, const tnrd_opts &oo, ForwardPlan *p)
+{
+    int st = check_image_args(f, N, H, W, L, m, u_out);
+    if (st != TNRD_OK) return st;
+    if (oo.prec < TNRD_PREC_FP32 || oo.prec > TNRD_PREC_FP16) return TNRD_ERR_ARG;
+    if (states && (states == f || states == u_out)) return TNRD_ERR_ARG;
+    p->window = rbf_window_for(m, oo.rbf_window);
+    p->impl = choose_impl(m, oo, p->window);
+    if (p->impl < 0) return p->impl;
+    p->ws_bytes = 0;
+    if (N == 0) return TNRD_OK;
+    if (p->impl == TNRD_IMPL_FUSED &&
+        !fused_config_ok(m->ksize, m->Nk, m->Nrbf, H, W, oo.tile_h, oo.tile_w, oo.wg_waves, 0))
+        return TNRD_ERR_UNSUPPORTED;
+    p->ws_bytes = forward_ws_bytes(N, H, W, m, oo, p->impl);
+    return TNRD_OK;
+}
+
+int run_forward(const float *f, int N, int H, int W, const tnrd_model *m, float *u_out,
+                float *states, const tnrd_opts &oo, const ForwardPlan &p, void *ws,
+                hipStream_t stream)
+{
+    const int impl = p.impl, window = p.window;
+    char *base = (char *)ws;
+    int *dflag = (int *)base;
+    size_t img = (size_t)N * H * W;
+    size_t scratch_floats = impl == TNRD_IMPL_SPLIT ? split_scratch_floats(N, H, W, m->Nk)
+                                                    : fused_scratch_floats(N, H, W, m->Nk, oo.prec);
+    float *scratch = (float *)(base + WS_ALIGN);
+    float *ping[2] = {nullptr, nullptr};
+    char *after = base + WS_ALIGN + align_up(scratch_floats * sizeof(float));
+    if (m->T > 1) {
+        ping[0] = (float *)after;
+        ping[1] = (float *)((char *)ping[0] + align_up(img * sizeof(float)));
+        after += 2 * align_up(img * sizeof(float));
+    }
+    float *prep = prep_region_floats(m, oo, impl, window, m->T) ? (float *)after : nullptr;
+
+    if (oo.validate) {
+        int st = run_domain_check(f, img, dflag, stream);
+        if (st != TNRD_OK) return st;
+    }
+
+    const int T = m->T;
+    const int s = oo.recompute_every < 1 ? 1 : oo.recompute_every;
+    if (states) {
+        if (hipMemcpyAsync(states, f, img * sizeof(float), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess)
+            return TNRD_ERR_HIP;
+    }
+    // destinations: stage t (0-based) writes u_{t+1}: u_out at the last stage, its
+    // checkpoint slot if it has one, else the ping-pong plane the input is not in.
+    // Stages run in chunks of a fixed number (one preparation launch per chunk),
+    // so the destination list lives on the stack.
+    constexpr int CHUNK = 64;
+    float *dsts[CHUNK];
+    const float *cur = f;
+    for (int t0 = 0; t0 < T; t0 += CHUNK) {
+        const int t1 = T < t0 + CHUNK ? T : t0 + CHUNK;
+        const float *start = cur;
+        for (int t = t0; t < t1; ++t) {
+            int slot = states ? checkpoint_slot(t + 1, T, s) : -1;
+            float *d;
+            if (t + 1 == T) d = u_out;
+            else if (slot >= 0) d = states + (size_t)slot * img;
+            else d = (cur == ping[0]) ? ping[1] : ping[0];
+            dsts[t - t0] = d;
+            cur = d;
+        }
+        int st = run_stages(f, N, H, W, m, oo, impl, window, t0, t1, start, dsts, scratch, prep, stream);
+        if (st != TNRD_OK) return st;
+    }
+    if (states) {
+        float *last = states + (size_t)(tnrd_num_checkpoints(T, s) - 1) * img;
+        if (hipMemcpyAsync(last, u_out, img * sizeof(float), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess)
+            return TNRD_ERR_HIP;
+    }
+    return TNRD_OK;
+}
+
 }  // namespace tnrd
 
 extern "C" {
@@ -262,69 +347,12 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
 {
     tnrd_opts oo;
     resolve_opts(o, &oo);
-    int st = check_image_args(f, N, H, W, L, m, u_out);
+    ForwardPlan p;
+    int st = plan_forward(f, N, H, W, L, m, u_out, states, oo, &p);
     if (st != TNRD_OK) return st;
-    if (oo.prec < TNRD_PREC_FP32 || oo.prec > TNRD_PREC_FP16) return TNRD_ERR_ARG;
-    if (states && (states == f || states == u_out)) return TNRD_ERR_ARG;
-    int window = rbf_window_for(m, oo.rbf_window);
-    int impl = choose_impl(m, oo, window);
-    if (impl < 0) return impl;
     if (N == 0) return TNRD_OK;
-    if (impl == TNRD_IMPL_FUSED &&
-        !fused_config_ok(m->ksize, m->Nk, m->Nrbf, H, W, oo.tile_h, oo.tile_w, oo.wg_waves, 0))
-        return TNRD_ERR_UNSUPPORTED;
-    size_t need = forward_ws_bytes(N, H, W, m, oo, impl);
-    if (!ws || ws_bytes < need) return TNRD_ERR_WORKSPACE;
-
-    hipStream_t stream = (hipStream_t)stream_;
-    char *base = (char *)ws;
-    int *dflag = (int *)base;
-    size_t img = (size_t)N * H * W;
-    size_t scratch_floats = impl == TNRD_IMPL_SPLIT ? split_scratch_floats(N, H, W, m->Nk)
-                                                    : fused_scratch_floats(N, H, W, m->Nk, oo.prec);
-    float *scratch = (float *)(base + WS_ALIGN);
-    float *ping[2] = {nullptr, nullptr};
-    char *after = base + WS_ALIGN + align_up(scratch_floats * sizeof(float));
-    if (m->T > 1) {
-        ping[0] = (float *)after;
-        ping[1] = (float *)((char *)ping[0] + align_up(img * sizeof(float)));
-        after += 2 * align_up(img * sizeof(float));
-    }
-    float *prep = prep_region_floats(m, oo, impl, window, m->T) ? (float *)after : nullptr;
-
-    if (oo.validate) {
-        st = run_domain_check(f, img, dflag, stream);
-        if (st != TNRD_OK) return st;
-    }
-
-    const int T = m->T;
-    const int s = oo.recompute_every < 1 ? 1 : oo.recompute_every;
-    // destinations: stage t (0-based) writes u_{t+1}
-    std::vector<float *> dsts(T);
-    const float *cur = f;
-    for (int t = 0; t < T; ++t) {
-        int slot = states ? checkpoint_slot(t + 1, T, s) : -1;
-        float *d;
-        if (t + 1 == T) d = u_out;
-        else if (slot >= 0) d = states + (size_t)slot * img;
-        else d = (cur == ping[0]) ? ping[1] : ping[0];
-        dsts[t] = d;
-        cur = d;
-    }
-    if (states) {
-        if (hipMemcpyAsync(states, f, img * sizeof(float), hipMemcpyDeviceToDevice, stream) !=
-            hipSuccess)
-            return TNRD_ERR_HIP;
-    }
-    st = run_stages(f, N, H, W, m, oo, impl, window, 0, T, f, dsts.data(), scratch, prep, stream);
-    if (st != TNRD_OK) return st;
-    if (states) {
-        float *last = states + (size_t)(tnrd_num_checkpoints(T, s) - 1) * img;
-        if (hipMemcpyAsync(last, u_out, img * sizeof(float), hipMemcpyDeviceToDevice, stream) !=
-            hipSuccess)
-            return TNRD_ERR_HIP;
-    }
-    return TNRD_OK;
+    if (!ws || ws_bytes < p.ws_bytes) return TNRD_ERR_WORKSPACE;
+    return run_forward(f, N, H, W, m, u_out, states, oo, p, ws, (hipStream_t)stream_);
 }
 
 const char *tnrd_status_str(int status)

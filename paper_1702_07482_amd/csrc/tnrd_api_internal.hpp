@@ -29,6 +29,21 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
 size_t prep_region_floats(const tnrd_model *m, const tnrd_opts &o, int impl, int window,
                           int stages);
 
+// Argument checks and plan of a forward call (tnrd_forward): the stage
+// implementation, the influence window and the workspace bytes it needs (0 for
+// N = 0).  Returns TNRD_OK or the status tnrd_forward returns for these arguments.
+struct ForwardPlan {
+    int impl, window;
+    size_t ws_bytes;
+};
+int plan_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                 const float *u_out, const float *states, const tnrd_opts &oo, ForwardPlan *p);
+// Runs a planned forward (N > 0) on a workspace of at least p.ws_bytes.  Allocates
+// nothing, host or device.
+int run_forward(const float *f, int N, int H, int W, const tnrd_model *m, float *u_out,
+                float *states, const tnrd_opts &oo, const ForwardPlan &p, void *ws,
+                hipStream_t stream);
+
 size_t backward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o,
                          int window);
 

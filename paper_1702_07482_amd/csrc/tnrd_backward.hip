@@ -752,13 +752,7 @@ hipError_t launch_bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, in
 {
     BpLds L = bp_lds(KS, NMB, gm.th, 16 * BP_NBW, grid.nrbf, BP_NW);
     size_t lds_bytes = (size_t)L.total * sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr_set = true;
-    }
+    raise_lds_limit((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA>);
     const int per_img = gm.tiles_x * gm.tiles_y;
     FusedRbf rb = make_fused_rbf(grid);
     hipLaunchKernelGGL((k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA>), dim3(gm.tiles), dim3(64 * BP_NW),
@@ -798,13 +792,7 @@ hipError_t launch_bwd_dw(const float *za, const BwdGeom &gm, int Nk,
                          const RbfGrid &grid, float *dw_part, hipStream_t stream)
 {
     const size_t lds_bytes = NW * dw_wave_bytes(grid.nrbf);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_bwd_dw<NW>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr_set = true;
-    }
+    raise_lds_limit((const void *)k_bwd_dw<NW>);
     // the kernel indexes a workgroup's pixels with 32-bit offsets and gives
     // every filter at least one of its 64 NW lanes
     if (gm.dw_per_wg >= (1LL << 30) || (long long)gm.dw_per_wg * za_stride(Nk) >= (1LL << 32) ||

@@ -205,12 +205,16 @@ std::vector<unsigned long long> signature(int B, const tnrd_image *imgs, int n_m
         I(m.ksize);
         I(m.Nrbf);
         I(m.L);
-        float fl[3] = {m.rbf_mu0, m.rbf_step, m.rbf_sigma};
-        unsigned int u[3];
+        I(m.reaction);
+        // every float field by its bits (the recorded descriptor copy carries
+        // reaction and proj_c, so a replay must not serve a model that differs there)
+        float fl[4] = {m.rbf_mu0, m.rbf_step, m.rbf_sigma, m.proj_c};
+        unsigned int u[4];
         memcpy(u, fl, sizeof(u));
         I(u[0]);
         I(u[1]);
         I(u[2]);
+        I(u[3]);
     }
     return s;
 }

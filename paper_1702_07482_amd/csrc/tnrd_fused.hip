@@ -3,6 +3,8 @@
 // tnrd_fused_{fwd,mixed,bwd,batched}.hip.
 #include <string.h>
 
+#include <atomic>
+
 #include "tnrd_fused_tile.hpp"
 
 namespace tnrd {
@@ -115,19 +117,20 @@ static bool lds_fits(int ks, int nk, int nrbf, int th, int tw, int nb, int nw, i
     return (size_t)L.total * sizeof(float) <= 160 * 1024;
 }
 
-// Compute units of the current device (cached per device).
+// Compute units of the current device (cached per device; concurrent first
+// calls from several threads store the same value).
 static int device_cus()
 {
-    static int cus[64] = {0};
+    static std::atomic<int> cus[64] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cus[dev] == 0) {
-        int n = 0;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
             n = 256;
-        cus[dev] = n;
+        cus[dev].store(n, std::memory_order_relaxed);
     }
-    return cus[dev];
+    return n;
 }
 
 struct TilePlan {

@@ -794,15 +794,7 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
 {
     FusedLds L = fused_lds(KS, NMB, NB, th, tw, s.grid.nrbf, NW, MODE, RBFM);
     size_t lds_bytes = (size_t)L.total * sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
-        // raise the dynamic LDS limit to the CU's 160 KB; a failure here shows
-        // up as a launch error below, so the status is cleared
-        (void)hipFuncSetAttribute((const void *)k_fused_stage<KS, NMB, NB, NW, MODE, PREC, RBFM>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr_set = true;
-    }
+    raise_lds_limit((const void *)k_fused_stage<KS, NMB, NB, NW, MODE, PREC, RBFM>);
     if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     FusedRbf rb = make_fused_rbf(s.grid);
     FusedIO io{};
@@ -856,13 +848,7 @@ inline hipError_t launch_batched_t(const BatchArgs &a, hipStream_t stream)
 {
     FusedLds L = fused_lds(KS, NMB, NB, a.Th, a.Tw, a.Nrbf, NW, MODE_FWD, RBFM);
     const size_t lds_bytes = (size_t)L.total * sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_batched_stage<KS, NMB, NB, NW, RBFM>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr_set = true;
-    }
+    raise_lds_limit((const void *)k_batched_stage<KS, NMB, NB, NW, RBFM>);
     if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     for (int t = 0; t < a.T; ++t) {
         hipLaunchKernelGGL((k_batched_stage<KS, NMB, NB, NW, RBFM>), dim3(a.items_per_stage),

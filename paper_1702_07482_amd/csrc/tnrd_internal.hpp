@@ -5,10 +5,38 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "tnrd_device.hpp"
 #include "tnrd_fused_common.hpp"
 
 namespace tnrd {
+
+// Raises a kernel's dynamic LDS limit to the compute unit's 160 KB, once per
+// (kernel, device), safely from any number of host threads, without
+// allocating (a fixed table; past its capacity the attribute is simply set
+// again, which is idempotent).  A failure shows up as a launch error of the
+// kernel, so the status is cleared here.
+inline void raise_lds_limit(const void *kernel)
+{
+    constexpr int CAP = 1024;
+    static std::mutex mu;
+    static const void *done_k[CAP];
+    static int done_d[CAP];
+    static int n_done = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < n_done; ++i)
+        if (done_k[i] == kernel && done_d[i] == dev) return;
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    if (n_done < CAP) {
+        done_k[n_done] = kernel;
+        done_d[n_done] = dev;
+        ++n_done;
+    }
+}
 
 // One forward stage over N equally sized images.
 struct StageArgs {

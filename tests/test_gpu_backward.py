@@ -213,3 +213,41 @@ def test_backward_of_an_empty_batch_zeroes_the_gradients():
     assert st == tnrd.TNRD_OK, tnrd.status_str(st)
     for g in (dK, dW, dl):
         assert torch.count_nonzero(g).item() == 0
+
+
+def test_c3_full_batch_every_output():
+    """The whole forward + backward workload: 16 x 180 x 180, L = 1, 8 stages of
+    48 7x7 filters, dl/du_T = 2 (u_T - u_gt) / n from the oracle's u_T.  Every
+    pixel of all 9 states against the oracle's forward; dK, dW, dlambda and
+    dl/du_0 against the oracle's backward (stored by
+    tests/golden/make_c3_reference.py, checked by digest first), with the
+    gradients computed under stage recomputation (every 4th state kept), as
+    the workload specifies."""
+    import os
+
+    from tests.golden import make_c3_reference as ref3
+
+    path = ref3.OUT
+    if not os.path.exists(path):
+        pytest.fail(f"{path} missing: run python tests/golden/make_c3_reference.py")
+    gold = np.load(path, allow_pickle=False)
+    m, u, f = ref3.case()
+    assert str(gold["digest_f"]) == ref3.digest(f) and str(gold["digest_u"]) == ref3.digest(u)
+    assert str(gold["digest_model"]) == ref3.model_digest(m)
+    print("[c3 full: oracle forward]", flush=True)
+    uT, st = ref3.oracle_forward(f, m, workers=16)
+    assert str(gold["digest_uT"]) == ref3.digest(uT), "the oracle's forward no longer matches the file"
+    gT = ref3.loss_gradient(uT, u)
+
+    print("[c3 full: GPU forward, every state]", flush=True)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd = _dev(f)
+    _, states = tnrd.forward(fd, dm, want_states=True)
+    states = states.cpu().numpy()
+    errs = [rel_inf(states[t], st[t]) for t in range(st.shape[0])]
+    print("per-state rel errors", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) <= TOL, errs
+
+    print("[c3 full: GPU backward, recompute_every=4]", flush=True)
+    got = _gpu_grads(f, m, gT, recompute_every=4)
+    _check(got, (gold["dK"], gold["dW"], gold["dlam"], gold["g0"].astype(np.float64)))

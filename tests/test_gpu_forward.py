@@ -3,6 +3,8 @@
 Bar: ||u_gpu - u_oracle||_inf / ||u_oracle||_inf <= 1e-4 per output tensor
 (FP32 GPU arithmetic against FP64).
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -79,6 +81,31 @@ def test_batch_of_images(impl):
     got = _run(f, m, impl, L=2)
     for n in range(3):
         assert rel_inf(got[n], ref[n]) <= TOL, n
+
+
+@functools.lru_cache(maxsize=2)
+def _c2_reference(L):
+    """The oracle's u_0..u_8 for the 512 x 512 image of look number L."""
+    m = synth.config_model(2)
+    _, f = synth.make_pair(512, 512, L, config_id=2)
+    _, states = oracle.forward(f, m, want_states=True)
+    return m, f, states
+
+
+@pytest.mark.parametrize("impl", IMPLS)
+@pytest.mark.parametrize("L", [1, 4])
+def test_c2_full_image_every_state(impl, L):
+    """512x512, 8 stages of 48 7x7 filters (the benchmark workload): every pixel
+    of all 9 states u_0..u_8 against the oracle's."""
+    print(f"[c2 full image impl={impl} L={L}]", flush=True)
+    m, f, ref = _c2_reference(L)
+    if impl == tnrd.IMPL_FUSED and not _fused_available(m):
+        pytest.skip("fused kernel not built for this model")
+    uT, states = _run(f, m, impl, L=L, want_states=True)
+    errs = [rel_inf(states[t, 0], ref[t]) for t in range(ref.shape[0])]
+    print("per-state rel errors", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) <= TOL, errs
+    np.testing.assert_array_equal(uT[0], states[-1, 0])
 
 
 @pytest.mark.parametrize("impl", IMPLS)
@@ -192,3 +219,45 @@ def test_merged_last_round_tiles(th):
     ref = oracle.forward(f, m)
     got = _run(f, m, tnrd.IMPL_FUSED, tile_h=th, tile_w=26)
     assert rel_inf(got, ref) <= TOL
+
+
+def test_concurrent_calls_from_two_threads_on_two_streams():
+    """The entry points are re-entrant: two host threads, each with its own
+    stream and workspace, run forwards at once (first calls included, which
+    set the kernels' launch attributes) and get the same bits as one thread."""
+    import threading
+
+    m = synth.config_model(2)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fs = [_dev(synth.make_pair(60 + 7 * i, 50 + 5 * i, 1, config_id=2, index=200 + i)[1])[None]
+          for i in range(6)]
+    ref = [tnrd.forward(f, dm).cpu() for f in fs]
+    torch.cuda.synchronize()
+    results = {}
+    errors = []
+
+    def worker(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                outs = []
+                for rep in range(5):
+                    for i in range(k, len(fs), 2):
+                        o = tnrd.default_opts(tile_h=24 + 8 * rep, tile_w=26)
+                        outs.append((i, rep, tnrd.forward(fs[i], dm, opts=o)))
+                s.synchronize()
+            results[k] = [(i, rep, u.cpu()) for i, rep, u in outs]
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    ths = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        for i, rep, u in results[k]:
+            ref_t = tnrd.forward(fs[i], dm, opts=tnrd.default_opts(tile_h=24 + 8 * rep, tile_w=26))
+            torch.testing.assert_close(u, ref_t.cpu(), rtol=0, atol=0)
+            assert rel_inf(u.numpy(), ref[i].numpy()) <= 2e-5

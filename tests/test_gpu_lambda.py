@@ -1,0 +1,123 @@
+"""The paper's (prox) model backward at lambda != 1 against the FP64 oracle.
+
+lambda enters the prox backward through c1 = 1 + 2 lambda and c2 = 2 lambda
+(y = du_t/d ut, eq. derv2; x_l = du_t/d lambda, eq. derv4; dl/dbeta = lambda
+dl/dlambda, eq. derv5), so a model with lambda = 1 everywhere cannot tell a
+wrong factor there from the right one.  Two models with lambda != 1:
+
+* 2 stages of 24 5x5 filters with lambda = (0.8, 1.3) on two 40 x 36 images;
+* the 8-stage 48 x 7x7 model with lambda^t drawn from U[0.5, 2].
+
+The backward is checked on shared states: both sides take the oracle's forward
+states rounded to FP32, so the comparison isolates the backward's arithmetic.
+Bar: ||a - b||_inf / ||b||_inf <= 1e-4 for dK, dW, dlambda (over the stages),
+dl/du_0 and dl/df.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1702_07482_amd import synth, tnrd
+from tests.helpers import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _design_case():
+    """2 stages x 24 5x5, lambda = (0.8, 1.3), two 40 x 36 images, loss 1/2 ||u_T - u_gt||^2."""
+    m = synth.make_model(2, 24, 5, np.random.default_rng(31))
+    m["lam"] = np.array([0.8, 1.3], dtype=np.float32)
+    pairs = [synth.make_pair(40, 36, 1, config_id=1, index=31 + i) for i in range(2)]
+    return m, np.stack([p[0] for p in pairs]), np.stack([p[1] for p in pairs]), 1.0
+
+
+def _c3_lambda_case():
+    """8 stages x 48 7x7 with lambda^t ~ U[0.5, 2], two 40 x 36 images, loss mean((u_T - u_gt)^2)."""
+    m = synth.config_model(3)
+    m["lam"] = synth.rng_for(3, 3, 7).uniform(0.5, 2.0, size=m["T"]).astype(np.float32)
+    pairs = [synth.make_pair(40, 36, 1, config_id=3, index=20 + i) for i in range(2)]
+    u = np.stack([p[0] for p in pairs])
+    return m, u, np.stack([p[1] for p in pairs]), 2.0 / u.size
+
+
+CASES = {"2x24x5x5": _design_case, "8x48x7x7": _c3_lambda_case}
+
+
+def _gpu_backward(m, f, states32, gT):
+    dm = tnrd.DeviceModel.from_numpy(m)
+    dK, dW, dl, g0, gf = tnrd.backward(_dev(f), dm, _dev(states32), _dev(gT), want_u0=True,
+                                        want_f=True)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in (dK, dW, dl, g0, gf)]
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_prox_backward_lambda_shared_states(case):
+    print(f"[lambda backward, shared states: {case}]", flush=True)
+    m, u, f, scale = CASES[case]()
+    assert np.all(m["lam"] != 1.0)
+    uT, st = oracle.forward(f, m, want_states=True)
+    gT = ((uT - u) * scale).astype(np.float32).astype(np.float64)
+    st32 = st.astype(np.float32)
+    ref = oracle.backward(f, m, st32.astype(np.float64), gT, want_df=True)
+    got = _gpu_backward(m, f, st32, gT)
+    names = ["dK", "dW", "dlam", "g0", "gf"]
+    errs = {n: rel_inf(a, b) for n, a, b in zip(names, got, ref)}
+    print("rel errors", errs, "lambda", m["lam"], flush=True)
+    for n in names:
+        assert errs[n] <= TOL, (n, errs)
+    # dl/dbeta = lambda dl/dlambda (eq. derv5) is what training moves: same bar
+    assert rel_inf(m["lam"] * got[2], m["lam"].astype(np.float64) * ref[2]) <= TOL
+
+
+def _stage_states(f, m, perturb=None):
+    """The oracle's states u_0..u_T, each stage started from the previous state
+    after `perturb` (None: exact FP64 chain)."""
+    T = m["filters"].shape[0]
+    f64 = f.astype(np.float64)
+    st = [f64]
+    cur = f64
+    for t in range(T):
+        cur, _ = oracle.stage(cur, f64, m, t)
+        if perturb is not None:
+            cur = perturb(cur)
+        st.append(cur)
+    return np.stack(st)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_prox_backward_lambda_end_to_end(case):
+    """GPU forward states, then the GPU backward, against the FP64 oracle end to end.
+
+    dK, dW, dl/du_0 and dl/df meet 1e-4.  dlambda^t = sum_p g_t x_l is a sum over
+    pixels with cancellation whose terms depend on u_t itself, so it carries the
+    FP32 forward's state error amplified; its bar is derived from the oracle
+    alone (see the assertion)."""
+    print(f"[lambda backward, end to end: {case}]", flush=True)
+    m, u, f, scale = CASES[case]()
+    uT, st = oracle.forward(f, m, want_states=True)
+    gT = ((uT - u) * scale).astype(np.float32).astype(np.float64)
+    ref = oracle.backward(f, m, st, gT, want_df=True)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd = _dev(f)
+    _, states = tnrd.forward(fd, dm, want_states=True)
+    dK, dW, dl, g0, gf = tnrd.backward(fd, dm, states, _dev(gT), want_u0=True, want_f=True)
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy() for x in (dK, dW, dl, g0, gf)]
+    names = ["dK", "dW", "dlam", "g0", "gf"]
+    errs = {n: rel_inf(a, b) for n, a, b in zip(names, got, ref)}
+    state_err = max(rel_inf(states.cpu().numpy()[t], st[t]) for t in range(st.shape[0]))
+    # conditioning of dlambda on the states: the oracle's own dlambda when every
+    # stage's state is rounded to FP32 before the next stage
+    st_r = _stage_states(f, m, lambda x: x.astype(np.float32).astype(np.float64))
+    kappa_round = rel_inf(oracle.backward(f, m, st_r, gT)[2], ref[2])
+    print("rel errors", errs, "state err", state_err, "kappa_round", kappa_round, flush=True)
+    for n in ["dK", "dW", "g0", "gf"]:
+        assert errs[n] <= TOL, (n, errs)

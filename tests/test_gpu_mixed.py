@@ -69,7 +69,9 @@ def test_mixed_full_size_sampled(prec):
     for n, pts in [(0, [(0, 0), (1024, 2047)]), (7, [(2047, 5), (700, 1300)])]:
         ref = oracle_uT_at(f[n], m, pts, radius)
         g = np.array([got[n][p] for p in pts])
-        assert np.abs(g - ref).max() <= BOUND[prec] * np.abs(f[n]).max(), (n, g, ref)
+        # normalised by the oracle's sampled u_T values (not by max|f|, which for
+        # L = 1 speckle is many times max|u_T|)
+        assert np.abs(g - ref).max() <= BOUND[prec] * np.abs(ref).max(), (n, g, ref)
 
 
 @pytest.mark.parametrize("prec", PRECS)
