@@ -50,7 +50,9 @@ typedef enum tnrd_status {
     TNRD_ERR_DOMAIN = -2,      /* validate: f <= 0 or not finite (the prox needs f > 0) */
     TNRD_ERR_WORKSPACE = -3,   /* ws_bytes smaller than tnrd_workspace_bytes() */
     TNRD_ERR_HIP = -4,         /* a HIP runtime call or launch failed */
-    TNRD_ERR_UNSUPPORTED = -5  /* valid but not built: ksize not in {3,5,7}, precision, ... */
+    TNRD_ERR_UNSUPPORTED = -5, /* valid but not built: ksize not in {3,5,7}, precision, ... */
+    TNRD_ERR_CAPACITY = -6     /* tnrd_forward_noalloc: the call needs more scratch than its
+                                  fixed TNRD_NOALLOC_SCRATCH_BYTES */
 } tnrd_status;
 
 /* Operand precision of the two filter-bank contractions (K and K^T, forward
@@ -212,6 +214,27 @@ size_t tnrd_batched_workspace_bytes(int B, const tnrd_image *imgs, int n_models,
                                     const tnrd_model *models, const tnrd_opts *o);
 int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models, const tnrd_model *models,
                          const tnrd_opts *o, void *ws, size_t ws_bytes, void *stream);
+
+/* Allocation-free forward, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, checks, kernels and results (bit for bit) as
+ * tnrd_forward without `ws`/`ws_bytes`: the scratch tnrd_forward takes from
+ * the caller's workspace comes from one fixed device array of
+ * TNRD_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, which each GPU the library runs
+ * on holds until the process ends.  The call allocates nothing, host or
+ * device (its first call on a device looks the array's address up once).
+ * The caller still passes f, u_out and states.  A call whose tnrd_workspace_bytes
+ * (which = 0) exceeds the array returns TNRD_ERR_CAPACITY before anything is
+ * enqueued: with the fused FP32 kernel and 48 filters of 7x7 over 8 stages
+ * that is N*H*W above about 8.2 million pixels.  All calls on one GPU share
+ * its array: calls that overlap in time on one GPU (two streams, or two host
+ * threads) race and must be serialised by the caller; calls on different GPUs
+ * are independent.  Nothing in the array needs to start at zero (the call
+ * clears its own domain flag).  Errors as tnrd_forward, plus TNRD_ERR_CAPACITY,
+ * and TNRD_ERR_HIP if the array's address cannot be obtained. */
+#define TNRD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int tnrd_forward_noalloc(const float *f, int N, int H, int W, int L, const tnrd_model *m,
+                         float *u_out, float *states, const tnrd_opts *o, void *stream);
 
 /* Static description of a status code. */
 const char *tnrd_status_str(int status);

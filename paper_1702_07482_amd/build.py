@@ -20,7 +20,8 @@ ARCH = "gfx950"
 
 SOURCES = ["tnrd_fused_fwd.hip", "tnrd_fused_mixed.hip", "tnrd_fused_bwd.hip",
            "tnrd_fused_batched.hip", "tnrd_backward.hip", "tnrd_fused.hip", "tnrd_api.cpp",
-           "tnrd_split.hip", "tnrd_batched.hip", "tnrd_peaks.hip", "tnrd_prep.hip"]
+           "tnrd_split.hip", "tnrd_batched.hip", "tnrd_peaks.hip", "tnrd_prep.hip",
+           "tnrd_noalloc.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-x", "hip",

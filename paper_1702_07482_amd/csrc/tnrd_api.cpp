@@ -364,6 +364,8 @@ const char *tnrd_status_str(int status)
     case TNRD_ERR_WORKSPACE: return "workspace missing or too small";
     case TNRD_ERR_HIP: return "HIP runtime error";
     case TNRD_ERR_UNSUPPORTED: return "unsupported configuration";
+    case TNRD_ERR_CAPACITY:
+        return "problem larger than the fixed scratch of tnrd_forward_noalloc (TNRD_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
     }
 }

@@ -27,6 +27,8 @@ TNRD_ERR_DOMAIN = -2
 TNRD_ERR_WORKSPACE = -3
 TNRD_ERR_HIP = -4
 TNRD_ERR_UNSUPPORTED = -5
+TNRD_ERR_CAPACITY = -6
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 REACT_PROX, REACT_PROJECTED, REACT_L2 = 0, 1, 2
@@ -85,6 +87,8 @@ SIGNATURES = [
                                            ctypes.POINTER(TnrdModel), ctypes.POINTER(TnrdOpts)]),
     ("tnrd_forward_batched", _I, [_I, ctypes.POINTER(TnrdImage), _I, ctypes.POINTER(TnrdModel),
                                   ctypes.POINTER(TnrdOpts), _P, _SZ, _P]),
+    ("tnrd_forward_noalloc", _I, [_P, _I, _I, _I, _I, ctypes.POINTER(TnrdModel), _P, _P,
+                                  ctypes.POINTER(TnrdOpts), _P]),
     ("tnrd_status_str", ctypes.c_char_p, [_I]),
     ("tnrd_peaks_sink_floats", _SZ, []),
     ("tnrd_measure_peaks", _I, [_P, _P, _SZ, _P, ctypes.POINTER(TnrdPeaks), _P]),
@@ -151,6 +155,12 @@ def tnrd_forward(f, N, H, W, L, model: TnrdModel, u_out, states, opts: TnrdOpts,
     return int(load().tnrd_forward(_ptr(f), N, H, W, L, ctypes.byref(model), _ptr(u_out),
                                    _ptr(states), ctypes.byref(opts), _ptr(ws), ws_bytes,
                                    _stream(stream)))
+
+
+def tnrd_forward_noalloc(f, N, H, W, L, model: TnrdModel, u_out, states, opts: TnrdOpts,
+                         stream=None) -> int:
+    return int(load().tnrd_forward_noalloc(_ptr(f), N, H, W, L, ctypes.byref(model), _ptr(u_out),
+                                           _ptr(states), ctypes.byref(opts), _stream(stream)))
 
 
 def tnrd_backward(f, N, H, W, L, model: TnrdModel, states, grad_uT, grad_filters, grad_rbf_w,

@@ -130,6 +130,24 @@ def test_num_checkpoints():
 
 
 def test_status_strings():
-    for st in [0, -1, -2, -3, -4, -5]:
+    for st in [0, -1, -2, -3, -4, -5, -6]:
         assert tnrd.status_str(st) and tnrd.status_str(st) != "unknown status"
     assert tnrd.status_str(12) == "unknown status"
+
+
+def test_noalloc_forward_rejects_oversized_calls_before_any_launch():
+    """The allocation-free forward checks its fixed scratch on the host: a call
+    needing more than TNRD_NOALLOC_SCRATCH_BYTES returns TNRD_ERR_CAPACITY and
+    enqueues nothing (the pointers here are never dereferenced)."""
+    m = _model(T=8, Nk=48, ks=7)
+    o = tnrd.default_opts()
+    lib = tnrd.load()
+    big = (4, 2048, 2048)  # two ping-pong planes of 64 MiB each
+    assert tnrd.tnrd_workspace_bytes(*big, m, o, 0) > tnrd.NOALLOC_SCRATCH_BYTES
+    st = lib.tnrd_forward_noalloc(FAKE_F, *big, 1, ctypes.byref(m), FAKE_U, None, ctypes.byref(o), None)
+    assert st == tnrd.TNRD_ERR_CAPACITY
+    # argument errors come first, as in tnrd_forward; N = 0 is a no-op
+    assert lib.tnrd_forward_noalloc(FAKE_F, 1, 32, 32, 1, ctypes.byref(m), FAKE_F, None,
+                                    ctypes.byref(o), None) == tnrd.TNRD_ERR_ARG
+    assert lib.tnrd_forward_noalloc(FAKE_F, 0, 32, 32, 1, ctypes.byref(m), FAKE_U, None,
+                                    ctypes.byref(o), None) == tnrd.TNRD_OK
