@@ -17,13 +17,12 @@ from . import tnrd
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-# (tile_h, tile_w, waves): widths 16*nb - (k-1) use every pixel of an E row
-# block for 7x7 filters (26, 42, 58); 32 keeps power-of-two tiles.  Tall
-# narrow tiles (80, 96 x 26) have the smallest halo that still fits the local
-# memory with the polynomial table.
+# (tile_h, tile_w, waves): widths 16*nb use every pixel of a row's 16-pixel
+# blocks (32, 48, 64); tall narrow tiles (80, 96 x 32) write the least slab ring
+# per pixel that still fits the local memory with the polynomial table.
 CANDIDATES = ([(th, tw, nw) for nw in (8, 4) for th in (16, 24, 32, 48, 64)
-               for tw in (26, 32, 42, 58)]
-              + [(th, 26, nw) for nw in (8, 4) for th in (80, 96)])
+               for tw in (32, 48, 64)]
+              + [(th, 32, nw) for nw in (8, 4) for th in (80, 96)])
 
 
 def _load():

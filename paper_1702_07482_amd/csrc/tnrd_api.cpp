@@ -141,7 +141,15 @@ size_t prep_region_floats(const tnrd_model *m, const tnrd_opts &o, int impl, int
     return (size_t)stages * fused_prep_floats(m->ksize, m->Nk, m->Nrbf);
 }
 
-// Forward workspace: [flags 256 B][scratch][ping A][ping B][prepared stage blocks]
+size_t slab_region_floats(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int impl,
+                          int window)
+{
+    if (impl != TNRD_IMPL_FUSED) return 0;
+    const bool poly = o.rbf_window < 0 && poly_form_ok(make_grid(m, window), 1);
+    return fused_slab_floats(m->ksize, m->Nk, m->Nrbf, N, H, W, o.tile_h, o.tile_w, o.wg_waves, poly);
+}
+
+// Forward workspace: [flags 256 B][scratch][ping A][ping B][prepared stage blocks][slabs x 2]
 size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int impl)
 {
     size_t img = (size_t)N * H * W;
@@ -151,6 +159,7 @@ size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opt
     if (m->T > 1) bytes += 2 * align_up(img * sizeof(float));
     const int window = rbf_window_for(m, o.rbf_window);
     bytes += align_up(prep_region_floats(m, o, impl, window, m->T) * sizeof(float));
+    bytes += 2 * align_up(slab_region_floats(N, H, W, m, o, impl, window) * sizeof(float));
     return bytes;
 }
 
@@ -172,9 +181,14 @@ int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream)
 
 // Runs stages [t_begin, t_end) (0-based stage index t computes u_{t+1})
 // starting from u_start = u_{t_begin}; the output of stage t goes to dst(t).
+// The fused forward runs in exchange form: the launch of stage t applies
+// stage t-1's reaction in its prologue (writing u_t to its destination) and
+// leaves its own diffusion force in slabs[t mod 2]; a final launch applies
+// the last reaction.
 int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const tnrd_opts &o,
                int impl, int window, int t_begin, int t_end, const float *u_start,
-               float *const *dst, float *scratch, float *prep, hipStream_t stream)
+               float *const *dst, float *scratch, float *prep, float *const *slabs,
+               hipStream_t stream)
 {
     StageArgs s;
     s.u_cur = nullptr;
@@ -206,17 +220,44 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
                        t_end - t_begin, m->ksize, m->Nk, s.grid, 0, prep, stream) != hipSuccess)
             return TNRD_ERR_HIP;
     }
+    if (impl == TNRD_IMPL_SPLIT) {
+        for (int t = t_begin; t < t_end; ++t) {
+            s.u_prev = cur;
+            s.u_next = dst[t - t_begin];
+            s.filt = m->filters + (size_t)t * m->Nk * kk;
+            s.rbfw = m->rbf_w + (size_t)t * m->Nk * m->Nrbf;
+            s.lam = m->lambda + t;
+            if (split_stage(s, stream) != hipSuccess) return TNRD_ERR_HIP;
+            cur = s.u_next;
+        }
+        return TNRD_OK;
+    }
+    if (t_end <= t_begin) return TNRD_OK;
+    if (!slabs || !slabs[0] || !slabs[1]) return TNRD_ERR_WORKSPACE;
+    // plane holding u_{t_begin + i}
+    auto state = [&](int i) -> const float * { return i == 0 ? u_start : dst[i - 1]; };
     for (int t = t_begin; t < t_end; ++t) {
-        s.u_prev = cur;
-        s.u_next = dst[t - t_begin];
+        const int i = t - t_begin;
+        s.pend = i > 0;
+        s.u_prev = s.pend ? state(i - 1) : u_start;
+        s.u_keep = s.pend ? dst[i - 1] : nullptr;
+        s.x_prev = s.pend ? slabs[(i - 1) & 1] : nullptr;
+        s.lam_prev = s.pend ? m->lambda + t - 1 : nullptr;
+        s.x_out = slabs[i & 1];
+        s.u_next = nullptr;
         s.filt = m->filters + (size_t)t * m->Nk * kk;
         s.rbfw = m->rbf_w + (size_t)t * m->Nk * m->Nrbf;
         s.lam = m->lambda + t;
-        s.prep = use_prep ? prep + (size_t)(t - t_begin) * prep_sf : nullptr;
-        hipError_t e = impl == TNRD_IMPL_SPLIT ? split_stage(s, stream) : fused_stage(s, stream);
-        if (e != hipSuccess) return TNRD_ERR_HIP;
-        cur = s.u_next;
+        s.prep = use_prep ? prep + (size_t)i * prep_sf : nullptr;
+        if (fused_stage(s, stream) != hipSuccess) return TNRD_ERR_HIP;
     }
+    const int n = t_end - t_begin;
+    s.pend = 1;
+    s.u_prev = state(n - 1);
+    s.x_prev = slabs[(n - 1) & 1];
+    s.lam_prev = m->lambda + t_end - 1;
+    s.u_next = dst[n - 1];
+    if (fused_finish(s, stream) != hipSuccess) return TNRD_ERR_HIP;
     return TNRD_OK;
 }
 
@@ -257,7 +298,15 @@ int run_forward(const float *f, int N, int H, int W, const tnrd_model *m, float 
         ping[1] = (float *)((char *)ping[0] + align_up(img * sizeof(float)));
         after += 2 * align_up(img * sizeof(float));
     }
-    float *prep = prep_region_floats(m, oo, impl, window, m->T) ? (float *)after : nullptr;
+    const size_t prep_floats = prep_region_floats(m, oo, impl, window, m->T);
+    float *prep = prep_floats ? (float *)after : nullptr;
+    after += align_up(prep_floats * sizeof(float));
+    const size_t slab_floats = slab_region_floats(N, H, W, m, oo, impl, window);
+    float *slabs[2] = {nullptr, nullptr};
+    if (slab_floats) {
+        slabs[0] = (float *)after;
+        slabs[1] = (float *)(after + align_up(slab_floats * sizeof(float)));
+    }
 
     if (oo.validate) {
         int st = run_domain_check(f, img, dflag, stream);
@@ -290,7 +339,8 @@ int run_forward(const float *f, int N, int H, int W, const tnrd_model *m, float 
             dsts[t - t0] = d;
             cur = d;
         }
-        int st = run_stages(f, N, H, W, m, oo, impl, window, t0, t1, start, dsts, scratch, prep, stream);
+        int st = run_stages(f, N, H, W, m, oo, impl, window, t0, t1, start, dsts, scratch, prep, slabs,
+                            stream);
         if (st != TNRD_OK) return st;
     }
     if (states) {

@@ -21,9 +21,14 @@ size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opt
 int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream);
 // Runs stages [t_begin, t_end) of m.  prep: room for the prepared blocks of
 // t_end - t_begin stages (prep_region_floats), used by the fused FP32 form.
+// slabs: two regions of slab_region_floats each (the fused forward's exchange buffers).
 int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const tnrd_opts &o,
                int impl, int window, int t_begin, int t_end, const float *u_start,
-               float *const *dst, float *scratch, float *prep, hipStream_t stream);
+               float *const *dst, float *scratch, float *prep, float *const *slabs,
+               hipStream_t stream);
+// Floats of one set of slabs of the fused forward (0 for the split path).
+size_t slab_region_floats(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int impl,
+                          int window);
 // Floats of the prepared blocks of `stages` stages of m (0 where the fused
 // kernel builds its constants itself).
 size_t prep_region_floats(const tnrd_model *m, const tnrd_opts &o, int impl, int window,

@@ -717,11 +717,14 @@ struct BwdWs {
     float *g[2], *za, *dk_part, *dl_part, *dw_part, *seg;
     float *prep_b;  // prepared blocks of the input-gradient stages (d phi / ds tables)
     float *prep_f;  // prepared blocks of the recomputed forward stages (phi tables)
+    float *slab[2]; // exchange buffers of the recomputed forward stages
     size_t bytes;
 };
 
-// prep: floats of T stages' prepared blocks (0: the kernels build them)
-BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s, size_t prep)
+// prep: floats of T stages' prepared blocks (0: the kernels build them);
+// slab: floats of one set of the forward's slabs
+BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s, size_t prep,
+                    size_t slab)
 {
     BwdGeom gm = bwd_geom(N, H, W, BP_TH_MIN);  // the most tiles any launch uses
     const size_t kk = (size_t)m->ksize * m->ksize;
@@ -741,6 +744,8 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s,
     w.seg = s > 1 ? take(gm.img * (size_t)(s + 1)) : nullptr;
     w.prep_b = prep ? take(prep) : nullptr;
     w.prep_f = prep && s > 1 ? take(prep) : nullptr;
+    w.slab[0] = s > 1 ? take(slab) : nullptr;
+    w.slab[1] = s > 1 ? take(slab) : nullptr;
     w.bytes = off;
     return w;
 }
@@ -860,7 +865,8 @@ size_t backward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_op
     if (!fused_supported(m->ksize, m->Nk, m->Nrbf, window, o.prec) || !bwd_lds_ok(m)) return 0;
     const int s = o.recompute_every < 1 ? 1 : o.recompute_every;
     return bwd_ws_layout(nullptr, N, H, W, m, s,
-                         prep_region_floats(m, o, TNRD_IMPL_FUSED, window, m->T)).bytes;
+                         prep_region_floats(m, o, TNRD_IMPL_FUSED, window, m->T),
+                         slab_region_floats(N, H, W, m, o, TNRD_IMPL_FUSED, window)).bytes;
 }
 
 }  // namespace tnrd
@@ -889,7 +895,8 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     const int T = m->T;
     const int s = oo.recompute_every < 1 ? 1 : oo.recompute_every;
     const size_t prep = prep_region_floats(m, oo, TNRD_IMPL_FUSED, window, T);
-    const size_t need = bwd_ws_layout(nullptr, N, H, W, m, s, prep).bytes;
+    const size_t slab = slab_region_floats(N, H, W, m, oo, TNRD_IMPL_FUSED, window);
+    const size_t need = bwd_ws_layout(nullptr, N, H, W, m, s, prep, slab).bytes;
     if (N > 0 && (!ws || ws_bytes < need)) return TNRD_ERR_WORKSPACE;
     hipStream_t stream = (hipStream_t)stream_;
     const size_t kk = (size_t)m->ksize * m->ksize;
@@ -901,7 +908,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             return TNRD_ERR_HIP;
         return TNRD_OK;
     }
-    BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep);
+    BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep, slab);
     // the two variants of k_bwd_params hold different numbers of workgroups per
     // compute unit, so each gets its own tile height (gm: loading z and a)
     BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, true));
@@ -955,7 +962,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
                 ut[t] = dst[t - seg_lo - 1];
             }
             st = run_stages(f, N, H, W, m, oo, TNRD_IMPL_FUSED, window, seg_lo, seg_hi - 1,
-                            ut[seg_lo], dst.data(), nullptr, w.prep_f, stream);
+                            ut[seg_lo], dst.data(), nullptr, w.prep_f, w.slab, stream);
             if (st != TNRD_OK) return st;
         }
         for (int t = seg_hi; t > seg_lo; --t) {

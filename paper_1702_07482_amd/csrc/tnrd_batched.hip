@@ -29,6 +29,8 @@ struct BatchPlan {
     size_t prep_stage;           // floats per prepared stage block (0: none)
     size_t off_imgs, off_models, off_items, off_tmp, off_prep, desc_bytes, total;
     std::vector<size_t> tmp_off; // per image, from the workspace base
+    std::vector<size_t> xs_off;  // per image: its two slab regions, from the workspace base
+    std::vector<size_t> xs_len;  // per image: floats of one slab region
 };
 
 int resolve_model(const tnrd_image &im, int n_models, const tnrd_model *models)
@@ -87,10 +89,19 @@ int check_batch(int B, const tnrd_image *imgs, int n_models, const tnrd_model *m
     off += al((size_t)plan.ntiles * sizeof(BatchItem));
     plan.desc_bytes = off - plan.off_imgs;
     plan.off_tmp = off;
+    const int R = m.ksize / 2;
+    plan.xs_off.assign(B, 0);
+    plan.xs_len.assign(B, 0);
     for (int b = 0; b < B; ++b) {
         plan.tmp_off[b] = off;
         off += al((size_t)imgs[b].H * imgs[b].W * sizeof(float));
         tmp_total += (size_t)imgs[b].H * imgs[b].W;
+        // the image's slabs: one per tile of (Th + 2R) x (Tw + 2R) floats, two sets
+        const size_t tiles = (size_t)((imgs[b].W + plan.tw - 1) / plan.tw) *
+                             ((imgs[b].H + plan.th - 1) / plan.th);
+        plan.xs_len[b] = tiles * (size_t)(plan.th + 2 * R) * (plan.tw + 2 * R);
+        plan.xs_off[b] = off;
+        off += 2 * al(plan.xs_len[b] * sizeof(float));
     }
     (void)tmp_total;
     // prepared stage blocks of the polynomial form, [model][T][prep_stage]
@@ -121,6 +132,8 @@ void build_descriptors(int B, const tnrd_image *imgs, int n_models, const tnrd_m
         di[b].f = im.f;
         di[b].u_out = im.u_out;
         di[b].u_tmp = (float *)(ws + plan.tmp_off[b]);
+        di[b].xs[0] = (float *)(ws + plan.xs_off[b]);
+        di[b].xs[1] = (float *)(ws + plan.xs_off[b] + al(plan.xs_len[b] * sizeof(float)));
         di[b].H = im.H;
         di[b].W = im.W;
         di[b].tiles_x = tx;

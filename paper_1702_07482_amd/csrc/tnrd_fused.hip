@@ -142,16 +142,22 @@ struct TilePlan {
 // is taken as given (clamped to the image).  Otherwise the tile minimises the
 // modelled time: the kernel holds one workgroup per compute unit (its LDS
 // footprint), so a launch of n tiles runs in ceil(n / CUs) rounds, each as
-// long as one tile.  A tile's (Th + 2R) E rows go to its waves in rounds, so a
-// wave runs ceil((Th + 2R) / waves) rows of nb 16-pixel blocks, plus a fixed
-// cost (prologue, output passes) worth about 2 such blocks.  Among tiles of
-// equal modelled time the one with the fewest E rows wins (its output passes
-// and prologue are the shortest), then the one with fewer tiles.  Tile widths
-// are those whose E rows fill their blocks exactly (16 nb - 2R).
+// long as one tile.  A tile's source rows (forward: its own Th rows;
+// input-gradient mode: Th + 2R E rows) go to its waves in rounds, so a wave
+// runs ceil(rows / waves) rows of nb 16-pixel blocks, plus a fixed cost
+// (prologue, output passes) worth about 2 such blocks.  Among tiles of equal
+// modelled time the one with the fewest rows wins (its output passes and
+// prologue are the shortest), then the one with fewer tiles.  Tile widths are
+// those whose source rows fill their blocks exactly (forward 16 nb,
+// input-gradient mode 16 nb - 2R).  The forward's tiles are at least 2R on
+// each side, so a padded position lies in the rings of at most two tiles per axis.
 static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req_h, int req_w,
                           int waves, int mode, bool poly)
 {
     const int R = ks / 2;
+    const bool xf = mode == MODE_FWD;
+    const int ring = xf ? 0 : 2 * R;   // source columns beyond the tile
+    const int tmin = xf ? 2 * R : R;   // smallest tile side
     TilePlan p;
     p.nw = waves == 4 ? 4 : 8;
     p.ok = false;
@@ -166,29 +172,29 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
         p.th = req_h > 0 ? req_h : 32;
         if (p.tw > W) p.tw = W;
         if (p.th > H) p.th = H;
-        p.nb = (p.tw + 2 * R + 15) / 16;
+        p.nb = (p.tw + ring + 15) / 16;
         if (p.nb < 2) p.nb = 2;
         p.rbfm = p.nb <= 4 ? form(p.th, p.tw, p.nb) : -1;
-        p.ok = p.nb <= 4 && p.th >= R && p.tw >= R && p.rbfm >= 0;
+        p.ok = p.nb <= 4 && p.th >= tmin && p.tw >= tmin && p.rbfm >= 0;
         return p;
     }
     const long cus = device_cus();
     double best = 0.0;
     for (int nb = 2; nb <= 4; ++nb) {
-        int tw = 16 * nb - 2 * R;
+        int tw = 16 * nb - ring;
         if (tw > W) tw = W;
-        for (int th = 8; th <= 96; ++th) {
+        for (int th = tmin; th <= 160; ++th) {
             const int t = th > H ? H : th;
             const int rbfm = form(t, tw, nb);
             if (rbfm < 0) continue;
             const long tiles = (long)N * ((H + t - 1) / t) * ((W + tw - 1) / tw);
             const long rounds = (tiles + cus - 1) / cus;
-            // per wave: ceil(E rows / waves) rows of nb blocks (the rows go to the
+            // per wave: ceil(rows / waves) rows of nb blocks (the rows go to the
             // waves in rounds); a block of the Gaussian form costs about 1.3 blocks
             // of the polynomial form
-            const int erows = (t < H ? t : H) + 2 * R;
-            const double blk = (rbfm == RBF_HORNER ? 1.3 : 1.0) * ((erows + p.nw - 1) / p.nw) * nb;
-            const double cost = (double)rounds * (blk + 2) + 1e-4 * erows * nb + 1e-9 * (double)tiles;
+            const int rows = (t < H ? t : H) + ring;
+            const double blk = (rbfm == RBF_HORNER ? 1.3 : 1.0) * ((rows + p.nw - 1) / p.nw) * nb;
+            const double cost = (double)rounds * (blk + 2) + 1e-4 * rows * nb + 1e-9 * (double)tiles;
             if (!p.ok || cost < best) {
                 best = cost;
                 p.th = t;
@@ -271,21 +277,42 @@ hipError_t fused_stage(const StageArgs &s, hipStream_t stream)
     return fused_dispatch<MODE_FWD>(s, stream);
 }
 
+hipError_t fused_finish(const StageArgs &s, hipStream_t stream)
+{
+    const bool poly = s.poly && poly_form_ok(s.grid, 1);
+    const TilePlan p = plan_tile_cached(s.ks, s.Nk, s.grid.nrbf, s.N, s.H, s.W, s.tile_h, s.tile_w,
+                                        s.waves, MODE_FWD, poly);
+    if (!p.ok) return hipErrorInvalidValue;
+    return fused_launch_final(s, p.th, p.tw, stream);
+}
+
+size_t fused_slab_floats(int ks, int nk, int nrbf, int N, int H, int W, int tile_h, int tile_w,
+                         int waves, bool poly)
+{
+    const TilePlan p = plan_tile_cached(ks, nk, nrbf, N, H, W, tile_h, tile_w, waves, MODE_FWD, poly);
+    if (!p.ok) return 0;
+    const int R = ks / 2;
+    const size_t tiles = (size_t)N * ((H + p.th - 1) / p.th) * ((W + p.tw - 1) / p.tw);
+    return tiles * (size_t)(p.th + 2 * R) * (p.tw + 2 * R);
+}
+
 hipError_t fused_stage_input_grad(const StageArgs &s, hipStream_t stream)
 {
     return fused_dispatch<MODE_BWD_INPUT>(s, stream);
 }
+// Blocks per row of a batched (forward, exchange form) tile of width tw.
+static int batched_blocks(int tw) { return tw <= 32 ? 2 : (tw + 15) / 16; }
+
 bool batched_config_ok(int ks, int nk, int nrbf, int th, int tw, int nw)
 {
     const int R = ks / 2;
-    const int nb = (tw + 2 * R + 15) / 16;
-    if (nb < 2 || nb > 4 || th < 2 * R || tw < 2 * R) return false;  // the halo must fit in one tile
+    const int nb = batched_blocks(tw);
+    if (nb > 4 || th < 2 * R || tw < 2 * R) return false;  // a ring reaches one tile at most
     return lds_fits(ks, nk, nrbf, th, tw, nb, nw == 4 ? 4 : 8, MODE_FWD, RBF_HORNER);
 }
 hipError_t batched_launch(const BatchArgs &a, int ks, int nw, hipStream_t stream)
 {
-    const int R = ks / 2;
-    const int nb = (a.Tw + 2 * R + 15) / 16;
+    const int nb = batched_blocks(a.Tw);
     const int rbfm = a.poly && lds_fits(ks, a.Nk, a.Nrbf, a.Th, a.Tw, nb, nw, MODE_FWD, RBF_POLY)
                          ? RBF_POLY
                          : RBF_HORNER;

@@ -113,11 +113,90 @@ struct FusedRbf {
     float pmd[POLY_NC][POLY_MW + 1];  // the same for d phi / ds (input-gradient mode)
 };
 
+// Forward stage in exchange form.  A tile computes z, phi and K^T v from its
+// own pixels only; K^T spreads them over the tile plus an R ring, so each tile
+// writes the diffusion force it contributes to those padded positions into a
+// slab of its own:
+//   slab_tau[dy][dx] = sum over own sources p of sum_i sum_(a,b) with
+//                      p - (a - R, b - R) = (ty0 - R + dy, tx0 - R + dx)
+//                      of k_i[a][b] v_i[p],
+// dy < Th + 2R, dx < Tw + 2R (row pitch sw = Tw + 2R, sl = (Th + 2R) sw
+// floats per slab, slabs tile-major).  The force at padded position q is the
+// sum of the slabs of the tiles whose ring covers q, and the force at pixel p
+// the sum over the padded positions that reflect onto p (the exact adjoint's
+// fold).  The reaction of stage t is applied where u_t is next needed: in the
+// prologue of stage t + 1 (over its u tile, own pixels written back) or by
+// the final reaction kernel after the last stage.  Every tile then works on
+// its own pixels only, with no recomputed halo of z and phi.
+struct XTiles {
+    int H, W;      // image
+    int Th, Tw;    // tile (>= 2R each, so a padded position lies in the rings of at most 2 x 2 tiles)
+    int nx, ny;    // tiles per row and per column
+    int sw, sl;    // slab row pitch and floats per slab
+};
+
+__host__ __device__ inline XTiles make_xtiles(int H, int W, int th, int tw, int R)
+{
+    XTiles x;
+    x.H = H;
+    x.W = W;
+    x.Th = th;
+    x.Tw = tw;
+    x.nx = (W + tw - 1) / tw;
+    x.ny = (H + th - 1) / th;
+    x.sw = tw + 2 * R;
+    x.sl = (th + 2 * R) * x.sw;
+    return x;
+}
+
+// Force at padded position (qy, qx), -R <= qy < H + R, -R <= qx < W + R: the
+// covering tiles' slab entries added in a fixed order (tile rows, then tile
+// columns, ascending), so every caller forms the same bits.
+template <int R>
+__device__ __forceinline__ float xpad_force(const float *__restrict__ xs, const XTiles &g, int qy, int qx)
+{
+    const int tyc = min(max(qy, 0) / g.Th, g.ny - 1);
+    const int txc = min(max(qx, 0) / g.Tw, g.nx - 1);
+    const bool ylo = tyc > 0 && qy < tyc * g.Th + R;                  // tile row tyc - 1 covers qy
+    const bool yhi = tyc + 1 < g.ny && qy >= (tyc + 1) * g.Th - R;   // tile row tyc + 1 covers qy
+    const bool xlo = txc > 0 && qx < txc * g.Tw + R;
+    const bool xhi = txc + 1 < g.nx && qx >= (txc + 1) * g.Tw - R;
+    const int ty0 = ylo ? tyc - 1 : tyc, ty1 = yhi ? tyc + 1 : tyc;
+    const int tx0 = xlo ? txc - 1 : txc, tx1 = xhi ? txc + 1 : txc;
+    auto at = [&](int ty, int tx) {
+        return xs[(size_t)(ty * g.nx + tx) * g.sl + (qy - ty * g.Th + R) * g.sw + (qx - tx * g.Tw + R)];
+    };
+    // four loads, whether or not the tiles differ (the duplicates are masked)
+    const float v00 = at(ty0, tx0), v01 = at(ty0, tx1), v10 = at(ty1, tx0), v11 = at(ty1, tx1);
+    float s = v00;
+    s += tx1 != tx0 ? v01 : 0.f;
+    s += ty1 != ty0 ? v10 : 0.f;
+    s += (ty1 != ty0 && tx1 != tx0) ? v11 : 0.f;
+    return s;
+}
+
+// Diffusion force x[p] = sum_i K_i^T v_i at pixel (y, x): the padded force at
+// p plus, within R of the border, at its mirror positions.
+template <int R>
+__device__ __forceinline__ float pixel_force(const float *__restrict__ xs, const XTiles &g, int y, int x)
+{
+    const int my = y < R ? -y - 1 : (y >= g.H - R ? 2 * g.H - 1 - y : y);
+    const int mx = x < R ? -x - 1 : (x >= g.W - R ? 2 * g.W - 1 - x : x);
+    float s = xpad_force<R>(xs, g, y, x);
+    if (mx != x) s += xpad_force<R>(xs, g, y, mx);
+    if (my != y) {
+        s += xpad_force<R>(xs, g, my, x);
+        if (mx != x) s += xpad_force<R>(xs, g, my, mx);
+    }
+    return s;
+}
+
 // Kernel arguments of one stage (forward or input-gradient mode).
 struct FusedIO {
-    const float *u_prev;  // u_{t-1}
+    const float *u_prev;  // forward: the stage input u_{t-1}, or with `pend` the state
+                          // u_{t-2} its pending reaction starts from; input gradient: u_{t-1}
     const float *f;
-    float *out;           // forward: u_t;  input gradient: g_{t-1}
+    float *out;           // input gradient: g_{t-1}
     const float *u_cur;   // input gradient: u_t
     const float *g_cur;   // input gradient: g_t = dl/du_t
     float *za;            // input gradient, optional: z = K u and a = K e at the tile's own
@@ -126,6 +205,13 @@ struct FusedIO {
     float proj_c;         // projected reaction: threshold c
     const float *prep;    // polynomial form: the stage's prepared table (and FP32 operands),
                           // k_prep_stage layout
+    // forward (exchange form)
+    const float *x_prev;  // pend: the previous stage's slabs (this image's first)
+    float *x_out;         // this stage's slabs (this image's first)
+    float *u_keep;        // pend: the tile's own pixels of u_{t-1} after the pending reaction
+    const float *lam_prev;  // pend: lambda of the previous stage
+    int pend;             // the previous stage's reaction is still to be applied
+    XTiles xt;            // this image's tiling
 };
 
 // Export of z = K u and a = K e for the parameter-gradient kernels: per pixel

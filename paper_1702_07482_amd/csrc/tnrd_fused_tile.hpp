@@ -82,8 +82,11 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
 {
     const int R = ks / 2;
     FusedLds l;
-    const int luh = th + 4 * R;
-    l.ldw = tw + 4 * R + 1;
+    // u tile origin: R before the tile (forward: z on the tile's own pixels),
+    // 2R (input-gradient mode: z on the tile plus an R ring)
+    const int uo = mode == MODE_FWD ? R : 2 * R;
+    const int luh = th + 2 * uo;
+    l.ldw = tw + 2 * uo + 1;
     l.u_off = 0;
     l.u_size = (luh * l.ldw + 63) & ~63;  // whole 64-word chunks (the direct-to-LDS loads)
     l.e_off = l.u_off + l.u_size;
@@ -115,6 +118,7 @@ __device__ __forceinline__ void fused_tile(
     const FusedRbf &rb, const float *__restrict__ lam_t, float *lds)
 {
     constexpr bool BWD = MODE == MODE_BWD_INPUT;
+    constexpr bool XF = MODE == MODE_FWD;  // forward: exchange form (own pixels, slabs)
     constexpr bool POLY = RBFM == RBF_POLY;
     // Polynomial form: the coefficient table comes ready-made from io.prep
     // (k_prep_stage); with FP32 operands the per-lane filter operands too
@@ -134,6 +138,14 @@ __device__ __forceinline__ void fused_tile(
     // output values a thread produces per round, at most: NW + R + FUSED_MERGE rows (a
     // merged last round of a tile at the bottom border) of a tile at most 16 NB - 2R wide
     constexpr int PF = ((NW + R + FUSED_MERGE) * (16 * NB - 2 * R) + THREADS - 1) / THREADS;
+    // forward: slab values a thread exports per round, at most: NW + 2R + FUSED_MERGE ring
+    // rows (a merged last round) of at most 16 NB + 2R columns
+    constexpr int PX = ((NW + 2 * R + FUSED_MERGE) * (16 * NB + 2 * R) + THREADS - 1) / THREADS;
+    // Source region whose responses the tile computes: forward, its own pixels
+    // (origin offset 0); input-gradient mode, the tile plus an R ring (E region,
+    // origin offset -R).  The u tile starts UO = R before the source region.
+    constexpr int SO = XF ? 0 : -R;
+    constexpr int UO = R - SO;
 
     const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW, MODE, RBFM);
     float *su = lds + L.u_off;
@@ -145,8 +157,8 @@ __device__ __forceinline__ void fused_tile(
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
 
-    const int Eh = Th + 2 * R, Ew = Tw + 2 * R;
-    const int luh = Th + 4 * R, luw = Tw + 4 * R;
+    const int Eh = Th - 2 * SO, Ew = Tw - 2 * SO;  // source region
+    const int luh = Th + 2 * UO, luw = Tw + 2 * UO;
 
     // ---- prologue: every global load of a thread is issued before the first
     // use, so the workgroup pays one memory latency, not one per element.
@@ -229,18 +241,50 @@ __device__ __forceinline__ void fused_tile(
                 if (base + k * THREADS + tid < n) dst[base + k * THREADS + tid] = v[k];
         }
     }
-    // (2) the u tile (rows ty0-2R .. ty0+Th+2R-1, reflected at the border),
+    // (2) the u tile (rows ty0-UO .. ty0+Th+UO-1, reflected at the border),
     // loaded straight into LDS in 64-word chunks (lane l of a wave fills word
     // l of its chunk).  The loads stay in flight while the filter registers
     // and the coefficient table are set up; padding words get an in-image value.
-    {
+    // Forward with the previous stage's reaction pending: u_{t-1} =
+    // reaction(u_{t-2}, force gathered from the slabs, f) at every position of
+    // the tile (own pixels also written back to io.u_keep for later stages).
+    if (!(XF && io.pend)) {
         for (int c = wave; c * 64 < L.u_size; c += NW) {
             const int k = c * 64 + lane;
             const int ly = k / L.ldw, lx = k - ly * L.ldw;
             const bool in = ly < luh && lx < luw;
-            const int yy = reflect_clamp(ty0 - 2 * R + (in ? ly : 0), H);
-            const int xx = reflect_clamp(tx0 - 2 * R + (in ? lx : 0), W);
+            const int yy = reflect_clamp(ty0 - UO + (in ? ly : 0), H);
+            const int xx = reflect_clamp(tx0 - UO + (in ? lx : 0), W);
             __builtin_amdgcn_global_load_lds(u_prev + (size_t)yy * W + xx, su + c * 64, 4, 0, 0);
+        }
+    } else {
+        const float lamp = io.lam_prev[0];
+        const int th_own = min(Th, H - ty0), tw_own = min(Tw, W - tx0);
+        const int n = luh * luw;
+        for (int base = 0; base < n; base += 4 * THREADS) {
+            float up[4], ff[4], xf[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = min(base + k * THREADS + tid, n - 1);
+                const int ly = i / luw, lx = i - ly * luw;
+                const int yy = reflect_clamp(ty0 - UO + ly, H), xx = reflect_clamp(tx0 - UO + lx, W);
+                const size_t q = (size_t)yy * W + xx;
+                up[k] = u_prev[q];
+                ff[k] = f[q];
+                xf[k] = pixel_force<R>(io.x_prev, io.xt, yy, xx);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = base + k * THREADS + tid;
+                if (i < n) {
+                    const int ly = i / luw, lx = i - ly * luw;
+                    const float uv = reaction_step(io.react, up[k], xf[k], ff[k], lamp, io.proj_c);
+                    su[ly * L.ldw + lx] = uv;
+                    const int oy = ly - UO, ox = lx - UO;
+                    if (oy >= 0 && oy < th_own && ox >= 0 && ox < tw_own)
+                        io.u_keep[(size_t)(ty0 + oy) * W + tx0 + ox] = uv;
+                }
+            }
         }
     }
     // (2c) polynomial form: the prepared coefficient table straight into LDS in
@@ -522,7 +566,7 @@ __device__ __forceinline__ void fused_tile(
     auto process = [&](int e, int cb, floatx4 *c1, const floatx4 *ca, float *xa, int en, int cbn,
                        floatx4 *n1, floatx4 *na) {
         const int c = 16 * cb + j;
-        const int xi = tx0 - R + c;
+        const int xi = tx0 + SO + c;
         const bool valid = (c < Ew) && (xi >= 0) && (xi < W);
         // input-gradient mode with export: z and a of this lane's pixel if it is
         // one of the tile's own (every image pixel is own to exactly one tile),
@@ -603,7 +647,7 @@ __device__ __forceinline__ void fused_tile(
     const float *fn = f;
     float *uo = io.out;
     const int y_lim = min(Th, H - ty0);
-    const int e_lo = max(0, R - ty0), e_hi = min(Eh, H - ty0 + R);
+    const int e_lo = max(0, -(ty0 + SO)), e_hi = min(Eh, H - (ty0 + SO));  // source rows in the image
     // the thread's p-th output of a round: row y0 + pdy[p], column pdx[p]
     int pdy[PF], pdx[PF];
 #pragma unroll
@@ -668,6 +712,40 @@ __device__ __forceinline__ void fused_tile(
         }
     };
 
+    // ---- forward: export of completed ring rows to the tile's slab.  Ring row o
+    // (source row e feeds ring row e - a with its tap row a) is slab row o + 2R;
+    // slab column dx is P column dx.  Tap rows written by source rows outside
+    // [0, e_hi) count as zero.
+    const int sw = Tw + 2 * R;
+    const int sw_own = min(Tw, W - tx0) + 2 * R;
+    int xdy[XF ? PX : 1], xdx[XF ? PX : 1];
+    if (XF) {
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            const int i = tid + p * THREADS;
+            xdy[p] = i / sw;
+            xdx[p] = i - xdy[p] * sw;
+        }
+    }
+    auto export_rows = [&](int o0, int o1) {
+        float *xo = io.x_out;
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            if (xdy[p] >= o1 - o0) break;
+            const int o = o0 + xdy[p], dx = xdx[p];
+            if (dx >= sw_own) continue;
+            const float *b = slot_of(o) + dx;
+            float xs = 0.f;
+#pragma unroll
+            for (int a = 0; a < KS; ++a) {
+                const int e = o + a;  // the source row that wrote tap row a
+                const float v = b[a * PW];
+                xs += (e >= 0 && e < e_hi) ? v : 0.f;
+            }
+            xo[(o + 2 * R) * sw + dx] = xs;
+        }
+    };
+
     // ---- main loop: rounds of NW E rows, one per wave.  After round k the
     // partials of every E row below NW (k+1) are in the ring; the output rows
     // they complete are produced after its barrier, before the next round's
@@ -688,6 +766,7 @@ __device__ __forceinline__ void fused_tile(
         c1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
         ca[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
+    int o_done = -2 * R;  // forward: ring rows exported so far
     for (int k = 0; k < rounds; ++k) {
         const bool sync = !(merge && k == rounds - 2);
         int y_end = e_hi <= NW * (k + 1) ? Th : max(0, NW * (k + 1) - 2 * R);
@@ -695,7 +774,7 @@ __device__ __forceinline__ void fused_tile(
         const int y0 = min(y_done, y_end);
         // f of this round's outputs, loaded ahead of the round's compute
         float fpre[PF];
-        if (!BWD) {
+        if (!BWD && !XF) {
 #pragma unroll
             for (int p = 0; p < PF; ++p) {
                 fpre[p] = 0.f;
@@ -729,8 +808,15 @@ __device__ __forceinline__ void fused_tile(
         }
         if (!sync) continue;
         __syncthreads();
-        produce(y0, y_end, fpre);
-        y_done = max(y_done, y_end);
+        if (XF) {
+            // ring rows below every source row still to come are complete
+            const int o_end = e_hi <= NW * (k + 1) ? e_hi : NW * (k + 1) - 2 * R;
+            export_rows(o_done, o_end);
+            o_done = o_end;
+        } else {
+            produce(y0, y_end, fpre);
+            y_done = max(y_done, y_end);
+        }
     }
     __syncthreads();  // LDS is free for the workgroup's next tile
 }
@@ -753,8 +839,42 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     ii.u_cur = io.u_cur ? io.u_cur + img * plane : nullptr;
     ii.g_cur = io.g_cur ? io.g_cur + img * plane : nullptr;
     ii.za = io.za ? io.za + img * plane * za_stride(Nk) : nullptr;
+    if (MODE == MODE_FWD) {
+        const size_t sl = (size_t)io.xt.sl;
+        ii.x_out = io.x_out + ((size_t)img * tiles_per_img + trem) * sl;
+        ii.x_prev = io.x_prev ? io.x_prev + (size_t)img * tiles_per_img * sl : nullptr;
+        ii.u_keep = io.u_keep ? io.u_keep + img * plane : nullptr;
+    }
     fused_tile<KS, NMB, NB, NW, MODE, PREC, RBFM>(ii, H, W, Th, Tw, ty * Th, tx * Tw, filt, Nk, rbfw,
                                                   Nrbf, rb, lam_t, lds);
+}
+
+// Final reaction of a forward in exchange form: u_T = reaction(u_{T-1}, force
+// gathered from the last stage's slabs, f) at the own pixels of one tile per
+// workgroup (workgroup b: image b / tiles_per_img, tile b mod tiles_per_img).
+template <int R>
+__global__ void __launch_bounds__(256) k_react_final(const float *__restrict__ u_prev,
+                                                     const float *__restrict__ f,
+                                                     const float *__restrict__ xs, float *__restrict__ out,
+                                                     XTiles xt, int tiles_per_img,
+                                                     const float *__restrict__ lam, int react, float proj_c)
+{
+    const int img = blockIdx.x / tiles_per_img;
+    const int tile = blockIdx.x - img * tiles_per_img;
+    const int ty = tile / xt.nx, tx = tile - ty * xt.nx;
+    const int y0 = ty * xt.Th, x0 = tx * xt.Tw;
+    const int th = min(xt.Th, xt.H - y0), tw = min(xt.Tw, xt.W - x0);
+    const size_t plane = (size_t)xt.H * xt.W;
+    const float *up = u_prev + img * plane;
+    const float *fp = f + img * plane;
+    float *op = out + img * plane;
+    const float *xi = xs + (size_t)img * tiles_per_img * xt.sl;
+    const float l = lam[0];
+    for (int i = threadIdx.x; i < th * tw; i += 256) {
+        const int y = y0 + i / tw, x = x0 + i % tw;
+        const size_t q = (size_t)y * xt.W + x;
+        op[q] = reaction_step(react, up[q], pixel_force<R>(xi, xt, y, x), fp[q], l, proj_c);
+    }
 }
 
 // ------------------------------------------------------------------ batched
@@ -762,31 +882,71 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
 // workgroup b takes the b-th (image, tile) item of the stage and runs the
 // fused stage on it with that image's model (chosen by its look number).
 // Stages are ordered by the kernel boundaries, so no workgroup ever waits on
-// another.  Ping-pong: stage t writes u_out if T-1-t is even, else the
-// image's scratch plane, and reads the other (stage 0 reads f).
+// another.  State planes: u_t (t >= 1) lives in u_out if T - t is even, else
+// in the image's scratch plane (u_0 = f); stage t reads u_{t-1}, applies the
+// pending reaction of stage t - 1 in its prologue (writing u_t), and writes its
+// slabs to xs[t & 1]; k_batched_final applies the last reaction into u_out.
+__device__ __forceinline__ XTiles batch_xtiles(const BatchImage &im, int Th, int Tw, int R)
+{
+    return make_xtiles(im.H, im.W, Th, Tw, R);
+}
+
+__device__ __forceinline__ float *batch_plane(const BatchImage &im, int T, int t)
+{
+    return ((T - t) & 1) == 0 ? im.u_out : im.u_tmp;
+}
+
 template <int KS, int NMB, int NB, int NW, int RBFM>
 __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
 {
     extern __shared__ float lds[];
-    constexpr int KK = KS * KS;
+    constexpr int KK = KS * KS, R = KS / 2;
     const BatchItem it = a.items[blockIdx.x];
     const BatchImage im = a.imgs[it.image];
     const int ty = it.tile / im.tiles_x, tx = it.tile - ty * im.tiles_x;
-    const bool to_out = ((a.T - 1 - t) & 1) == 0;
+    const BatchModel md = a.models[im.model];
     FusedIO io{};
     io.f = im.f;
-    io.u_prev = t == 0 ? im.f : (to_out ? im.u_tmp : im.u_out);
-    io.out = to_out ? im.u_out : im.u_tmp;
+    io.xt = batch_xtiles(im, a.Th, a.Tw, R);
+    io.pend = t > 0;
+    io.u_prev = t <= 1 ? im.f : batch_plane(im, a.T, t - 1);
+    io.u_keep = t > 0 ? batch_plane(im, a.T, t) : nullptr;
+    io.x_prev = t > 0 ? im.xs[(t - 1) & 1] : nullptr;
+    io.x_out = im.xs[t & 1] + (size_t)it.tile * io.xt.sl;
+    io.lam_prev = md.lam + (t > 0 ? t - 1 : 0);
+    io.out = nullptr;
     io.u_cur = nullptr;
     io.g_cur = nullptr;
     io.za = nullptr;
-    const BatchModel md = a.models[im.model];
     io.react = md.react;
     io.proj_c = md.proj_c;
     io.prep = md.prep + (size_t)t * a.prep_stage;
     fused_tile<KS, NMB, NB, NW, MODE_FWD, PREC_F32, RBFM>(
         io, im.H, im.W, a.Th, a.Tw, ty * a.Th, tx * a.Tw, md.filt + (size_t)t * a.Nk * KK, a.Nk,
         md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb, md.lam + t, lds);
+}
+
+// The last stage's reaction of every image: u_T into u_out, one (image, tile)
+// item per workgroup.
+template <int R>
+__global__ void __launch_bounds__(256) k_batched_final(BatchArgs a)
+{
+    const BatchItem it = a.items[blockIdx.x];
+    const BatchImage im = a.imgs[it.image];
+    const BatchModel md = a.models[im.model];
+    const XTiles xt = batch_xtiles(im, a.Th, a.Tw, R);
+    const int ty = it.tile / xt.nx, tx = it.tile - ty * xt.nx;
+    const int y0 = ty * xt.Th, x0 = tx * xt.Tw;
+    const int th = min(xt.Th, xt.H - y0), tw = min(xt.Tw, xt.W - x0);
+    const int T = a.T;
+    const float *up = T == 1 ? im.f : batch_plane(im, T, T - 1);
+    const float *xs = im.xs[(T - 1) & 1];
+    const float l = md.lam[T - 1];
+    for (int i = threadIdx.x; i < th * tw; i += 256) {
+        const int y = y0 + i / tw, x = x0 + i % tw;
+        const size_t q = (size_t)y * xt.W + x;
+        im.u_out[q] = reaction_step(md.react, up[q], pixel_force<R>(xs, xt, y, x), im.f[q], l, md.proj_c);
+    }
 }
 
 template <int KS, int NMB, int NB, int NW, int MODE, int PREC, int RBFM>
@@ -810,10 +970,31 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     if (RBFM == RBF_POLY && !s.prep) return hipErrorInvalidValue;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
+    if (MODE == MODE_FWD) {
+        if (!s.x_out || (s.pend && (!s.x_prev || !s.u_keep || !s.lam_prev))) return hipErrorInvalidValue;
+        io.x_prev = s.x_prev;
+        io.x_out = s.x_out;
+        io.u_keep = s.u_keep;
+        io.lam_prev = s.pend ? s.lam_prev : s.lam;
+        io.pend = s.pend;
+        io.xt = make_xtiles(s.H, s.W, th, tw, KS / 2);
+    }
     dim3 grid(tiles * s.N);
     hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW, MODE, PREC, RBFM>), grid, dim3(64 * NW),
                        lds_bytes, stream, io, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk, s.rbfw,
                        s.grid.nrbf, rb, s.lam);
+    return hipGetLastError();
+}
+
+// Final reaction of a forward in exchange form on the tiling (th, tw).
+template <int KS>
+inline hipError_t launch_react_final(const StageArgs &s, int th, int tw, hipStream_t stream)
+{
+    if (!s.x_prev || !s.lam_prev || !s.u_prev || !s.u_next) return hipErrorInvalidValue;
+    const XTiles xt = make_xtiles(s.H, s.W, th, tw, KS / 2);
+    const int tiles = xt.nx * xt.ny;
+    hipLaunchKernelGGL((k_react_final<KS / 2>), dim3(tiles * s.N), dim3(256), 0, stream, s.u_prev, s.f,
+                       s.x_prev, s.u_next, xt, tiles, s.lam_prev, s.react, s.proj_c);
     return hipGetLastError();
 }
 
@@ -856,7 +1037,8 @@ inline hipError_t launch_batched_t(const BatchArgs &a, hipStream_t stream)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    hipLaunchKernelGGL((k_batched_final<KS / 2>), dim3(a.items_per_stage), dim3(256), 0, stream, a);
+    return hipGetLastError();
 }
 
 template <int KS, int NMB, int RBFM>

@@ -38,11 +38,15 @@ inline void raise_lds_limit(const void *kernel)
     }
 }
 
-// One forward stage over N equally sized images.
+// One forward stage over N equally sized images.  The forward runs in
+// exchange form (see XTiles): stage t writes its diffusion force to slabs, and
+// its reaction is applied by stage t + 1's prologue or by fused_finish.
 struct StageArgs {
-    const float *u_prev;  // [N][H][W] u_{t-1}
+    const float *u_prev;  // [N][H][W] u_{t-1} (forward with pend: u_{t-2}, input of the
+                          // pending reaction)
     const float *f;       // [N][H][W]
-    float *u_next;        // [N][H][W] u_t (input-gradient mode: g_{t-1})
+    float *u_next;        // [N][H][W] input-gradient mode: g_{t-1}; split forward and
+                          // fused_finish: the stage output
     const float *u_cur;   // input-gradient mode: u_t
     const float *g_cur;   // input-gradient mode: g_t
     int N, H, W;
@@ -63,6 +67,12 @@ struct StageArgs {
     const float *prep = nullptr;  // polynomial form: this stage's block written by fused_prep
                                   // (phi table in the forward, d phi / ds in the input-gradient
                                   // mode; FP32 operands use its filter block too); required there
+    // fused forward (exchange form)
+    int pend = 0;                  // the previous stage's reaction is still to be applied
+    const float *x_prev = nullptr; // pend / fused_finish: the previous stage's slabs
+    float *x_out = nullptr;        // this stage's slabs
+    float *u_keep = nullptr;       // pend: where u_{t-1} (own pixels) goes
+    const float *lam_prev = nullptr;  // pend / fused_finish: lambda of the pending reaction
 };
 
 // Batched forward (device descriptors, filled on the host).
@@ -70,6 +80,7 @@ struct BatchImage {
     const float *f;
     float *u_out;
     float *u_tmp;
+    float *xs[2];  // slabs of even and odd stages (tiles x (Th + 2R)(Tw + 2R) floats each)
     int H, W, tiles_x, tiles, model;
 };
 
@@ -117,6 +128,13 @@ hipError_t split_stage(const StageArgs &s, hipStream_t stream);
 size_t split_scratch_floats(int N, int H, int W, int Nk);
 
 hipError_t fused_stage(const StageArgs &s, hipStream_t stream);
+// The pending reaction of the last forward stage: u_next = reaction(u_prev,
+// force from x_prev, f) with lam_prev, on the tiling fused_stage used.
+hipError_t fused_finish(const StageArgs &s, hipStream_t stream);
+// Floats of one set of slabs of a fused forward with these arguments (0 when
+// the fused kernel cannot run them).
+size_t fused_slab_floats(int ks, int nk, int nrbf, int N, int H, int W, int tile_h, int tile_w,
+                         int waves, bool poly);
 hipError_t fused_stage_input_grad(const StageArgs &s, hipStream_t stream);
 bool fused_supported(int ks, int Nk, int nrbf, int window, int prec);
 bool fused_config_ok(int ks, int Nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves,
@@ -131,6 +149,7 @@ hipError_t fused_launch_fwd_mixed(const StageArgs &s, int th, int tw, int nb, in
                                   hipStream_t stream);
 hipError_t fused_launch_bwd(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
                             hipStream_t stream);
+hipError_t fused_launch_final(const StageArgs &s, int th, int tw, hipStream_t stream);
 hipError_t batched_launch_impl(const BatchArgs &a, int ks, int nb, int nw, int rbfm,
                                hipStream_t stream);
 

@@ -208,11 +208,13 @@ def test_other_rbf_counts(nrbf, mu0):
     assert rel_inf(got, ref) <= TOL
 
 
-@pytest.mark.parametrize("th", [43, 44, 45, 10])
+@pytest.mark.parametrize("th", [41, 42, 43, 9, 10, 16])
 def test_merged_last_round_tiles(th):
-    """Tile heights whose last row round holds 1 or 2 E rows (43, 44: run without a barrier
-    of their own after the round before), 3 rows (45: a round of its own) and a tile of
-    two rounds (10); the 100-row image ends in a partial tile row for each."""
+    """Tile heights whose last round of rows (8 waves, one row each) holds 1 or 2 rows
+    (41, 42: run without a barrier of their own after the round before), 3 rows (43: a
+    round of its own), tiles of one round plus 1 or 2 rows (9, 10: a single export of
+    every slab row) and of two full rounds (16); the 100-row image ends in a partial
+    tile row for each."""
     print(f"[merged round th={th}]", flush=True)
     m = synth.config_model(2)
     _, f = synth.make_pair(100, 70, 1, config_id=2, index=th)
