@@ -45,6 +45,17 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 FLOP_PER_PX_STAGE_FWD = 2 * 2 * 48 * 49   # K and K^T, 48 filters of 7x7 (multiply-add = 2 flop)
+# forward + backward: the forward's K and K^T, then the backward's K u (z, not stored by the
+# forward), K e, K^T (phi' a) and the two dK correlations: 5 more contractions of 4704 flop
+FLOP_PER_PX_STAGE_FWD_BWD = FLOP_PER_PX_STAGE_FWD + 5 * 4704
+
+
+def roofline_entry(mpst, flop_per_pxst, peak_tflops, note):
+    """Convolution work of a whole form (every kernel of a call) against a published
+    peak: achieved = algorithmic flop per pixel-stage x pixel-stages per second."""
+    achieved = mpst * 1e6 * flop_per_pxst / 1e12
+    return {"bound": "mfma", "achieved": achieved, "peak": peak_tflops, "unit": "TFLOP/s",
+            "frac": achieved / peak_tflops, "flop_per_pixel_stage": flop_per_pxst, "basis": note}
 
 
 def parse():
@@ -155,7 +166,8 @@ def leg_forward(args, impl_code):
 
 
 def leg_fwd_bwd(args):
-    """16 x 180 x 180, forward keeping the states + hand-written backward."""
+    """16 x 180 x 180: forward (checkpoints every 4 stages; the backward recomputes the
+    states between them) + hand-written backward, and the same with every state stored."""
     import torch
     from paper_1702_07482_amd import synth, tnrd
 
@@ -167,47 +179,63 @@ def leg_fwd_bwd(args):
     dm = tnrd.DeviceModel.from_numpy(m)
     fd = torch.from_numpy(f).cuda().contiguous()
     ud = torch.from_numpy(ugt).cuda().contiguous()
-    o = tnrd.default_opts()
     mm = dm.abi()
-    nbf = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 0)
-    nbb = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 1)
-    if nbf == 0 or nbb == 0:
-        raise RuntimeError("unsupported configuration")
-    wsf = torch.empty(nbf, dtype=torch.uint8, device="cuda")
-    wsb = torch.empty(nbb, dtype=torch.uint8, device="cuda")
     u = torch.empty_like(fd)
-    states = torch.empty((T + 1, N, H, W), dtype=torch.float32, device="cuda")
     g = torch.empty_like(fd)
     dK = torch.empty_like(dm.filters)
     dW = torch.empty_like(dm.rbf_w)
     dl = torch.empty_like(dm.lam)
+    res = {}
+    for every in (4, 1):
+        o = tnrd.default_opts(recompute_every=every)
+        nbf = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 0)
+        nbb = tnrd.tnrd_workspace_bytes(N, H, W, mm, o, 1)
+        if nbf == 0 or nbb == 0:
+            raise RuntimeError("unsupported configuration")
+        wsf = torch.empty(nbf, dtype=torch.uint8, device="cuda")
+        wsb = torch.empty(nbb, dtype=torch.uint8, device="cuda")
+        ns = tnrd.tnrd_num_checkpoints(T, every)
+        states = torch.empty((ns, N, H, W), dtype=torch.float32, device="cuda")
 
-    def step():
-        st = tnrd.tnrd_forward(fd, N, H, W, 1, mm, u, states, o, wsf, nbf)
-        if st != 0:
-            raise RuntimeError(tnrd.status_str(st))
-        torch.sub(u, ud, out=g)
-        g.mul_(2.0 / g.numel())
-        st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, None, o, wsb, nbb)
-        if st != 0:
-            raise RuntimeError(tnrd.status_str(st))
+        def step():
+            st = tnrd.tnrd_forward(fd, N, H, W, 1, mm, u, states, o, wsf, nbf)
+            if st != 0:
+                raise RuntimeError(tnrd.status_str(st))
+            torch.sub(u, ud, out=g)
+            g.mul_(2.0 / g.numel())
+            st = tnrd.tnrd_backward(fd, N, H, W, 1, mm, states, g, dK, dW, dl, None, None, o, wsb, nbb)
+            if st != 0:
+                raise RuntimeError(tnrd.status_str(st))
 
-    steps = max(3, args.steps // 5)
-    for _ in range(max(2, args.warmup // 5)):
-        step()
-    torch.cuda.synchronize()
-    a, b = _events()
-    a.record()
-    for _ in range(steps):
-        step()
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / steps
-    return {"value": N * H * W * T / 1e6 / (ms / 1e3), "unit": "megapixel-stages/s",
-            "ms_per_step": ms, "steps": steps,
-            "workload": "forward (states kept) + backward, 16 x 180 x 180 FP32, L=1, 8 stages x "
-                        "48 7x7 filters, loss mean((u_T - u_gt)^2); gradients for all filters, "
-                        "RBF weights and lambda"}
+        steps = max(3, args.steps // 5)
+        for _ in range(max(2, args.warmup // 5)):
+            step()
+        torch.cuda.synchronize()
+        a, b = _events()
+        a.record()
+        for _ in range(steps):
+            step()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        mpst = N * H * W * T / 1e6 / (ms / 1e3)
+        res[every] = {"value": mpst, "ms_per_step": ms, "steps": steps, "checkpoints": ns,
+                      "state_bytes": ns * N * H * W * 4}
+        del wsf, wsb, states
+    out = dict(res[4])
+    out.update({
+        "unit": "megapixel-stages/s", "recompute_every": 4,
+        "roofline": roofline_entry(out["value"], FLOP_PER_PX_STAGE_FWD_BWD, PEAK_FP32_MFMA_TFLOPS,
+                                   "FP32 matrix peak; 32928 flop per pixel-stage (forward K, K^T; "
+                                   "backward K u, K e, K^T, two dK correlations); the recomputed "
+                                   "forward stages are not counted"),
+        "store_all": dict(res[1], recompute_every=1),
+        "workload": "forward (states checkpointed every 4 stages, recomputed in the backward) + "
+                    "backward, 16 x 180 x 180 FP32, L=1, 8 stages x 48 7x7 filters, loss "
+                    "mean((u_T - u_gt)^2); gradients for all filters, RBF weights and lambda"})
+    out["store_all"]["roofline"] = roofline_entry(res[1]["value"], FLOP_PER_PX_STAGE_FWD_BWD,
+                                                  PEAK_FP32_MFMA_TFLOPS, "as above")
+    return out
 
 
 def leg_train(args):
@@ -283,8 +311,11 @@ def leg_batched(args):
         stream.synchronize()
     ms = a.elapsed_time(b) / steps
     mp = sum(h * w for h, w in sizes) / 1e6
-    return {"value": mp * T / (ms / 1e3), "unit": "megapixel-stages/s", "ms_per_step": ms,
+    mpst = mp * T / (ms / 1e3)
+    return {"value": mpst, "unit": "megapixel-stages/s", "ms_per_step": ms,
             "steps": steps, "megapixels": mp, "tile": [th, tw, nw],
+            "roofline": roofline_entry(mpst, FLOP_PER_PX_STAGE_FWD, PEAK_FP32_MFMA_TFLOPS,
+                                       "FP32 matrix peak; 9408 flop per pixel-stage (K and K^T)"),
             "workload": "batched forward, 64 images of 256x256/384x512/512x512/1024x768, "
                         "L in {1,2,4,8} (one model per L), 8 stages x 48 7x7, FP32, one "
                         "launch per stage over all tiles, replayed from a HIP graph"}
@@ -349,25 +380,89 @@ def leg_mixed(args):
         fwd_bwd()
         torch.cuda.synchronize()
         a.record()
-        fwd_bwd()
+        for _ in range(2):
+            fwd_bwd()
         b.record()
         torch.cuda.synchronize()
-        ms_fb = a.elapsed_time(b)
+        ms_fb = a.elapsed_time(b) / 2
         mpst = N * H * W * T / 1e6
+        peak = PEAK_FP32_MFMA_TFLOPS if name == "fp32" else PEAK_BF16_TFLOPS
+        pname = "FP32 matrix" if name == "fp32" else f"dense {name.upper()} matrix (2.5 PFLOP/s)"
         res[name] = {"fwd_mpst_s": mpst / (ms_f / 1e3), "fwd_ms": ms_f,
-                     "fwd_bwd_mpst_s": mpst / (ms_fb / 1e3), "fwd_bwd_ms": ms_fb}
+                     "fwd_bwd_mpst_s": mpst / (ms_fb / 1e3), "fwd_bwd_ms": ms_fb,
+                     "roofline_fwd": roofline_entry(mpst / (ms_f / 1e3), FLOP_PER_PX_STAGE_FWD, peak,
+                                                    f"{pname} peak; 9408 flop per pixel-stage"),
+                     "roofline_fwd_bwd": roofline_entry(
+                         mpst / (ms_fb / 1e3), FLOP_PER_PX_STAGE_FWD_BWD, peak,
+                         f"{pname} peak; 32928 flop per pixel-stage (the backward's parameter-"
+                         "gradient contractions run FP32)")}
         del wsf, wsb
-    ref = outs["fp32"].double()
-    mse_ref = torch.mean((ref - ud.double()) ** 2).item()
-    for name in ("bf16", "fp16"):
-        d = (outs[name].double() - ref).abs()
-        mse = torch.mean((outs[name].double() - ud.double()) ** 2).item()
-        res[name]["max_rel_err_vs_fp32_path"] = (d.max() / ref.abs().max()).item()
-        res[name]["mean_abs_err_vs_fp32_path"] = d.mean().item()
-        res[name]["dpsnr_db_vs_fp32_path"] = abs(10 * math.log10(mse_ref / mse))
+    # the outputs on the oracle patches; the CPU-baseline leg compares them with the oracle
+    res["_patch_inputs"] = mixed_patch_inputs(f, ugt, m, outs)
     res["workload"] = ("mixed precision: 8 x 2048 x 2048, L=1, 8 stages x 48 7x7; filter-bank "
                        "operands FP32/BF16/FP16 with FP32 accumulation; influence and prox FP32")
     return res
+
+
+# 128 x 128 patches (image, row, column) on which the mixed-precision outputs are
+# compared with the FP64 oracle: a corner, the interior, the bottom and the right border
+MIXED_PATCHES = [(0, 0, 0), (3, 960, 960), (5, 1920, 512), (7, 600, 1920)]
+MIXED_PATCH = 128
+
+
+def mixed_patch_inputs(f, ugt, m, outs):
+    """For each patch of MIXED_PATCHES: the crop of f holding the patch plus its
+    receptive field (T stages x (k - 1) = 48 pixels per side, or up to the image
+    border, which the crop then shares, so u_T on the patch is the whole image's),
+    the patch's clean image, and each precision's u_T on the patch."""
+    T = m["filters"].shape[0]
+    radius = T * (m["filters"].shape[2] - 1)
+    N, H, W = f.shape
+    host = {k: v.cpu().numpy() for k, v in outs.items()}
+    items = []
+    for n, y0, x0 in MIXED_PATCHES:
+        y1, x1 = y0 + MIXED_PATCH, x0 + MIXED_PATCH
+        cy0, cy1 = max(0, y0 - radius), min(H, y1 + radius)
+        cx0, cx1 = max(0, x0 - radius), min(W, x1 + radius)
+        items.append({"crop": np.ascontiguousarray(f[n, cy0:cy1, cx0:cx1]),
+                      "at": (y0 - cy0, x0 - cx0),
+                      "clean": ugt[n, y0:y1, x0:x1].astype(np.float64),
+                      "got": {k: host[k][n, y0:y1, x0:x1].astype(np.float64) for k in host}})
+    return {"model": m, "items": items}
+
+
+def mixed_vs_oracle(pin):
+    """CPU-baseline leg: error of each precision's u_T against the FP64 oracle on
+    MIXED_PATCHES (the oracle runs on each patch's crop).  Per precision: max |a - b| /
+    max |b| and mean |a - b| over the patches, and the PSNR of u_T against the clean
+    image on the patches (peak 255) minus the oracle's."""
+    import oracle
+
+    t0 = time.perf_counter()
+    ref, clean, got = [], [], {}
+    for it in pin["items"]:
+        uT = oracle.forward(it["crop"], pin["model"])
+        y, x = it["at"]
+        ref.append(uT[y:y + MIXED_PATCH, x:x + MIXED_PATCH])
+        clean.append(it["clean"])
+        for k, v in it["got"].items():
+            got.setdefault(k, []).append(v)
+    ref, clean = np.stack(ref), np.stack(clean)
+
+    def psnr(u):
+        mse = float(np.mean((u - clean) ** 2))
+        return 10 * math.log10(255.0 ** 2 / mse) if mse > 0 else float("inf")
+
+    out = {"oracle_patches": {"patches": [list(p) for p in MIXED_PATCHES], "size": MIXED_PATCH,
+                              "oracle_s": time.perf_counter() - t0,
+                              "psnr_db_oracle": psnr(ref)}}
+    for k, v in got.items():
+        a = np.stack(v)
+        d = np.abs(a - ref)
+        out[k + "_vs_oracle"] = {"max_rel_err": float(d.max() / np.abs(ref).max()),
+                                 "mean_abs_err": float(d.mean()),
+                                 "dpsnr_db": psnr(a) - psnr(ref)}
+    return out
 
 
 def leg_projected(args):
@@ -572,7 +667,29 @@ def cpu_baseline(f, m, rows):
         "cores": oracle.max_threads(), "kind": "oracle",
         "sample": f"FP64 oracle forward, all {T} stages, on rows 0..{rows - 1} of the "
                   f"512x512 image ({rows}x512 px), {runs} runs of {dt:.1f} s each",
+        "single_thread": cpu_single_thread(f, m),
     }
+
+
+def cpu_single_thread(f2, m2):
+    """The oracle on one thread (the paper's CPU figures are single-threaded Matlab,
+    Table runtime; context only): the whole 128 x 128 image of 5 stages x 24 5x5
+    filters, and a 32-row strip of the 512 x 512 image with 8 stages x 48 7x7."""
+    import oracle
+    from paper_1702_07482_amd import synth
+
+    out = {}
+    m1 = synth.config_model(1)
+    _, f1 = synth.make_pair(128, 128, 1, config_id=1)
+    for name, img, m in (("plain forward 1x128x128, 5 stages x 24 5x5", f1, m1),
+                         ("plain forward, rows 0..31 of 1x512x512, 8 stages x 48 7x7",
+                          np.ascontiguousarray(f2[:32]), m2)):
+        t0 = time.perf_counter()
+        oracle.forward(img, m, nthreads=1)
+        dt = time.perf_counter() - t0
+        out[name] = {"value": img.size * m["filters"].shape[0] / 1e6 / dt,
+                     "unit": "megapixel-stages/s", "seconds": dt, "cores": 1}
+    return out
 
 
 def main():
@@ -631,8 +748,11 @@ def main():
     if "peaks" in legs:
         out["peaks"] = leg_peaks(args)
         out["fractions"] = fractions(out)
+    pin = out["mixed"].pop("_patch_inputs", None) if "mixed" in out else None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(fwd["f"], fwd["m"], args.cpu_rows)
+        if pin is not None:
+            out["mixed"].update(mixed_vs_oracle(pin))
     print(json.dumps(out), flush=True)
 
 

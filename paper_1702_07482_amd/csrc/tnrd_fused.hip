@@ -180,13 +180,20 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
     }
     const long cus = device_cus();
     double best = 0.0;
+    // heights: forward from 2R (its LDS holds taller tiles), input-gradient mode 8..96
+    const int th_lo = xf ? tmin : 8, th_hi = xf ? 160 : 96;
+    // the polynomial form wherever a tile fits it (the Gaussian form's extra
+    // exponentials cost far more than a slightly worse tile)
+    bool poly_fits = false;
+    for (int nb = 2; nb <= 4 && poly; ++nb)
+        poly_fits = poly_fits || form(th_lo > H ? H : th_lo, 16 * nb - ring > W ? W : 16 * nb - ring, nb) == RBF_POLY;
     for (int nb = 2; nb <= 4; ++nb) {
         int tw = 16 * nb - ring;
         if (tw > W) tw = W;
-        for (int th = tmin; th <= 160; ++th) {
+        for (int th = th_lo; th <= th_hi; ++th) {
             const int t = th > H ? H : th;
             const int rbfm = form(t, tw, nb);
-            if (rbfm < 0) continue;
+            if (rbfm < 0 || (poly_fits && rbfm != RBF_POLY)) continue;
             const long tiles = (long)N * ((H + t - 1) / t) * ((W + tw - 1) / tw);
             const long rounds = (tiles + cus - 1) / cus;
             // per wave: ceil(rows / waves) rows of nb blocks (the rows go to the

@@ -149,46 +149,91 @@ __host__ __device__ inline XTiles make_xtiles(int H, int W, int th, int tw, int 
     return x;
 }
 
-// Force at padded position (qy, qx), -R <= qy < H + R, -R <= qx < W + R: the
-// covering tiles' slab entries added in a fixed order (tile rows, then tile
-// columns, ascending), so every caller forms the same bits.
+// The slab entry of tile (ty, tx) at padded position (qy, qx) sits at
+//   (ty nx + tx) sl + (qy - ty Th + R) sw + (qx - tx Tw + R)
+//   = [ty nx sl + (qy - ty Th + R) sw] + [tx sl + (qx - tx Tw + R)],
+// a row term plus a column term.  AxisTerms holds, for one axis of a pixel,
+// the terms of its padded images (the pixel itself and, within R of the
+// border, its mirror position, whose force the exact adjoint folds onto it)
+// and of the one or two tiles whose ring covers each image.  A missing second
+// tile repeats the first one's term (its load is masked), so every force sum
+// issues the same loads in the same order.
+struct AxisTerms {
+    int t[2][2];   // [image][covering tile] term
+    bool two[2];   // [image] a second covering tile exists
+    bool mir;      // the mirror image exists
+};
+
+// Terms of pixel coordinate p (0 <= p < n) along an axis of tiles of size ts,
+// nt of them; tile-index stride `ts_stride` (row axis: nx sl; column axis:
+// sl) and coordinate stride `c_stride` (row axis: sw; column axis: 1).
 template <int R>
-__device__ __forceinline__ float xpad_force(const float *__restrict__ xs, const XTiles &g, int qy, int qx)
+__host__ __device__ __forceinline__ AxisTerms axis_terms(int p, int n, int ts, int nt, int ts_stride,
+                                                         int c_stride)
 {
-    const int tyc = min(max(qy, 0) / g.Th, g.ny - 1);
-    const int txc = min(max(qx, 0) / g.Tw, g.nx - 1);
-    const bool ylo = tyc > 0 && qy < tyc * g.Th + R;                  // tile row tyc - 1 covers qy
-    const bool yhi = tyc + 1 < g.ny && qy >= (tyc + 1) * g.Th - R;   // tile row tyc + 1 covers qy
-    const bool xlo = txc > 0 && qx < txc * g.Tw + R;
-    const bool xhi = txc + 1 < g.nx && qx >= (txc + 1) * g.Tw - R;
-    const int ty0 = ylo ? tyc - 1 : tyc, ty1 = yhi ? tyc + 1 : tyc;
-    const int tx0 = xlo ? txc - 1 : txc, tx1 = xhi ? txc + 1 : txc;
-    auto at = [&](int ty, int tx) {
-        return xs[(size_t)(ty * g.nx + tx) * g.sl + (qy - ty * g.Th + R) * g.sw + (qx - tx * g.Tw + R)];
-    };
-    // four loads, whether or not the tiles differ (the duplicates are masked)
-    const float v00 = at(ty0, tx0), v01 = at(ty0, tx1), v10 = at(ty1, tx0), v11 = at(ty1, tx1);
+    AxisTerms a;
+    const int m = p < R ? -p - 1 : (p >= n - R ? 2 * n - 1 - p : p);
+    a.mir = m != p;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int q = k == 0 ? p : m;
+        const int tc = min(max(q, 0) / ts, nt - 1);
+        const bool lo = tc > 0 && q < tc * ts + R;            // tile tc - 1 covers q
+        const bool hi = tc + 1 < nt && q >= (tc + 1) * ts - R;  // tile tc + 1 covers q
+        const int t0 = lo ? tc - 1 : tc, t1 = hi ? tc + 1 : tc;
+        a.t[k][0] = t0 * ts_stride + (q - t0 * ts + R) * c_stride;
+        a.t[k][1] = t1 * ts_stride + (q - t1 * ts + R) * c_stride;
+        a.two[k] = t1 != t0;
+    }
+    return a;
+}
+
+template <int R>
+__host__ __device__ __forceinline__ AxisTerms row_terms(const XTiles &g, int y)
+{
+    return axis_terms<R>(y, g.H, g.Th, g.ny, g.nx * g.sl, g.sw);
+}
+
+template <int R>
+__host__ __device__ __forceinline__ AxisTerms col_terms(const XTiles &g, int x)
+{
+    return axis_terms<R>(x, g.W, g.Tw, g.nx, g.sl, 1);
+}
+
+// Force at the padded position given by row image iy and column image ix:
+// the covering tiles' entries added in a fixed order.
+__device__ __forceinline__ float xpad_terms(const float *__restrict__ xs, const AxisTerms &Y, int iy,
+                                            const AxisTerms &X, int ix)
+{
+    const float v00 = xs[Y.t[iy][0] + X.t[ix][0]], v01 = xs[Y.t[iy][0] + X.t[ix][1]];
+    const float v10 = xs[Y.t[iy][1] + X.t[ix][0]], v11 = xs[Y.t[iy][1] + X.t[ix][1]];
     float s = v00;
-    s += tx1 != tx0 ? v01 : 0.f;
-    s += ty1 != ty0 ? v10 : 0.f;
-    s += (ty1 != ty0 && tx1 != tx0) ? v11 : 0.f;
+    s += X.two[ix] ? v01 : 0.f;
+    s += Y.two[iy] ? v10 : 0.f;
+    s += (Y.two[iy] && X.two[ix]) ? v11 : 0.f;
     return s;
 }
 
-// Diffusion force x[p] = sum_i K_i^T v_i at pixel (y, x): the padded force at
-// p plus, within R of the border, at its mirror positions.
+// Diffusion force x[p] = sum_i K_i^T v_i at the pixel whose row and column
+// terms are Y and X: the padded force at p plus, within R of the border, at
+// its mirror positions.  Every caller (stage prologues, final reaction) forms
+// the same bits.
+__device__ __forceinline__ float force_at(const float *__restrict__ xs, const AxisTerms &Y,
+                                          const AxisTerms &X)
+{
+    float s = xpad_terms(xs, Y, 0, X, 0);
+    if (X.mir) s += xpad_terms(xs, Y, 0, X, 1);
+    if (Y.mir) {
+        s += xpad_terms(xs, Y, 1, X, 0);
+        if (X.mir) s += xpad_terms(xs, Y, 1, X, 1);
+    }
+    return s;
+}
+
 template <int R>
 __device__ __forceinline__ float pixel_force(const float *__restrict__ xs, const XTiles &g, int y, int x)
 {
-    const int my = y < R ? -y - 1 : (y >= g.H - R ? 2 * g.H - 1 - y : y);
-    const int mx = x < R ? -x - 1 : (x >= g.W - R ? 2 * g.W - 1 - x : x);
-    float s = xpad_force<R>(xs, g, y, x);
-    if (mx != x) s += xpad_force<R>(xs, g, y, mx);
-    if (my != y) {
-        s += xpad_force<R>(xs, g, my, x);
-        if (mx != x) s += xpad_force<R>(xs, g, my, mx);
-    }
-    return s;
+    return force_at(xs, row_terms<R>(g, y), col_terms<R>(g, x));
 }
 
 // Kernel arguments of one stage (forward or input-gradient mode).

@@ -258,31 +258,52 @@ __device__ __forceinline__ void fused_tile(
             __builtin_amdgcn_global_load_lds(u_prev + (size_t)yy * W + xx, su + c * 64, 4, 0, 0);
         }
     } else {
+        // wave w takes the tile rows w, w + NW, ...; lane l the columns l + 64 c.  A
+        // row's terms (reflection, covering tiles) are wave-uniform; a column's are
+        // computed once per lane.
         const float lamp = io.lam_prev[0];
         const int th_own = min(Th, H - ty0), tw_own = min(Tw, W - tx0);
-        const int n = luh * luw;
-        for (int base = 0; base < n; base += 4 * THREADS) {
-            float up[4], ff[4], xf[4];
+        constexpr int NCX = (16 * NB + 2 * R + 63) / 64;  // column chunks of the u tile
+        const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+        int xcol[NCX];
+        AxisTerms xt[NCX];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int i = min(base + k * THREADS + tid, n - 1);
-                const int ly = i / luw, lx = i - ly * luw;
-                const int yy = reflect_clamp(ty0 - UO + ly, H), xx = reflect_clamp(tx0 - UO + lx, W);
-                const size_t q = (size_t)yy * W + xx;
-                up[k] = u_prev[q];
-                ff[k] = f[q];
-                xf[k] = pixel_force<R>(io.x_prev, io.xt, yy, xx);
+        for (int c = 0; c < NCX; ++c) {
+            const int lx = min(lane + 64 * c, luw - 1);
+            xcol[c] = reflect_clamp(tx0 - UO + lx, W);
+            xt[c] = col_terms<R>(io.xt, xcol[c]);
+        }
+        constexpr int RU = 2;  // rows in flight per wave
+        for (int ly0 = wave_u; ly0 < luh; ly0 += RU * NW) {
+            float up[RU][NCX], ff[RU][NCX], xf[RU][NCX];
+#pragma unroll
+            for (int k = 0; k < RU; ++k) {
+                const int ly = min(ly0 + k * NW, luh - 1);
+                const int yy = reflect_clamp(ty0 - UO + ly, H);
+                const AxisTerms yt = row_terms<R>(io.xt, yy);
+                const size_t rowq = (size_t)yy * W;
+#pragma unroll
+                for (int c = 0; c < NCX; ++c) {
+                    up[k][c] = u_prev[rowq + xcol[c]];
+                    ff[k][c] = f[rowq + xcol[c]];
+                    xf[k][c] = force_at(io.x_prev, yt, xt[c]);
+                }
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int i = base + k * THREADS + tid;
-                if (i < n) {
-                    const int ly = i / luw, lx = i - ly * luw;
-                    const float uv = reaction_step(io.react, up[k], xf[k], ff[k], lamp, io.proj_c);
-                    su[ly * L.ldw + lx] = uv;
-                    const int oy = ly - UO, ox = lx - UO;
-                    if (oy >= 0 && oy < th_own && ox >= 0 && ox < tw_own)
-                        io.u_keep[(size_t)(ty0 + oy) * W + tx0 + ox] = uv;
+            for (int k = 0; k < RU; ++k) {
+                const int ly = ly0 + k * NW;
+                if (ly >= luh) break;
+                const int oy = ly - UO;
+#pragma unroll
+                for (int c = 0; c < NCX; ++c) {
+                    const int lx = lane + 64 * c;
+                    if (lx < luw) {
+                        const float uv = reaction_step(io.react, up[k][c], xf[k][c], ff[k][c], lamp, io.proj_c);
+                        su[ly * L.ldw + lx] = uv;
+                        const int ox = lx - UO;
+                        if (oy >= 0 && oy < th_own && ox >= 0 && ox < tw_own)
+                            io.u_keep[(size_t)(ty0 + oy) * W + tx0 + ox] = uv;
+                    }
                 }
             }
         }
@@ -850,8 +871,9 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
 }
 
 // Final reaction of a forward in exchange form: u_T = reaction(u_{T-1}, force
-// gathered from the last stage's slabs, f) at the own pixels of one tile per
-// workgroup (workgroup b: image b / tiles_per_img, tile b mod tiles_per_img).
+// gathered from the last stage's slabs, f), one pixel per thread: workgroup
+// (b, c) covers pixels 256 c .. 256 c + 255 of tile b mod tiles_per_img of
+// image b / tiles_per_img.
 template <int R>
 __global__ void __launch_bounds__(256) k_react_final(const float *__restrict__ u_prev,
                                                      const float *__restrict__ f,
@@ -870,7 +892,8 @@ __global__ void __launch_bounds__(256) k_react_final(const float *__restrict__ u
     float *op = out + img * plane;
     const float *xi = xs + (size_t)img * tiles_per_img * xt.sl;
     const float l = lam[0];
-    for (int i = threadIdx.x; i < th * tw; i += 256) {
+    const int i = blockIdx.y * 256 + threadIdx.x;
+    if (i < th * tw) {
         const int y = y0 + i / tw, x = x0 + i % tw;
         const size_t q = (size_t)y * xt.W + x;
         op[q] = reaction_step(react, up[q], pixel_force<R>(xi, xt, y, x), fp[q], l, proj_c);
@@ -926,8 +949,8 @@ __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
         md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb, md.lam + t, lds);
 }
 
-// The last stage's reaction of every image: u_T into u_out, one (image, tile)
-// item per workgroup.
+// The last stage's reaction of every image: u_T into u_out, one pixel per
+// thread; workgroup (b, c) covers pixels 256 c .. 256 c + 255 of item b.
 template <int R>
 __global__ void __launch_bounds__(256) k_batched_final(BatchArgs a)
 {
@@ -942,7 +965,8 @@ __global__ void __launch_bounds__(256) k_batched_final(BatchArgs a)
     const float *up = T == 1 ? im.f : batch_plane(im, T, T - 1);
     const float *xs = im.xs[(T - 1) & 1];
     const float l = md.lam[T - 1];
-    for (int i = threadIdx.x; i < th * tw; i += 256) {
+    const int i = blockIdx.y * 256 + threadIdx.x;
+    if (i < th * tw) {
         const int y = y0 + i / tw, x = x0 + i % tw;
         const size_t q = (size_t)y * xt.W + x;
         im.u_out[q] = reaction_step(md.react, up[q], pixel_force<R>(xs, xt, y, x), im.f[q], l, md.proj_c);
@@ -993,7 +1017,8 @@ inline hipError_t launch_react_final(const StageArgs &s, int th, int tw, hipStre
     if (!s.x_prev || !s.lam_prev || !s.u_prev || !s.u_next) return hipErrorInvalidValue;
     const XTiles xt = make_xtiles(s.H, s.W, th, tw, KS / 2);
     const int tiles = xt.nx * xt.ny;
-    hipLaunchKernelGGL((k_react_final<KS / 2>), dim3(tiles * s.N), dim3(256), 0, stream, s.u_prev, s.f,
+    hipLaunchKernelGGL((k_react_final<KS / 2>), dim3(tiles * s.N, (th * tw + 255) / 256), dim3(256), 0,
+                       stream, s.u_prev, s.f,
                        s.x_prev, s.u_next, xt, tiles, s.lam_prev, s.react, s.proj_c);
     return hipGetLastError();
 }
@@ -1037,7 +1062,8 @@ inline hipError_t launch_batched_t(const BatchArgs &a, hipStream_t stream)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_batched_final<KS / 2>), dim3(a.items_per_stage), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_batched_final<KS / 2>), dim3(a.items_per_stage, (a.Th * a.Tw + 255) / 256),
+                       dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
