@@ -394,8 +394,8 @@ def leg_mixed(args):
                                                     f"{pname} peak; 9408 flop per pixel-stage"),
                      "roofline_fwd_bwd": roofline_entry(
                          mpst / (ms_fb / 1e3), FLOP_PER_PX_STAGE_FWD_BWD, peak,
-                         f"{pname} peak; 32928 flop per pixel-stage (the backward's parameter-"
-                         "gradient contractions run FP32)")}
+                         f"{pname} peak; 32928 flop per pixel-stage (z = K u of the parameter-"
+                         "gradient pass runs FP32 in every mode)")}
         del wsf, wsb
     # the outputs on the oracle patches; the CPU-baseline leg compares them with the oracle
     res["_patch_inputs"] = mixed_patch_inputs(f, ugt, m, outs)

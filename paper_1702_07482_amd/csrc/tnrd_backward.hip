@@ -27,6 +27,18 @@
 // straight into the weight-gradient contraction without passing through LDS.
 // When it computes z and a itself, the filter-bank GEMM runs transposed
 // (rows = 16 pixels, columns = 16 filters) to leave them in that layout.
+// With BF16/FP16 operands (the mixed-precision backward), a = K e and the dK
+// contraction run on v_mfma_f32_16x16x16_{bf16,f16} with FP32 accumulation:
+// the transposed filter bank for a (k = 16 taps per step) and dK (k = the
+// block's 16 pixels in one step, whose B operand is the transposed bank's
+// accumulator quad, pixels 4g .. 4g+3 of filter j, converted once).  e enters
+// scaled by a per-tile power of two (max |e| -> 2^10, FP16's normal range)
+// that is undone in FP32 on dK and on the exported a.  Two operands stay
+// accurate to about 2^-16: z = K u stays on the FP32 instruction (it feeds phi,
+// phi' and the Gaussians of dW, and u carries a large mean that 8 or 11
+// mantissa bits of u or of k would move z by several units), and ubar enters
+// the second dK term as a BF16/FP16 pair ubar = hi + lo (two MFMAs).  The
+// influence function and dlambda stay FP32.
 //
 // k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms, each lane working
 // on one filter and owning its column (a filter has several lanes, each with a
@@ -68,10 +80,13 @@ struct BwdParamsIO {
 };
 
 struct BpLds {
-    int ldw, tile_size, u_off, e_off, t_off, t_pitch, red_off, red_size, dl_off, total;
+    int ldw, tile_size, u_off, e_off, t_off, t_pitch, red_off, red_size, dl_off, mb_off, total;
 };
 
-__host__ __device__ inline BpLds bp_lds(int ks, int nmb, int th, int tw, int nrbf, int nw)
+// mixed: room for the BF16/FP16 filter operands of a = K e, [nb][k-step][lane]
+// (8 bytes each)
+__host__ __device__ inline BpLds bp_lds(int ks, int nmb, int th, int tw, int nrbf, int nw,
+                                        bool mixed = false)
 {
     const int R = ks / 2;
     BpLds l;
@@ -84,7 +99,8 @@ __host__ __device__ inline BpLds bp_lds(int ks, int nmb, int th, int tw, int nrb
     l.red_off = l.t_off + 16 * nmb * l.t_pitch;
     l.red_size = 16 * nmb * ks * ks;
     l.dl_off = l.red_off + l.red_size;
-    l.total = l.dl_off + nw;
+    l.mb_off = (l.dl_off + nw + 1) & ~1;
+    l.total = l.mb_off + (mixed ? nmb * ((ks * ks + 15) / 16) * 64 * 2 : 0);
     return l;
 }
 
@@ -118,7 +134,7 @@ __device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__rest
 // the LDS allows it); it loads each block's z and a right before using them.
 // The one computing them is held to 256 (2 waves per SIMD); it reads a filter
 // block's GEMM operands from the LDS copy of the bank when it starts the block.
-template <int KS, int NMB, int NBW, int NW, bool LOADZA>
+template <int KS, int NMB, int NBW, int NW, bool LOADZA, int PREC>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LOADZA ? 4 : 2, 8)))
 k_bwd_params(
     BwdParamsIO io, int H, int W, int Th, int tiles_x, int tiles_per_img,
@@ -129,9 +145,14 @@ k_bwd_params(
     constexpr int R = G::R, KK = G::KK, KS1 = G::KS1, MB2 = G::MB2;
     constexpr int THREADS = 64 * NW;
     constexpr int Tw = 16 * NBW;
+    constexpr bool MIXED = PREC != PREC_F32;
+    static_assert(!(MIXED && LOADZA), "the mixed-precision variant computes z and a itself");
+    using MX = Mix<PREC>;
+    typedef typename MX::V MV;
+    constexpr int KSH = (KK + 15) / 16;  // mixed: transposed filter-bank k-steps of 16 taps
 
     extern __shared__ float lds[];
-    const BpLds L = bp_lds(KS, NMB, Th, Tw, Nrbf, NW);
+    const BpLds L = bp_lds(KS, NMB, Th, Tw, Nrbf, NW, MIXED);
     float *su = lds + L.u_off;
     float *se = lds + L.e_off;
     float *stab = lds + L.t_off;
@@ -163,6 +184,7 @@ k_bwd_params(
         }
     }
     float dl_acc = 0.f;
+    float emax = 0.f;  // mixed: largest |e| of the tile
     {
         const float *un = io.u_prev + img * plane;
         const float *uc = io.u_cur + img * plane;
@@ -196,6 +218,7 @@ k_bwd_params(
                     const float ev = proj ? (uv[k] > io.proj_c ? gg[k] : 0.f)
                                      : quad ? gg[k] : u2 / den * gg[k];
                     se[ly * L.ldw + lx] = ev;
+                    emax = fmaxf(emax, fabsf(ev));
                     int yi = ty0 - R + ly, xi = tx0 - R + lx;
                     bool own = ly >= R && ly < R + Th && lx >= R && lx < R + Tw && yi < H && xi < W;
                     if (own) {
@@ -238,7 +261,25 @@ k_bwd_params(
                 if (base + k * THREADS + tid < n) stab[base + k * THREADS + tid] = v[k];
         }
     }
+    // mixed: e is scaled by 2^(10 - ilogb(max |e|)) before its conversion (FP16's
+    // normal range is 2^-14 .. 65504; |K e| <= 7 max|e| for unit-norm 7x7 filters)
+    float escale = 1.f, einv = 1.f;
+    if (MIXED) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) emax = fmaxf(emax, __shfl_xor(emax, o));
+        if (lane == 0) sdl[wave] = emax;
+    }
     __syncthreads();
+    if (MIXED) {
+        float mx = 0.f;
+        for (int w = 0; w < NW; ++w) mx = fmaxf(mx, sdl[w]);
+        if (mx > 0.f && isfinite(mx)) {
+            const int ex = ilogbf(mx);
+            escale = ldexpf(1.f, 10 - ex);
+            einv = ldexpf(1.f, ex - 10);
+        }
+        __syncthreads();  // sdl is read again for dlambda at the end
+    }
 
     // filter bank as the B operand of the transposed GEMM: B[k=g][n=j] = k_{16 nb + j}[tap 4 s + g]
     // (block nb read from the staged bank in red when it is used)
@@ -351,7 +392,125 @@ k_bwd_params(
             }
         }
     }
-    for (int y = wave; !LOADZA && y < Th; y += NW) {
+    if constexpr (MIXED) {
+        // transposed filter bank of a = K e as the B operand, converted once into
+        // LDS, [nb][s][lane]: lane (g, j) holds taps 16 s + 4 g + i (i = 0..3) of
+        // filter 16 nb + j
+        MV *smb = reinterpret_cast<MV *>(lds + L.mb_off);
+        for (int q = tid; q < NMB * KSH * 64; q += THREADS) {
+            const int ql = q & 63, qs = (q >> 6) % KSH, qn = (q >> 6) / KSH;
+            const int qg = ql >> 4, qj = ql & 15;
+            floatx4 x;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int fi = 16 * qn + qj, t = 16 * qs + 4 * qg + i;
+                x[i] = (fi < Nk && t < KK) ? red[fi * KK + t] : 0.f;
+            }
+            smb[q] = MX::cvt4(x);
+        }
+        __syncthreads();
+        int offm[KSH][4];
+#pragma unroll
+        for (int s = 0; s < KSH; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = 16 * s + 4 * g + i;
+                offm[s][i] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
+            }
+        for (int y = wave; y < Th; y += NW) {
+            const int yi = ty0 + y;
+            if (yi >= H) break;
+#pragma unroll 1
+            for (int cb = 0; cb < NBW; ++cb) {
+                // A operands of K u (FP32, 4 taps per k-step) and of K e (scaled, 16
+                // taps per k-step) at pixel j of the block
+                const float *ubase = su + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
+                const float *ebase = se + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
+                float bu[KS1];
+#pragma unroll
+                for (int s = 0; s < KS1; ++s) bu[s] = ubase[-off1[s]];
+                MV ae[KSH];
+#pragma unroll
+                for (int s = 0; s < KSH; ++s) {
+                    floatx4 xe;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xe[i] = escale * ebase[-offm[s][i]];
+                    ae[s] = MX::cvt4(xe);
+                }
+                // A operands of the dK contraction: rows = taps 16 mt + j, k = the
+                // block's pixels 4 g + i: scaled ebar, and ubar as hi + lo
+                MV de[MB2], duh[MB2], dul[MB2];
+#pragma unroll
+                for (int mt = 0; mt < MB2; ++mt) {
+                    floatx4 xe, xu, xl;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int b2 = (y + 2 * R) * L.ldw + 16 * cb + 4 * g + i + 2 * R;
+                        xe[i] = tapok[mt] ? escale * se[b2 - offt[mt]] : 0.f;
+                        xu[i] = tapok[mt] ? su[b2 - offt[mt]] : 0.f;
+                    }
+                    de[mt] = MX::cvt4(xe);
+                    duh[mt] = MX::cvt4(xu);
+                    const floatx4 hi = MX::widen4(duh[mt]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xl[i] = xu[i] - hi[i];
+                    dul[mt] = MX::cvt4(xl);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NMB; ++nb) {
+                    floatx4 accz = floatx4{0.f, 0.f, 0.f, 0.f}, acca = floatx4{0.f, 0.f, 0.f, 0.f};
+                    float bf[KS1];
+                    load_bf(nb, bf);
+#pragma unroll
+                    for (int s = 0; s < KS1; ++s)
+                        accz = __builtin_amdgcn_mfma_f32_16x16x4f32(bu[s], bf[s], accz, 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < KSH; ++s) acca = MX::mfma(ae[s], smb[(nb * KSH + s) * 64 + lane], acca);
+                    // influence, export (a unscaled), and the dK operands v, h (scaled) in place
+                    const float *row = stab + nb * 16 * L.t_pitch + j;
+                    const int fi = 16 * nb + j;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int x = 16 * cb + 4 * g + r, xi = tx0 + x;
+                        const bool valid = xi < W;
+                        const float z = accz[r], a = acca[r];
+                        float ph, dph;
+                        rbf_phi_dphi_horner(z, row, rb, ph, dph);
+                        if (valid && fi < Nk) {
+                            const size_t pix = img * plane + (size_t)yi * W + xi;
+                            io.za[za_index(pix, Nk, fi)] = z;
+                            io.za[za_index(pix, Nk, fi) + 4] = a * einv;
+                        }
+                        accz[r] = valid ? ph : 0.f;
+                        acca[r] = valid ? dph * a : 0.f;
+                    }
+                    const MV vb = MX::cvt4(accz), hb = MX::cvt4(acca);
+#pragma unroll
+                    for (int mt = 0; mt < MB2; ++mt) {
+                        dkt[mt][nb] = MX::mfma(de[mt], vb, dkt[mt][nb]);
+                        dkt[mt][nb] = MX::mfma(duh[mt], hb, dkt[mt][nb]);
+                        dkt[mt][nb] = MX::mfma(dul[mt], hb, dkt[mt][nb]);
+                    }
+                    if (G::VTAP) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int b2 = (y + 2 * R) * L.ldw + 16 * cb + 4 * g + r + 2 * R;
+                            const float ev = escale * se[b2 - offv], uvv = su[b2 - offv];
+                            acc48[nb] = fmaf(accz[r], ev, fmaf(acca[r], uvv, acc48[nb]));
+                        }
+                    }
+                }
+            }
+        }
+        // back to the gradient's own scale
+#pragma unroll
+        for (int nb = 0; nb < NMB; ++nb) {
+            acc48[nb] *= einv;
+#pragma unroll
+            for (int mt = 0; mt < MB2; ++mt) dkt[mt][nb] *= einv;
+        }
+    }
+    for (int y = wave; !LOADZA && !MIXED && y < Th; y += NW) {
         const int yi = ty0 + y;
         if (yi >= H) break;
 #pragma unroll 1
@@ -641,43 +800,51 @@ BwdGeom bwd_geom(int N, int H, int W, int th)
     return gm;
 }
 
+// The k_bwd_params instance for a filter size, filter-block count, variant
+// (loadza: z and a loaded from the export; else computed) and operand precision.
+template <int KS, int NMB>
+static const void *bp_kernel_t(bool loadza, int prec)
+{
+    if (loadza) return (const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, true, PREC_F32>;
+    if (KS == 7 && prec == PREC_BF16) return (const void *)k_bwd_params<7, NMB, BP_NBW, BP_NW, false, PREC_BF16>;
+    if (KS == 7 && prec == PREC_F16) return (const void *)k_bwd_params<7, NMB, BP_NBW, BP_NW, false, PREC_F16>;
+    return (const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, false, PREC_F32>;
+}
+
+static const void *bp_kernel(int ks, int nmb, bool loadza, int prec)
+{
+    if (ks == 7) return nmb == 2 ? bp_kernel_t<7, 2>(loadza, prec) : bp_kernel_t<7, 3>(loadza, prec);
+    return nmb == 2 ? bp_kernel_t<5, 2>(loadza, prec) : bp_kernel_t<5, 3>(loadza, prec);
+}
+
 // Workgroups per compute unit that the k_bwd_params tile plan assumes for one
-// variant (loadza: z and a loaded from the export; else computed) and tile
-// height th: the runtime's occupancy for its register footprint and the LDS of
-// that tile, but at least 2 (with a single resident workgroup the taller tiles
-// of a 1-per-CU plan ran slower than the 2-per-CU plan's); cached per thread.
-static int bp_per_cu(int ks, int nk, int nrbf, bool loadza, int th)
+// kernel instance (bp_kernel) and tile height th: the runtime's occupancy for
+// its register footprint and the LDS of that tile, but at least 2 (with a
+// single resident workgroup the taller tiles of a 1-per-CU plan ran slower
+// than the 2-per-CU plan's); cached per thread.
+static int bp_per_cu(int ks, int nk, int nrbf, bool loadza, int prec, int th)
 {
     const int nmb = (nk + 15) / 16 <= 2 ? 2 : 3;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    static thread_local int key[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
-    static thread_local int cached[2][BP_TH_MAX + 1];
-    const int v = loadza ? 1 : 0;
+    static thread_local int key[4][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1},
+                                         {-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};
+    static thread_local int cached[4][BP_TH_MAX + 1];
+    const int v = loadza ? 3 : (prec >= 0 && prec <= 2 ? prec : 0);
     th = th < BP_TH_MIN ? BP_TH_MIN : (th > BP_TH_MAX ? BP_TH_MAX : th);
-    if (!(key[v][0] == ks && key[v][1] == nmb && key[v][2] == nrbf && key[v][3] == dev)) {
+    if (!(key[v][0] == ks && key[v][1] == nmb && key[v][2] == nrbf && key[v][3] == dev && key[v][4] == prec)) {
         for (int i = 0; i <= BP_TH_MAX; ++i) cached[v][i] = 0;
         key[v][0] = ks;
         key[v][1] = nmb;
         key[v][2] = nrbf;
         key[v][3] = dev;
+        key[v][4] = prec;
     }
     if (cached[v][th] > 0) return cached[v][th];
-    const BpLds L = bp_lds(ks, nmb, th, 16 * BP_NBW, nrbf, BP_NW);
-    const void *k = nullptr;
-    if (ks == 7)
-        k = nmb == 2 ? (loadza ? (const void *)k_bwd_params<7, 2, BP_NBW, BP_NW, true>
-                               : (const void *)k_bwd_params<7, 2, BP_NBW, BP_NW, false>)
-                     : (loadza ? (const void *)k_bwd_params<7, 3, BP_NBW, BP_NW, true>
-                               : (const void *)k_bwd_params<7, 3, BP_NBW, BP_NW, false>);
-    else
-        k = nmb == 2 ? (loadza ? (const void *)k_bwd_params<5, 2, BP_NBW, BP_NW, true>
-                               : (const void *)k_bwd_params<5, 2, BP_NBW, BP_NW, false>)
-                     : (loadza ? (const void *)k_bwd_params<5, 3, BP_NBW, BP_NW, true>
-                               : (const void *)k_bwd_params<5, 3, BP_NBW, BP_NW, false>);
+    const BpLds L = bp_lds(ks, nmb, th, 16 * BP_NBW, nrbf, BP_NW, !loadza && prec != PREC_F32);
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * BP_NW, (size_t)L.total * sizeof(float)) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, bp_kernel(ks, nmb, loadza, prec), 64 * BP_NW,
+                                                     (size_t)L.total * sizeof(float)) != hipSuccess ||
         n < 2)
         n = 2;
     (void)hipGetLastError();
@@ -688,7 +855,7 @@ static int bp_per_cu(int ks, int nk, int nrbf, bool loadza, int th)
 // Tile height of k_bwd_params: with p(th) workgroups resident per compute unit,
 // n tiles run in ceil(n / (p CUs)) rounds of th rows of BP_NBW blocks each (plus
 // a fixed cost of ~4 blocks).
-int bwd_tile_h(int N, int H, int W, int ks, int nk, int nrbf, bool loadza)
+int bwd_tile_h(int N, int H, int W, int ks, int nk, int nrbf, bool loadza, int prec)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -697,7 +864,7 @@ int bwd_tile_h(int N, int H, int W, int ks, int nk, int nrbf, bool loadza)
     int best_th = BP_TH_MIN;
     double best = 0.0;
     for (int th = BP_TH_MIN; th <= BP_TH_MAX; ++th) {
-        const long slots = (long)bp_per_cu(ks, nk, nrbf, loadza, th) * cus;
+        const long slots = (long)bp_per_cu(ks, nk, nrbf, loadza, prec, th) * cus;
         const long tiles = (long)N * ((H + th - 1) / th) * ((W + 16 * BP_NBW - 1) / (16 * BP_NBW));
         const long rounds = (tiles + slots - 1) / slots;
         const double cost = (double)rounds * (th * BP_NBW + 4) + 1e-6 * th;
@@ -750,45 +917,50 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s,
     return w;
 }
 
-template <int KS, int NMB, bool LOADZA>
+template <int KS, int NMB, bool LOADZA, int PREC>
 hipError_t launch_bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, int W, const float *filt,
                              int Nk, const float *rbfw, const RbfGrid &grid, const float *lam,
                              hipStream_t stream)
 {
-    BpLds L = bp_lds(KS, NMB, gm.th, 16 * BP_NBW, grid.nrbf, BP_NW);
+    BpLds L = bp_lds(KS, NMB, gm.th, 16 * BP_NBW, grid.nrbf, BP_NW, PREC != PREC_F32);
     size_t lds_bytes = (size_t)L.total * sizeof(float);
-    raise_lds_limit((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA>);
+    raise_lds_limit((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA, PREC>);
     const int per_img = gm.tiles_x * gm.tiles_y;
     FusedRbf rb = make_fused_rbf(grid);
-    hipLaunchKernelGGL((k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA>), dim3(gm.tiles), dim3(64 * BP_NW),
-                       lds_bytes, stream, io, H, W, gm.th, gm.tiles_x, per_img, filt, Nk, rbfw,
-                       grid.nrbf, rb, lam);
+    hipLaunchKernelGGL((k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA, PREC>), dim3(gm.tiles),
+                       dim3(64 * BP_NW), lds_bytes, stream, io, H, W, gm.th, gm.tiles_x, per_img, filt, Nk,
+                       rbfw, grid.nrbf, rb, lam);
     return hipGetLastError();
 }
 
 template <int KS, int NMB>
-hipError_t launch_bwd_params_mode(bool loadza, const BwdParamsIO &io, const BwdGeom &gm, int H, int W,
-                                  const float *filt, int Nk, const float *rbfw, const RbfGrid &grid,
-                                  const float *lam, hipStream_t stream)
+hipError_t launch_bwd_params_mode(bool loadza, int prec, const BwdParamsIO &io, const BwdGeom &gm, int H,
+                                  int W, const float *filt, int Nk, const float *rbfw,
+                                  const RbfGrid &grid, const float *lam, hipStream_t stream)
 {
-    return loadza ? launch_bwd_params<KS, NMB, true>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
-                  : launch_bwd_params<KS, NMB, false>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+    if (loadza) return launch_bwd_params<KS, NMB, true, PREC_F32>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+    if (KS == 7 && prec == PREC_BF16)
+        return launch_bwd_params<7, NMB, false, PREC_BF16>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+    if (KS == 7 && prec == PREC_F16)
+        return launch_bwd_params<7, NMB, false, PREC_F16>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+    return launch_bwd_params<KS, NMB, false, PREC_F32>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
 }
 
 // Parameter-gradient partials of one stage.  loadza: z = K u and a = K e come
 // from the input-gradient kernel's export (FP32 path); otherwise they are
-// computed here and exported for k_bwd_dw.
-hipError_t bwd_params(bool loadza, const BwdParamsIO &io, const BwdGeom &gm, int H, int W, int ks,
-                      const float *filt, int Nk, const float *rbfw, const RbfGrid &grid,
+// computed here, with the operand precision prec, and exported for k_bwd_dw.
+hipError_t bwd_params(bool loadza, int prec, const BwdParamsIO &io, const BwdGeom &gm, int H, int W,
+                      int ks, const float *filt, int Nk, const float *rbfw, const RbfGrid &grid,
                       const float *lam, hipStream_t stream)
 {
     const int nmb = (Nk + 15) / 16;
+    if (prec != PREC_F32 && (ks != 7 || loadza)) return hipErrorInvalidValue;
     if (ks == 7)
-        return nmb <= 2 ? launch_bwd_params_mode<7, 2>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
-                        : launch_bwd_params_mode<7, 3>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+        return nmb <= 2 ? launch_bwd_params_mode<7, 2>(loadza, prec, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params_mode<7, 3>(loadza, prec, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     if (ks == 5)
-        return nmb <= 2 ? launch_bwd_params_mode<5, 2>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
-                        : launch_bwd_params_mode<5, 3>(loadza, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
+        return nmb <= 2 ? launch_bwd_params_mode<5, 2>(loadza, prec, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
+                        : launch_bwd_params_mode<5, 3>(loadza, prec, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     return hipErrorInvalidValue;
 }
 
@@ -853,7 +1025,7 @@ hipError_t reduce_partials(const RedJob *jobs, int n, hipStream_t stream)
 bool bwd_lds_ok(const tnrd_model *m)
 {
     const int nmb = (m->Nk + 15) / 16 <= 2 ? 2 : 3;
-    BpLds L = bp_lds(m->ksize, nmb, BP_TH_MAX, 16 * BP_NBW, m->Nrbf, BP_NW);
+    BpLds L = bp_lds(m->ksize, nmb, BP_TH_MAX, 16 * BP_NBW, m->Nrbf, BP_NW, true);
     return (size_t)L.total * sizeof(float) <= 160 * 1024 && dw_wave_bytes(m->Nrbf) <= 160 * 1024 &&
            m->Nk <= 64;
 }
@@ -911,8 +1083,9 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep, slab);
     // the two variants of k_bwd_params hold different numbers of workgroups per
     // compute unit, so each gets its own tile height (gm: loading z and a)
-    BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, true));
-    const BwdGeom gm_own = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, false));
+    BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, true, TNRD_PREC_FP32));
+    const BwdGeom gm_own =
+        bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, false, oo.prec));
     const size_t img = gm.img;
     if (oo.validate) {
         st = run_domain_check(f, img, (int *)ws, stream);
@@ -1001,7 +1174,8 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
                 if (fused_stage_input_grad(ia, stream) != hipSuccess) return TNRD_ERR_HIP;
             }
             const BwdGeom &gp = loadza ? gm : gm_own;
-            if (bwd_params(loadza, io, gp, H, W, m->ksize, filt, m->Nk, rbfw, ia.grid, lam, stream) !=
+            if (bwd_params(loadza, loadza ? TNRD_PREC_FP32 : oo.prec, io, gp, H, W, m->ksize, filt, m->Nk,
+                           rbfw, ia.grid, lam, stream) !=
                 hipSuccess)
                 return TNRD_ERR_HIP;
             if (bwd_dw(w.za, gm, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)

@@ -38,6 +38,14 @@ template <> struct Mix<PREC_BF16> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
     }
+    // the four values of an operand back in FP32 (exact)
+    static __device__ __forceinline__ floatx4 widen4(V v)
+    {
+        floatx4 r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = __builtin_bit_cast(float, (int)((unsigned)(unsigned short)v[i] << 16));
+        return r;
+    }
 };
 template <> struct Mix<PREC_F16> {
     typedef half4v V;
@@ -50,12 +58,17 @@ template <> struct Mix<PREC_F16> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ floatx4 widen4(V v)
+    {
+        return floatx4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    }
 };
 template <> struct Mix<PREC_F32> {  // placeholder so templates instantiate; never used
     typedef short4v V;
     static __device__ __forceinline__ short cvt(float) { return 0; }
     static __device__ __forceinline__ V cvt4(floatx4) { return V{0, 0, 0, 0}; }
     static __device__ __forceinline__ floatx4 mfma(V, V, floatx4 c) { return c; }
+    static __device__ __forceinline__ floatx4 widen4(V) { return floatx4{0.f, 0.f, 0.f, 0.f}; }
 };
 
 constexpr int RBF_WIN = 5;                // Horner window half-width (11 centres)
