@@ -12,7 +12,9 @@
 //   g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)                  (transposed eq. derv1-1)
 //
 // Three kernels per stage, then one deterministic reduction:
-//   k_fused_stage<.., MODE_BWD_INPUT>  g_{t-1} (tnrd_fused_tile.hpp); in FP32 it
+//   k_fused_stage<.., MODE_BWD_INPUT>  the force sum_i K_i^T(phi_i'(z_i) a_i) of
+//                  each tile's own pixels into its slab (tnrd_fused_tile.hpp), then
+//                  k_grad_finish forms g_{t-1} from the slabs; in FP32 the first
 //                  also stores z and a of every pixel (za_index layout)
 //   k_bwd_params   dK and dl partial sums per tile, from the stored z, a (FP32),
 //                  or computing and storing them itself (BF16/FP16, and the first
@@ -885,13 +887,14 @@ struct BwdWs {
     float *prep_b;  // prepared blocks of the input-gradient stages (d phi / ds tables)
     float *prep_f;  // prepared blocks of the recomputed forward stages (phi tables)
     float *slab[2]; // exchange buffers of the recomputed forward stages
+    float *slab_b;  // the input-gradient kernel's slabs
     size_t bytes;
 };
 
 // prep: floats of T stages' prepared blocks (0: the kernels build them);
-// slab: floats of one set of the forward's slabs
+// slab: floats of one set of the forward's slabs; slab_b: of the input-gradient kernel's
 BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s, size_t prep,
-                    size_t slab)
+                    size_t slab, size_t slab_b)
 {
     BwdGeom gm = bwd_geom(N, H, W, BP_TH_MIN);  // the most tiles any launch uses
     const size_t kk = (size_t)m->ksize * m->ksize;
@@ -913,6 +916,7 @@ BwdWs bwd_ws_layout(char *base, int N, int H, int W, const tnrd_model *m, int s,
     w.prep_f = prep && s > 1 ? take(prep) : nullptr;
     w.slab[0] = s > 1 ? take(slab) : nullptr;
     w.slab[1] = s > 1 ? take(slab) : nullptr;
+    w.slab_b = take(slab_b);
     w.bytes = off;
     return w;
 }
@@ -1032,13 +1036,21 @@ bool bwd_lds_ok(const tnrd_model *m)
 
 }  // namespace
 
+// Floats of the input-gradient kernel's slabs (its own tiling, automatic tiles).
+size_t bwd_slab_floats(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int window)
+{
+    const bool poly = o.rbf_window < 0 && poly_form_ok(make_grid(m, window), 1);
+    return fused_slab_floats(m->ksize, m->Nk, m->Nrbf, N, H, W, 0, 0, 0, poly, MODE_BWD_INPUT);
+}
+
 size_t backward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int window)
 {
     if (!fused_supported(m->ksize, m->Nk, m->Nrbf, window, o.prec) || !bwd_lds_ok(m)) return 0;
     const int s = o.recompute_every < 1 ? 1 : o.recompute_every;
     return bwd_ws_layout(nullptr, N, H, W, m, s,
                          prep_region_floats(m, o, TNRD_IMPL_FUSED, window, m->T),
-                         slab_region_floats(N, H, W, m, o, TNRD_IMPL_FUSED, window)).bytes;
+                         slab_region_floats(N, H, W, m, o, TNRD_IMPL_FUSED, window),
+                         bwd_slab_floats(N, H, W, m, o, window)).bytes;
 }
 
 }  // namespace tnrd
@@ -1068,7 +1080,8 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     const int s = oo.recompute_every < 1 ? 1 : oo.recompute_every;
     const size_t prep = prep_region_floats(m, oo, TNRD_IMPL_FUSED, window, T);
     const size_t slab = slab_region_floats(N, H, W, m, oo, TNRD_IMPL_FUSED, window);
-    const size_t need = bwd_ws_layout(nullptr, N, H, W, m, s, prep, slab).bytes;
+    const size_t slab_b = bwd_slab_floats(N, H, W, m, oo, window);
+    const size_t need = bwd_ws_layout(nullptr, N, H, W, m, s, prep, slab, slab_b).bytes;
     if (N > 0 && (!ws || ws_bytes < need)) return TNRD_ERR_WORKSPACE;
     hipStream_t stream = (hipStream_t)stream_;
     const size_t kk = (size_t)m->ksize * m->ksize;
@@ -1080,7 +1093,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             return TNRD_ERR_HIP;
         return TNRD_OK;
     }
-    BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep, slab);
+    BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep, slab, slab_b);
     // the two variants of k_bwd_params hold different numbers of workgroups per
     // compute unit, so each gets its own tile height (gm: loading z and a)
     BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, true, TNRD_PREC_FP32));
@@ -1162,16 +1175,23 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             const bool loadza = need_g && oo.prec == TNRD_PREC_FP32 && (long long)H * W <= INT_MAX;
             float *g_next = (t == 1 && grad_u0) ? grad_u0 : w.g[ping];
             if (need_g) {
+                // the input-gradient kernel leaves the force of e in its slabs; the
+                // finisher forms g_{t-1} from them
                 ia.u_prev = ut[t - 1];
                 ia.u_cur = ut[t];
                 ia.g_cur = g_cur;
-                ia.u_next = g_next;
+                ia.u_next = nullptr;
+                ia.x_out = w.slab_b;
                 ia.filt = filt;
                 ia.rbfw = rbfw;
                 ia.lam = lam;
                 ia.za = loadza ? w.za : nullptr;
                 ia.prep = use_prep ? w.prep_b + (size_t)ts * prep_sf : nullptr;
                 if (fused_stage_input_grad(ia, stream) != hipSuccess) return TNRD_ERR_HIP;
+                StageArgs fa = ia;
+                fa.x_prev = w.slab_b;
+                fa.u_next = g_next;
+                if (fused_grad_finish(fa, stream) != hipSuccess) return TNRD_ERR_HIP;
             }
             const BwdGeom &gp = loadza ? gm : gm_own;
             if (bwd_params(loadza, loadza ? TNRD_PREC_FP32 : oo.prec, io, gp, H, W, m->ksize, filt, m->Nk,

@@ -125,4 +125,28 @@ __device__ __forceinline__ float reaction_step(int react, float u_prev, float x,
     return prox(u_prev - x, f, lam);
 }
 
+// Derivative of the reaction step in ut_t written with its output u_t (prox:
+// y = u^2 / ((1+2l) u^2 + 2 l f^2), the closed form of eq. derv2 by the prox's
+// optimality condition; projected: 1 where u_t > c, else 0; quadratic: 1).
+__device__ __forceinline__ float react_dut(int react, float u_cur, float f, float lam, float c)
+{
+    if (react == 1) return u_cur > c ? 1.f : 0.f;
+    if (react == 2) return 1.f;
+    const float u2 = u_cur * u_cur;
+    return u2 / fmaf(1.f + 2.f * lam, u2, 2.f * lam * f * f);
+}
+
+// dl/du_{t-1} of a stage from g = dl/du_t and the diffusion force x = sum_i K_i^T
+// (phi_i'(z_i) a_i) of e = y g (transposed eq. derv1-1): g_{t-1} = e - x, and the
+// projected reaction adds -(d psi/du)(u_{t-1}) e, the quadratic one -l e.
+__device__ __forceinline__ float grad_step(int react, float u_prev, float u_cur, float f, float g, float x,
+                                           float lam, float c)
+{
+    const float e = react_dut(react, u_cur, f, lam, c) * g;
+    float gv = e - x;
+    if (react == 1) gv -= proj_psi_du(u_prev, f, lam) * e;
+    else if (react == 2) gv -= lam * e;
+    return gv;
+}
+
 }  // namespace tnrd

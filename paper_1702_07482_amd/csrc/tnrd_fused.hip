@@ -142,22 +142,20 @@ struct TilePlan {
 // is taken as given (clamped to the image).  Otherwise the tile minimises the
 // modelled time: the kernel holds one workgroup per compute unit (its LDS
 // footprint), so a launch of n tiles runs in ceil(n / CUs) rounds, each as
-// long as one tile.  A tile's source rows (forward: its own Th rows;
-// input-gradient mode: Th + 2R E rows) go to its waves in rounds, so a wave
-// runs ceil(rows / waves) rows of nb 16-pixel blocks, plus a fixed cost
-// (prologue, output passes) worth about 2 such blocks.  Among tiles of equal
-// modelled time the one with the fewest rows wins (its output passes and
-// prologue are the shortest), then the one with fewer tiles.  Tile widths are
-// those whose source rows fill their blocks exactly (forward 16 nb,
-// input-gradient mode 16 nb - 2R).  The forward's tiles are at least 2R on
-// each side, so a padded position lies in the rings of at most two tiles per axis.
+// long as one tile.  A tile's Th rows (every mode works on the tile's own
+// pixels) go to its waves in rounds, so a wave runs ceil(rows / waves) rows of
+// nb 16-pixel blocks, plus a fixed cost (prologue, output passes) worth about
+// 2 such blocks.  Among tiles of equal modelled time the one with the fewest
+// rows wins (its output passes and prologue are the shortest), then the one
+// with fewer tiles.  Tile widths are those whose rows fill their blocks
+// exactly (16 nb).  Tiles are at least 2R on each side, so a padded position
+// lies in the rings of at most two tiles per axis.
 static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req_h, int req_w,
                           int waves, int mode, bool poly)
 {
     const int R = ks / 2;
     const bool xf = mode == MODE_FWD;
-    const int ring = xf ? 0 : 2 * R;   // source columns beyond the tile
-    const int tmin = xf ? 2 * R : R;   // smallest tile side
+    const int tmin = 2 * R;  // smallest tile side
     TilePlan p;
     p.nw = waves == 4 ? 4 : 8;
     p.ok = false;
@@ -172,7 +170,7 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
         p.th = req_h > 0 ? req_h : 32;
         if (p.tw > W) p.tw = W;
         if (p.th > H) p.th = H;
-        p.nb = (p.tw + ring + 15) / 16;
+        p.nb = (p.tw + 15) / 16;
         if (p.nb < 2) p.nb = 2;
         p.rbfm = p.nb <= 4 ? form(p.th, p.tw, p.nb) : -1;
         p.ok = p.nb <= 4 && p.th >= tmin && p.tw >= tmin && p.rbfm >= 0;
@@ -186,9 +184,9 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
     // exponentials cost far more than a slightly worse tile)
     bool poly_fits = false;
     for (int nb = 2; nb <= 4 && poly; ++nb)
-        poly_fits = poly_fits || form(th_lo > H ? H : th_lo, 16 * nb - ring > W ? W : 16 * nb - ring, nb) == RBF_POLY;
+        poly_fits = poly_fits || form(th_lo > H ? H : th_lo, 16 * nb > W ? W : 16 * nb, nb) == RBF_POLY;
     for (int nb = 2; nb <= 4; ++nb) {
-        int tw = 16 * nb - ring;
+        int tw = 16 * nb;
         if (tw > W) tw = W;
         for (int th = th_lo; th <= th_hi; ++th) {
             const int t = th > H ? H : th;
@@ -199,7 +197,7 @@ static TilePlan plan_tile(int ks, int nk, int nrbf, int N, int H, int W, int req
             // per wave: ceil(rows / waves) rows of nb blocks (the rows go to the
             // waves in rounds); a block of the Gaussian form costs about 1.3 blocks
             // of the polynomial form
-            const int rows = (t < H ? t : H) + ring;
+            const int rows = t < H ? t : H;
             const double blk = (rbfm == RBF_HORNER ? 1.3 : 1.0) * ((rows + p.nw - 1) / p.nw) * nb;
             const double cost = (double)rounds * (blk + 2) + 1e-4 * rows * nb + 1e-9 * (double)tiles;
             if (!p.ok || cost < best) {
@@ -293,10 +291,19 @@ hipError_t fused_finish(const StageArgs &s, hipStream_t stream)
     return fused_launch_final(s, p.th, p.tw, stream);
 }
 
-size_t fused_slab_floats(int ks, int nk, int nrbf, int N, int H, int W, int tile_h, int tile_w,
-                         int waves, bool poly)
+hipError_t fused_grad_finish(const StageArgs &s, hipStream_t stream)
 {
-    const TilePlan p = plan_tile_cached(ks, nk, nrbf, N, H, W, tile_h, tile_w, waves, MODE_FWD, poly);
+    const bool poly = s.poly && poly_form_ok(s.grid, 1);
+    const TilePlan p = plan_tile_cached(s.ks, s.Nk, s.grid.nrbf, s.N, s.H, s.W, s.tile_h, s.tile_w,
+                                        s.waves, MODE_BWD_INPUT, poly);
+    if (!p.ok) return hipErrorInvalidValue;
+    return fused_launch_grad_finish(s, p.th, p.tw, stream);
+}
+
+size_t fused_slab_floats(int ks, int nk, int nrbf, int N, int H, int W, int tile_h, int tile_w,
+                         int waves, bool poly, int mode)
+{
+    const TilePlan p = plan_tile_cached(ks, nk, nrbf, N, H, W, tile_h, tile_w, waves, mode, poly);
     if (!p.ok) return 0;
     const int R = ks / 2;
     const size_t tiles = (size_t)N * ((H + p.th - 1) / p.th) * ((W + p.tw - 1) / p.tw);

@@ -26,4 +26,11 @@ hipError_t fused_launch_bwd(const StageArgs &s, int th, int tw, int nb, int nw, 
     return hipErrorInvalidValue;
 }
 
+hipError_t fused_launch_grad_finish(const StageArgs &s, int th, int tw, hipStream_t stream)
+{
+    if (s.ks == 7) return launch_grad_finish<7>(s, th, tw, stream);
+    if (s.ks == 5) return launch_grad_finish<5>(s, th, tw, stream);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace tnrd

@@ -1,7 +1,7 @@
 // Device code of the fused stage kernel and its templated launchers; the
 // translation units tnrd_fused_{fwd,mixed,bwd,batched}.hip instantiate them.
 //
-// Fused stage: one kernel per stage computes, for a tile of output pixels,
+// Fused stage: one kernel per stage computes, for the own pixels of a tile,
 //
 //   z_i = K_i u        filter bank as an implicit GEMM on MFMA (v_mfma_f32_16x16x4_f32)
 //   v_i = phi_i(z_i)   influence on the vector ALUs: a piecewise degree-7
@@ -11,19 +11,23 @@
 //                      into LDS; or, for explicit RBF windows, the windowed
 //                      Gaussian sum evaluated with Horner's rule
 //   Y   = K^T-GEMM     [tap slots x pixels] = [tap slots x filters] . [filters x pixels] on MFMA
-//   x   = col2im(Y)    x-direction shift-add of the tap columns with DPP row shifts,
-//                      y-direction sum of the tap rows through LDS (plus the
-//                      reflected-border fold)
-//   u'  = prox(u - x)
+//   X   = col2im(Y)    x-direction shift-add of the tap columns with DPP row shifts,
+//                      y-direction sum of the tap rows through LDS
 //
-// without writing the Nk response maps anywhere but registers.
+// without writing the Nk response maps anywhere but registers.  K^T spreads a
+// tile's own pixels over the tile plus an R ring, so X is exported to the
+// tile's slab (exchange form, XTiles in tnrd_fused_common.hpp); the force at
+// a pixel is the sum of the slabs covering it and its border mirrors (the
+// exact adjoint's fold).  The forward applies stage t's reaction,
+// u_t = prox(u_{t-1} - x), in the prologue of stage t + 1 (k_react_final after
+// the last stage); the input-gradient mode's g_{t-1} = e - x is formed by
+// k_grad_finish.  No tile recomputes z or phi for a neighbour's pixels.
 //
 // Tile geometry (R = (KS-1)/2): the workgroup owns an output tile of Th x Tw
-// pixels.  K^T needs v on the tile plus an R ring ("E region", Eh x Ew), and
-// z on E needs u on the tile plus a 2R ring (the u tile staged in LDS).  Each
-// wave takes whole E rows; a row is cut into NB blocks of 16 pixels, the N
-// dimension of every MFMA.  Pixels of a block that fall outside the image (or
-// beyond Ew) carry v = 0.
+// pixels (Th, Tw >= 2R).  z on the tile needs u on the tile plus an R ring
+// (the u tile staged in LDS).  Each wave takes whole tile rows; a row is cut
+// into NB blocks of 16 pixels, the N dimension of every MFMA.  Pixels of a
+// block that fall outside the image (or beyond Tw) carry v = 0.
 //
 // GEMM layouts for v_mfma_f32_16x16x4_f32 (lane l, g = l / 16, j = l % 16):
 //   A operand  A[j][g]   (row j, k = g)
@@ -38,18 +42,16 @@
 //   lane group g, tap row a = 4 (R' % HB) + g (HB = ceil(KS / 4)): every lane
 //   group of a register holds the same b for 16 consecutive pixels.
 //
-// col2im: Y of tap (a, b) at source pixel (e, c) belongs to output (e - a, c - b)
-// in tile coordinates.  Shifting by b along the 16 pixels of a block is one DPP
-// row shift per register (row_shl b inside the block, row_shr 16 - b for the
-// part that lands in the block to the left), so the sum over b stays in
-// registers and each E row e leaves its tap-row partials sum_b Y_(a,b)[qx + b] in a
-// ring of LDS rows indexed by the output row they feed, P[e - a][a][qx + 2R]; every
-// entry is written once, by the wave that owns row e (no atomics, deterministic).
-// Output row y is X(y, x) = sum_a P[y][a][x + 2R]: KS words of one ring slot.
-//
-// The border fold (K^T is the exact adjoint of "reflect, then convolve"): an
-// output pixel within R of the image border also receives X at its mirror
-// position in the padded ring, which the tile's P already holds.
+// col2im: Y of tap (a, b) at source pixel (e, c) belongs to padded position
+// (e - a + R, c - b + R) in tile coordinates, "ring row" e - a and "ring column"
+// c - b.  Shifting by b along the 16 pixels of a block is one DPP row shift per
+// register (row_shl b inside the block, row_shr 16 - b for the part that lands
+// in the block to the left), so the sum over b stays in registers and each row
+// e leaves its tap-row partials sum_b Y_(a,b)[qx + b] in a ring of LDS rows
+// indexed by the ring row they feed, P[e - a][a][qx + 2R]; every entry is
+// written once, by the wave that owns row e (no atomics, deterministic).  Ring
+// row o is complete once rows o .. o + 2R are done; its slab row o + 2R is
+// X(o, x) = sum_a P[o][a][x + 2R] over the tap rows written by rows of the tile.
 #pragma once
 
 #include "tnrd_device.hpp"
@@ -82,9 +84,9 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
 {
     const int R = ks / 2;
     FusedLds l;
-    // u tile origin: R before the tile (forward: z on the tile's own pixels),
-    // 2R (input-gradient mode: z on the tile plus an R ring)
-    const int uo = mode == MODE_FWD ? R : 2 * R;
+    // u (and e) tile origin: R before the tile (z on the tile's own pixels)
+    const int uo = R;
+    (void)mode;
     const int luh = th + 2 * uo;
     l.ldw = tw + 2 * uo + 1;
     l.u_off = 0;
@@ -118,7 +120,6 @@ __device__ __forceinline__ void fused_tile(
     const FusedRbf &rb, const float *__restrict__ lam_t, float *lds)
 {
     constexpr bool BWD = MODE == MODE_BWD_INPUT;
-    constexpr bool XF = MODE == MODE_FWD;  // forward: exchange form (own pixels, slabs)
     constexpr bool POLY = RBFM == RBF_POLY;
     // Polynomial form: the coefficient table comes ready-made from io.prep
     // (k_prep_stage); with FP32 operands the per-lane filter operands too
@@ -133,19 +134,11 @@ __device__ __forceinline__ void fused_tile(
     constexpr int KS2 = 4 * NMB;  // GEMM2 k-steps (4 filters each)
     constexpr int THREADS = 64 * NW;
     constexpr int RING = 2 * NW + 2 * R + FUSED_MERGE;
-    static_assert(FUSED_MERGE <= R, "the output-pass size PF assumes FUSED_MERGE <= R");
     constexpr int PW = 16 * NB + 2 * R;  // P row pitch (fused_lds().pw)
-    // output values a thread produces per round, at most: NW + R + FUSED_MERGE rows (a
-    // merged last round of a tile at the bottom border) of a tile at most 16 NB - 2R wide
-    constexpr int PF = ((NW + R + FUSED_MERGE) * (16 * NB - 2 * R) + THREADS - 1) / THREADS;
-    // forward: slab values a thread exports per round, at most: NW + 2R + FUSED_MERGE ring
-    // rows (a merged last round) of at most 16 NB + 2R columns
-    constexpr int PX = ((NW + 2 * R + FUSED_MERGE) * (16 * NB + 2 * R) + THREADS - 1) / THREADS;
-    // Source region whose responses the tile computes: forward, its own pixels
-    // (origin offset 0); input-gradient mode, the tile plus an R ring (E region,
-    // origin offset -R).  The u tile starts UO = R before the source region.
-    constexpr int SO = XF ? 0 : -R;
-    constexpr int UO = R - SO;
+    // Every mode computes responses on the tile's own pixels (its source region)
+    // and exports the force they spread over the tile plus an R ring to its slab;
+    // the u (and e) tile starts UO = R before the tile.
+    constexpr int UO = R;
 
     const FusedLds L = fused_lds(KS, NMB, NB, Th, Tw, Nrbf, NW, MODE, RBFM);
     float *su = lds + L.u_off;
@@ -157,7 +150,7 @@ __device__ __forceinline__ void fused_tile(
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
 
-    const int Eh = Th - 2 * SO, Ew = Tw - 2 * SO;  // source region
+    const int Eh = Th, Ew = Tw;  // source region
     const int luh = Th + 2 * UO, luw = Tw + 2 * UO;
 
     // ---- prologue: every global load of a thread is issued before the first
@@ -183,7 +176,6 @@ __device__ __forceinline__ void fused_tile(
     float emax = 0.f;  // largest |e| of the tile (input-gradient mode)
     if (BWD) {
         const float lam0 = lam_t[0];
-        const float c1 = 1.f + 2.f * lam0, c2 = 2.f * lam0;
         const float *ucn = io.u_cur;
         const float *gcn = io.g_cur;
         const float *fcn = f;
@@ -194,7 +186,7 @@ __device__ __forceinline__ void fused_tile(
             for (int k = 0; k < 4; ++k) {
                 int i = min(base + k * THREADS + tid, n - 1);
                 int ly = i / luw, lx = i - ly * luw;
-                int yy = reflect_clamp(ty0 - 2 * R + ly, H), xx = reflect_clamp(tx0 - 2 * R + lx, W);
+                int yy = reflect_clamp(ty0 - UO + ly, H), xx = reflect_clamp(tx0 - UO + lx, W);
                 size_t q = (size_t)yy * W + xx;
                 uu[k] = ucn[q];
                 ff[k] = fcn[q];
@@ -205,13 +197,7 @@ __device__ __forceinline__ void fused_tile(
                 int i = base + k * THREADS + tid;
                 if (i < n) {
                     int ly = i / luw, lx = i - ly * luw;
-                    float u2 = uu[k] * uu[k];
-                    // prox: y = du_t/d(ut_t); projected: 1 where ut_t > c (u_t > c), else 0;
-                    // quadratic data term: 1
-                    float y = io.react == 1   ? (uu[k] > io.proj_c ? 1.f : 0.f)
-                              : io.react == 2 ? 1.f
-                                              : u2 / fmaf(c1, u2, c2 * ff[k] * ff[k]);
-                    float ev = y * gg[k];
+                    const float ev = react_dut(io.react, uu[k], ff[k], lam0, io.proj_c) * gg[k];
                     se[ly * L.ldw + lx] = ev;
                     emax = fmaxf(emax, fabsf(ev));
                 }
@@ -248,7 +234,7 @@ __device__ __forceinline__ void fused_tile(
     // Forward with the previous stage's reaction pending: u_{t-1} =
     // reaction(u_{t-2}, force gathered from the slabs, f) at every position of
     // the tile (own pixels also written back to io.u_keep for later stages).
-    if (!(XF && io.pend)) {
+    if (MODE != MODE_FWD || !io.pend) {
         for (int c = wave; c * 64 < L.u_size; c += NW) {
             const int k = c * 64 + lane;
             const int ly = k / L.ldw, lx = k - ly * L.ldw;
@@ -436,7 +422,7 @@ __device__ __forceinline__ void fused_tile(
     // per-lane part of the polynomial table address: filter 16 mb + 4 g + r
     const int tab_g = 4 * g * POLY_TFP;
 
-    // GEMM1 of block (E row e, 16-pixel block cb): z = K u (and a = K e in
+    // GEMM1 of block (row e, 16-pixel block cb): z = K u (and a = K e in
     // input-gradient mode).  The B operands are read first (gemm1_load), the
     // MFMAs run in k-step ranges (gemm1_steps) spread over the next block's work.
     constexpr int K1 = MIXED ? KSH : KS1;  // GEMM1 k-steps
@@ -580,20 +566,20 @@ __device__ __forceinline__ void fused_tile(
     // the x-direction col2im.  xa[h] enters holding block cb-1's partial X (tap
     // rows a = 4h + g) and leaves holding block cb's; block cb-1 is complete
     // then and goes to the P ring slot of output row e - a:
-    //   P[(e - a) mod RING][a][qx + 2R] = sum_b Y_(a,b)[qx + b]   (qx relative to the E row)
+    //   P[(e - a) mod RING][a][qx + 2R] = sum_b Y_(a,b)[qx + b]   (qx relative to the row)
     // The scheduling fences split the work into NMB + 1 segments; in each, the
     // table reads of the next filter group and a third of the next GEMM1 are
     // in flight while the current group's influence and GEMM2 run.
     auto process = [&](int e, int cb, floatx4 *c1, const floatx4 *ca, float *xa, int en, int cbn,
                        floatx4 *n1, floatx4 *na) {
         const int c = 16 * cb + j;
-        const int xi = tx0 + SO + c;
-        const bool valid = (c < Ew) && (xi >= 0) && (xi < W);
-        // input-gradient mode with export: z and a of this lane's pixel if it is
-        // one of the tile's own (every image pixel is own to exactly one tile),
-        // stored before anything else of the block, when the fewest registers are live
-        if (BWD && io.za && c >= R && c < R + Tw && xi < W && e >= R && e < R + Th && ty0 - R + e < H) {
-            float *q = io.za + za_index((size_t)(ty0 - R + e) * W + xi, Nk, 4 * g);
+        const int xi = tx0 + c;
+        const bool valid = (c < Ew) && (xi < W);
+        // input-gradient mode with export: z and a of this lane's pixel (every image
+        // pixel is own to exactly one tile), stored before anything else of the
+        // block, when the fewest registers are live
+        if (BWD && io.za && valid) {
+            float *q = io.za + za_index((size_t)(ty0 + e) * W + xi, Nk, 4 * g);
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb)
                 if (16 * mb + 4 * g < Nk) {
@@ -661,99 +647,25 @@ __device__ __forceinline__ void fused_tile(
         }
     };
 
-    // ---- gather X over the tap rows, fold the border ring, prox, store.
-    // Output row y sums the KS tap rows of its ring slot.  Near the image border
-    // the pixel also receives X at its mirror position (a ring slot of the same
-    // round), and tap rows written by E rows outside the image count as zero.
-    const float *fn = f;
-    float *uo = io.out;
-    const int y_lim = min(Th, H - ty0);
-    const int e_lo = max(0, -(ty0 + SO)), e_hi = min(Eh, H - (ty0 + SO));  // source rows in the image
-    // the thread's p-th output of a round: row y0 + pdy[p], column pdx[p]
-    int pdy[PF], pdx[PF];
-#pragma unroll
-    for (int p = 0; p < PF; ++p) {
-        const int i = tid + p * THREADS;
-        pdy[p] = i / Tw;
-        pdx[p] = i - pdy[p] * Tw;
-    }
+    const int e_lo = 0, e_hi = min(Eh, H - ty0);  // source rows in the image
     auto slot_of = [&](int qy) {  // ring slot of output row qy (-RING < qy)
         const int m = (qy + RING) % RING;
         return sp + m * KS * PW;
     };
-    auto produce = [&](int y0, int y1, const float *fpre) {
-#pragma unroll
-        for (int p = 0; p < PF; ++p) {
-            if (pdy[p] >= y1 - y0) break;
-            const int y = y0 + pdy[p], x = pdx[p];
-            const int yi = ty0 + y, xi = tx0 + x;
-            if (xi >= W) continue;
-            float xs = 0.f;
-            const bool fy = yi < R || yi >= H - R, fx = xi < R || xi >= W - R;
-            if (!(fy || fx)) {
-                // interior: every tap row of the slot comes from an E row inside the image
-                const float *b = slot_of(y) + x + 2 * R;
-#pragma unroll
-                for (int a = 0; a < KS; ++a) xs += b[a * PW];
-            } else {
-                int qy[2] = {y, 0}, qx[2] = {x, 0};
-                int nqy = 1, nqx = 1;
-                if (yi < R) qy[nqy++] = -yi - 1 - ty0;
-                else if (yi >= H - R) qy[nqy++] = 2 * H - 1 - yi - ty0;
-                if (xi < R) qx[nqx++] = -xi - 1 - tx0;
-                else if (xi >= W - R) qx[nqx++] = 2 * W - 1 - xi - tx0;
-                for (int iy = 0; iy < nqy; ++iy) {
-                    const float *srow = slot_of(qy[iy]);
-                    for (int ix = 0; ix < nqx; ++ix) {
-                        const float *b = srow + qx[ix] + 2 * R;
-#pragma unroll
-                        for (int a = 0; a < KS; ++a) {
-                            const int e = qy[iy] + a;  // the E row that wrote tap row a
-                            const float v = b[a * PW];
-                            xs += (e >= e_lo && e < e_hi) ? v : 0.f;
-                        }
-                    }
-                }
-            }
-            const size_t pix = (size_t)yi * W + xi;
-            if (BWD) {
-                // g_{t-1} = e - sum_i K_i^T (phi_i'(z_i) a_i)  (transposed eq. derv1-1);
-                // the projected reaction adds -(d psi/du)(u_{t-1}) e, the quadratic one -l e
-                const float ev = se[(y + 2 * R) * L.ldw + x + 2 * R];
-                float gv = ev - xs * einv;
-                if (io.react == 1)
-                    gv -= proj_psi_du(su[(y + 2 * R) * L.ldw + x + 2 * R], fn[pix], lam) * ev;
-                else if (io.react == 2)
-                    gv -= lam * ev;
-                uo[pix] = gv;
-            } else {
-                const float uv = su[(y + 2 * R) * L.ldw + x + 2 * R];
-                uo[pix] = reaction_step(io.react, uv, xs, fpre[p], lam, io.proj_c);
-            }
-        }
-    };
 
-    // ---- forward: export of completed ring rows to the tile's slab.  Ring row o
-    // (source row e feeds ring row e - a with its tap row a) is slab row o + 2R;
-    // slab column dx is P column dx.  Tap rows written by source rows outside
-    // [0, e_hi) count as zero.
+    // ---- export of completed ring rows to the tile's slab.  Ring row o (source
+    // row e feeds ring row e - a with its tap row a) is slab row o + 2R; slab
+    // column dx is P column dx.  Tap rows written by source rows outside
+    // [0, e_hi) count as zero.  The input-gradient mode's slab holds the force
+    // in the gradient's own scale (BF16/FP16: einv undoes the tile's e scale).
     const int sw = Tw + 2 * R;
     const int sw_own = min(Tw, W - tx0) + 2 * R;
-    int xdy[XF ? PX : 1], xdx[XF ? PX : 1];
-    if (XF) {
-#pragma unroll
-        for (int p = 0; p < PX; ++p) {
-            const int i = tid + p * THREADS;
-            xdy[p] = i / sw;
-            xdx[p] = i - xdy[p] * sw;
-        }
-    }
     auto export_rows = [&](int o0, int o1) {
         float *xo = io.x_out;
-#pragma unroll
-        for (int p = 0; p < PX; ++p) {
-            if (xdy[p] >= o1 - o0) break;
-            const int o = o0 + xdy[p], dx = xdx[p];
+        const int nx = (o1 - o0) * sw;
+        for (int i = tid; i < nx; i += THREADS) {
+            const int xdy = i / sw, xdx = i - xdy * sw;
+            const int o = o0 + xdy, dx = xdx;
             if (dx >= sw_own) continue;
             const float *b = slot_of(o) + dx;
             float xs = 0.f;
@@ -763,14 +675,14 @@ __device__ __forceinline__ void fused_tile(
                 const float v = b[a * PW];
                 xs += (e >= 0 && e < e_hi) ? v : 0.f;
             }
-            xo[(o + 2 * R) * sw + dx] = xs;
+            xo[(o + 2 * R) * sw + dx] = BWD ? xs * einv : xs;
         }
     };
 
-    // ---- main loop: rounds of NW E rows, one per wave.  After round k the
-    // partials of every E row below NW (k+1) are in the ring; the output rows
-    // they complete are produced after its barrier, before the next round's
-    // rows are stored.  A last round of at most FUSED_MERGE rows follows the
+    // ---- main loop: rounds of NW tile rows, one per wave.  After round k the
+    // partials of every row below NW (k+1) are in the ring; the ring rows they
+    // complete are exported after its barrier, before the next round's rows are
+    // stored.  A last round of at most FUSED_MERGE rows follows the
     // round before it without a barrier between them, instead of running as a
     // round of its own in which most waves wait.  The ring holds
     // 2 NW + 2R + FUSED_MERGE rows, so the rows written between two barriers
@@ -779,7 +691,6 @@ __device__ __forceinline__ void fused_tile(
     // current one.
     const int rounds = (e_hi + NW - 1) / NW;
     const bool merge = rounds >= 2 && e_hi - NW * (rounds - 1) <= FUSED_MERGE;
-    int y_done = 0;
     bool have = false;
     floatx4 c1[NMB], ca[NMB];
 #pragma unroll
@@ -787,22 +698,9 @@ __device__ __forceinline__ void fused_tile(
         c1[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
         ca[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    int o_done = -2 * R;  // forward: ring rows exported so far
+    int o_done = -2 * R;  // ring rows exported so far
     for (int k = 0; k < rounds; ++k) {
         const bool sync = !(merge && k == rounds - 2);
-        int y_end = e_hi <= NW * (k + 1) ? Th : max(0, NW * (k + 1) - 2 * R);
-        y_end = min(y_end, y_lim);
-        const int y0 = min(y_done, y_end);
-        // f of this round's outputs, loaded ahead of the round's compute
-        float fpre[PF];
-        if (!BWD && !XF) {
-#pragma unroll
-            for (int p = 0; p < PF; ++p) {
-                fpre[p] = 0.f;
-                if (sync && pdy[p] < y_end - y0 && tx0 + pdx[p] < W)
-                    fpre[p] = fn[(size_t)(ty0 + y0 + pdy[p]) * W + tx0 + pdx[p]];
-            }
-        }
         const int e = NW * k + wave;
         if (e >= e_lo && e < e_hi) {
             if (!have) gemm1(e, 0, c1, ca);
@@ -829,15 +727,10 @@ __device__ __forceinline__ void fused_tile(
         }
         if (!sync) continue;
         __syncthreads();
-        if (XF) {
-            // ring rows below every source row still to come are complete
-            const int o_end = e_hi <= NW * (k + 1) ? e_hi : NW * (k + 1) - 2 * R;
-            export_rows(o_done, o_end);
-            o_done = o_end;
-        } else {
-            produce(y0, y_end, fpre);
-            y_done = max(y_done, y_end);
-        }
+        // ring rows below every source row still to come are complete
+        const int o_end = e_hi <= NW * (k + 1) ? e_hi : NW * (k + 1) - 2 * R;
+        export_rows(o_done, o_end);
+        o_done = o_end;
     }
     __syncthreads();  // LDS is free for the workgroup's next tile
 }
@@ -856,16 +749,14 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     FusedIO ii = io;  // per-image pointers below; every other field as launched
     ii.u_prev = io.u_prev + img * plane;
     ii.f = io.f + img * plane;
-    ii.out = io.out + img * plane;
+    ii.out = io.out ? io.out + img * plane : nullptr;
     ii.u_cur = io.u_cur ? io.u_cur + img * plane : nullptr;
     ii.g_cur = io.g_cur ? io.g_cur + img * plane : nullptr;
     ii.za = io.za ? io.za + img * plane * za_stride(Nk) : nullptr;
-    if (MODE == MODE_FWD) {
-        const size_t sl = (size_t)io.xt.sl;
-        ii.x_out = io.x_out + ((size_t)img * tiles_per_img + trem) * sl;
-        ii.x_prev = io.x_prev ? io.x_prev + (size_t)img * tiles_per_img * sl : nullptr;
-        ii.u_keep = io.u_keep ? io.u_keep + img * plane : nullptr;
-    }
+    const size_t sl = (size_t)io.xt.sl;
+    ii.x_out = io.x_out + ((size_t)img * tiles_per_img + trem) * sl;
+    ii.x_prev = io.x_prev ? io.x_prev + (size_t)img * tiles_per_img * sl : nullptr;
+    ii.u_keep = io.u_keep ? io.u_keep + img * plane : nullptr;
     fused_tile<KS, NMB, NB, NW, MODE, PREC, RBFM>(ii, H, W, Th, Tw, ty * Th, tx * Tw, filt, Nk, rbfw,
                                                   Nrbf, rb, lam_t, lds);
 }
@@ -934,8 +825,11 @@ __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
     io.pend = t > 0;
     io.u_prev = t <= 1 ? im.f : batch_plane(im, a.T, t - 1);
     io.u_keep = t > 0 ? batch_plane(im, a.T, t) : nullptr;
-    io.x_prev = t > 0 ? im.xs[(t - 1) & 1] : nullptr;
-    io.x_out = im.xs[t & 1] + (size_t)it.tile * io.xt.sl;
+    // (selects, not an indexed load: an indexed member array would put the
+    // descriptor copy in scratch memory)
+    float *const xs_even = im.xs[0], *const xs_odd = im.xs[1];
+    io.x_prev = t > 0 ? ((t & 1) ? xs_even : xs_odd) : nullptr;
+    io.x_out = ((t & 1) ? xs_odd : xs_even) + (size_t)it.tile * io.xt.sl;
     io.lam_prev = md.lam + (t > 0 ? t - 1 : 0);
     io.out = nullptr;
     io.u_cur = nullptr;
@@ -963,7 +857,7 @@ __global__ void __launch_bounds__(256) k_batched_final(BatchArgs a)
     const int th = min(xt.Th, xt.H - y0), tw = min(xt.Tw, xt.W - x0);
     const int T = a.T;
     const float *up = T == 1 ? im.f : batch_plane(im, T, T - 1);
-    const float *xs = im.xs[(T - 1) & 1];
+    const float *xs = ((T - 1) & 1) ? im.xs[1] : im.xs[0];
     const float l = md.lam[T - 1];
     const int i = blockIdx.y * 256 + threadIdx.x;
     if (i < th * tw) {
@@ -994,19 +888,63 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     if (RBFM == RBF_POLY && !s.prep) return hipErrorInvalidValue;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
-    if (MODE == MODE_FWD) {
-        if (!s.x_out || (s.pend && (!s.x_prev || !s.u_keep || !s.lam_prev))) return hipErrorInvalidValue;
+    if (!s.x_out) return hipErrorInvalidValue;
+    io.x_out = s.x_out;
+    io.xt = make_xtiles(s.H, s.W, th, tw, KS / 2);
+    io.lam_prev = s.lam;
+    if (MODE == MODE_FWD && s.pend) {
+        if (!s.x_prev || !s.u_keep || !s.lam_prev) return hipErrorInvalidValue;
         io.x_prev = s.x_prev;
-        io.x_out = s.x_out;
         io.u_keep = s.u_keep;
-        io.lam_prev = s.pend ? s.lam_prev : s.lam;
-        io.pend = s.pend;
-        io.xt = make_xtiles(s.H, s.W, th, tw, KS / 2);
+        io.lam_prev = s.lam_prev;
+        io.pend = 1;
     }
     dim3 grid(tiles * s.N);
     hipLaunchKernelGGL((k_fused_stage<KS, NMB, NB, NW, MODE, PREC, RBFM>), grid, dim3(64 * NW),
                        lds_bytes, stream, io, s.H, s.W, th, tw, tiles_x, tiles, s.filt, s.Nk, s.rbfw,
                        s.grid.nrbf, rb, s.lam);
+    return hipGetLastError();
+}
+
+// Input gradient of a stage from the input-gradient kernel's slabs (tiling
+// (th, tw)): g_{t-1} = e - x - r e, e = y g_t, with y the reaction's derivative
+// in ut_t and r its explicit derivative in u_{t-1} (prox: 0; projected:
+// psi_u(u_{t-1}); quadratic: lambda), one pixel per thread as k_react_final.
+template <int R>
+__global__ void __launch_bounds__(256) k_grad_finish(const float *__restrict__ u_prev,
+                                                     const float *__restrict__ u_cur,
+                                                     const float *__restrict__ f,
+                                                     const float *__restrict__ g_cur,
+                                                     const float *__restrict__ xs, float *__restrict__ out,
+                                                     XTiles xt, int tiles_per_img,
+                                                     const float *__restrict__ lam, int react, float proj_c)
+{
+    const int img = blockIdx.x / tiles_per_img;
+    const int tile = blockIdx.x - img * tiles_per_img;
+    const int ty = tile / xt.nx, tx = tile - ty * xt.nx;
+    const int y0 = ty * xt.Th, x0 = tx * xt.Tw;
+    const int th = min(xt.Th, xt.H - y0), tw = min(xt.Tw, xt.W - x0);
+    const size_t plane = (size_t)xt.H * xt.W;
+    const float *xi = xs + (size_t)img * tiles_per_img * xt.sl;
+    const float l = lam[0];
+    const int i = blockIdx.y * 256 + threadIdx.x;
+    if (i < th * tw) {
+        const int y = y0 + i / tw, x = x0 + i % tw;
+        const size_t q = img * plane + (size_t)y * xt.W + x;
+        out[q] = grad_step(react, u_prev[q], u_cur[q], f[q], g_cur[q],
+                           pixel_force<R>(xi, xt, y, x), l, proj_c);
+    }
+}
+
+template <int KS>
+inline hipError_t launch_grad_finish(const StageArgs &s, int th, int tw, hipStream_t stream)
+{
+    if (!s.x_prev || !s.u_prev || !s.u_cur || !s.g_cur || !s.u_next) return hipErrorInvalidValue;
+    const XTiles xt = make_xtiles(s.H, s.W, th, tw, KS / 2);
+    const int tiles = xt.nx * xt.ny;
+    hipLaunchKernelGGL((k_grad_finish<KS / 2>), dim3(tiles * s.N, (th * tw + 255) / 256), dim3(256), 0,
+                       stream, s.u_prev, s.u_cur, s.f, s.g_cur, s.x_prev, s.u_next, xt, tiles, s.lam,
+                       s.react, s.proj_c);
     return hipGetLastError();
 }
 

@@ -134,7 +134,10 @@ hipError_t fused_finish(const StageArgs &s, hipStream_t stream);
 // Floats of one set of slabs of a fused forward with these arguments (0 when
 // the fused kernel cannot run them).
 size_t fused_slab_floats(int ks, int nk, int nrbf, int N, int H, int W, int tile_h, int tile_w,
-                         int waves, bool poly);
+                         int waves, bool poly, int mode = MODE_FWD);
+// The input gradient of a stage after fused_stage_input_grad wrote its slabs
+// (x_prev): u_next = g_{t-1} from u_prev = u_{t-1}, u_cur = u_t, g_cur = g_t, f, lam.
+hipError_t fused_grad_finish(const StageArgs &s, hipStream_t stream);
 hipError_t fused_stage_input_grad(const StageArgs &s, hipStream_t stream);
 bool fused_supported(int ks, int Nk, int nrbf, int window, int prec);
 bool fused_config_ok(int ks, int Nk, int nrbf, int H, int W, int tile_h, int tile_w, int waves,
@@ -150,6 +153,7 @@ hipError_t fused_launch_fwd_mixed(const StageArgs &s, int th, int tw, int nb, in
 hipError_t fused_launch_bwd(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
                             hipStream_t stream);
 hipError_t fused_launch_final(const StageArgs &s, int th, int tw, hipStream_t stream);
+hipError_t fused_launch_grad_finish(const StageArgs &s, int th, int tw, hipStream_t stream);
 hipError_t batched_launch_impl(const BatchArgs &a, int ks, int nb, int nw, int rbfm,
                                hipStream_t stream);
 
