@@ -51,6 +51,8 @@ typedef enum tnrd_status {
     TNRD_ERR_WORKSPACE = -3,   /* ws_bytes smaller than tnrd_workspace_bytes() */
     TNRD_ERR_HIP = -4,         /* a HIP runtime call or launch failed */
     TNRD_ERR_UNSUPPORTED = -5, /* valid but not built: ksize not in {3,5,7}, precision, ... */
+    TNRD_ERR_TIMEOUT = -7,     /* validate: a persistent batched launch gave up waiting for a
+                                  neighbour tile (its results are not valid) */
     TNRD_ERR_CAPACITY = -6     /* tnrd_forward_noalloc: the call needs more scratch than its
                                   fixed TNRD_NOALLOC_SCRATCH_BYTES */
 } tnrd_status;
@@ -119,6 +121,10 @@ typedef struct tnrd_opts {
     int32_t wg_waves;     /* fused kernel: wavefronts per workgroup, 4 or 8; 0 = automatic */
     int32_t use_graph;    /* tnrd_forward_batched: 1 (default) records the launch sequence in a HIP
                              graph once per batch signature and replays it; 0 launches directly */
+    int32_t persistent;   /* tnrd_forward_batched: 1 runs every stage of every image in one
+                             persistent launch (workgroups take (stage, tile) items in stage-major
+                             order and wait for the tile's neighbours to finish the stage before);
+                             0 (default) launches once per stage */
 } tnrd_opts;
 
 /* Fills `o` with the defaults (FP32, AUTO, automatic window, no checkpointing,
@@ -192,12 +198,20 @@ typedef struct tnrd_image {
 } tnrd_image;
 
 /* Batched forward over B images of different sizes and look numbers (per-L
- * models: the paper trains one model per noise level, Sec. 4.5).  Each stage
- * is one launch over the tiles of every image.  `imgs` and `models` are HOST
+ * models: the paper trains one model per noise level, Sec. 4.5).  With
+ * opts->persistent every stage of every tile runs in one persistent launch:
+ * workgroups take (stage, tile) items in stage-major order from an atomic
+ * counter and start an item once the tile's 3 x 3 neighbourhood has finished
+ * the stage before (per-tile flags, device-scope release/acquire).  A wait
+ * gives up after 2^21 polls or once its workgroup has run for its clock budget
+ * (2 s, more for batches of over 10^5 items) and then marks an abort flag, so
+ * a launch always ends; with opts->validate such a launch returns
+ * TNRD_ERR_TIMEOUT.  Otherwise (default) each stage is one launch over the
+ * tiles of every image.  `imgs` and `models` are HOST
  * arrays; the models must share T, Nk, ksize, Nrbf and the RBF grid; an image
  * uses the model whose L equals its own, else one with L == 0.  Workspace from
  * tnrd_batched_workspace_bytes.  With opts->use_graph (default) and a non-null
- * stream, the descriptor upload and the T launches are recorded once into a HIP
+ * stream, the descriptor upload and the launches are recorded once into a HIP
  * graph per (stream, workspace, batch signature: image pointers, sizes and
  * looks; every model field, parameter pointers, reaction and proj_c included;
  * tiles) and replayed on later calls.  Host resources of that path, the one

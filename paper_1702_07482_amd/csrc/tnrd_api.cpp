@@ -366,6 +366,7 @@ void tnrd_default_opts(tnrd_opts *o)
     o->recompute_every = 1;
     o->validate = 0;
     o->use_graph = 1;
+    o->persistent = 0;
 }
 
 int tnrd_num_checkpoints(int T, int recompute_every)
@@ -414,6 +415,7 @@ const char *tnrd_status_str(int status)
     case TNRD_ERR_WORKSPACE: return "workspace missing or too small";
     case TNRD_ERR_HIP: return "HIP runtime error";
     case TNRD_ERR_UNSUPPORTED: return "unsupported configuration";
+    case TNRD_ERR_TIMEOUT: return "a persistent batched launch gave up waiting (results not valid)";
     case TNRD_ERR_CAPACITY:
         return "problem larger than the fixed scratch of tnrd_forward_noalloc (TNRD_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";

@@ -27,7 +27,7 @@ struct BatchPlan {
     int ntiles;                  // items per stage
     int n_models;
     size_t prep_stage;           // floats per prepared stage block (0: none)
-    size_t off_imgs, off_models, off_items, off_tmp, off_prep, desc_bytes, total;
+    size_t off_imgs, off_models, off_items, off_tmp, off_prep, off_ctl, desc_bytes, total;
     std::vector<size_t> tmp_off; // per image, from the workspace base
     std::vector<size_t> xs_off;  // per image: its two slab regions, from the workspace base
     std::vector<size_t> xs_len;  // per image: floats of one slab region
@@ -111,6 +111,9 @@ int check_batch(int B, const tnrd_image *imgs, int n_models, const tnrd_model *m
                           : 0;
     plan.off_prep = off;
     off += al((size_t)n_models * m.T * plan.prep_stage * sizeof(float));
+    // persistent launch: [item counter][abort flag][stages finished per item]
+    plan.off_ctl = off;
+    off += al((size_t)(2 + plan.ntiles) * sizeof(int));
     plan.total = off;
     return TNRD_OK;
 }
@@ -154,8 +157,15 @@ void build_descriptors(int B, const tnrd_image *imgs, int n_models, const tnrd_m
     }
 }
 
+// Polls a persistent launch's wait makes before it gives up (about 1 s of polling)
+constexpr int PERSIST_SPIN_LIMIT = 1 << 21;
+// Seconds after its start at which a persistent workgroup's waits give up: 2 s,
+// or 20 us per item for batches of over 10^5 items (the whole forward runs at
+// well under 1 us per item)
+inline double persist_budget_s(int n_items) { return n_items > 100000 ? 2e-5 * n_items : 2.0; }
+
 BatchArgs make_args(const BatchPlan &plan, const tnrd_model &m, int window, int automatic_window,
-                    char *ws)
+                    int persistent, char *ws)
 {
     BatchArgs a;
     a.imgs = (const BatchImage *)(ws + plan.off_imgs);
@@ -172,6 +182,16 @@ BatchArgs make_args(const BatchPlan &plan, const tnrd_model &m, int window, int 
     a.poly = poly_form_ok(grid, automatic_window) && plan.prep_stage > 0;
     a.prep_stage = plan.prep_stage;
     a.n_models = plan.n_models;
+    a.persistent = persistent;
+    int *ctl = (int *)(ws + plan.off_ctl);
+    a.ctl.next = ctl;
+    a.ctl.abort_flag = ctl + 1;
+    a.ctl.flags = ctl + 2;
+    a.ctl.per_stage = plan.ntiles;
+    a.ctl.n_items = (m.T + 1) * plan.ntiles;
+    a.ctl.spin_limit = PERSIST_SPIN_LIMIT;
+    a.ctl.budget = 0;  // set in ticks of the device clock at launch
+    a.budget_s = persist_budget_s(a.ctl.n_items);
     return a;
 }
 
@@ -201,6 +221,7 @@ std::vector<unsigned long long> signature(int B, const tnrd_image *imgs, int n_m
     I(o.tile_w);
     I(o.wg_waves);
     I(o.rbf_window);
+    I(o.persistent);
     for (int b = 0; b < B; ++b) {
         P(imgs[b].f);
         P(imgs[b].u_out);
@@ -267,8 +288,18 @@ extern "C" int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models,
             if (st != TNRD_OK) return st;
         }
     }
-    const BatchArgs a = make_args(plan, m, window, oo.rbf_window < 0, wsb);
+    const BatchArgs a = make_args(plan, m, window, oo.rbf_window < 0, oo.persistent != 0, wsb);
     const bool graph = oo.use_graph != 0 && stream != nullptr;
+    // validate: a persistent launch whose waits gave up is reported (a direct
+    // launch only; graph replays are not checked)
+    auto check_abort = [&]() -> int {
+        if (!oo.validate || !a.persistent) return TNRD_OK;
+        int host = 0;
+        if (hipMemcpyAsync(&host, a.ctl.abort_flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return TNRD_ERR_HIP;
+        return host ? TNRD_ERR_TIMEOUT : TNRD_OK;
+    };
 
     if (!graph) {
         std::vector<unsigned char> host(plan.desc_bytes);
@@ -280,6 +311,8 @@ extern "C" int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models,
             return TNRD_ERR_HIP;
         // the pageable source must outlive the copy
         if (hipStreamSynchronize(stream) != hipSuccess) return TNRD_ERR_HIP;
+        st = check_abort();
+        if (st != TNRD_OK) return st;
     } else {
         std::lock_guard<std::mutex> lock(g_mu);
         std::vector<unsigned long long> sig = signature(B, imgs, n_models, models, oo, ws, ws_bytes);
@@ -308,6 +341,12 @@ extern "C" int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models,
                 batched_launch(a, m.ksize, plan.nw, stream) != hipSuccess) {
                 (void)hipHostFree(e.host_desc);
                 return TNRD_ERR_HIP;
+            }
+            st = check_abort();
+            if (st != TNRD_OK) {
+                (void)hipStreamSynchronize(stream);
+                (void)hipHostFree(e.host_desc);
+                return st;
             }
             hipGraph_t g = nullptr;
             if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {

@@ -810,12 +810,12 @@ __device__ __forceinline__ float *batch_plane(const BatchImage &im, int T, int t
     return ((T - t) & 1) == 0 ? im.u_out : im.u_tmp;
 }
 
+// Stage t (< T) of batch item k.
 template <int KS, int NMB, int NB, int NW, int RBFM>
-__global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
+__device__ __forceinline__ void batched_stage_item(const BatchArgs &a, int t, int k, float *lds)
 {
-    extern __shared__ float lds[];
     constexpr int KK = KS * KS, R = KS / 2;
-    const BatchItem it = a.items[blockIdx.x];
+    const BatchItem it = a.items[k];
     const BatchImage im = a.imgs[it.image];
     const int ty = it.tile / im.tiles_x, tx = it.tile - ty * im.tiles_x;
     const BatchModel md = a.models[im.model];
@@ -843,28 +843,102 @@ __global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
         md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb, md.lam + t, lds);
 }
 
-// The last stage's reaction of every image: u_T into u_out, one pixel per
-// thread; workgroup (b, c) covers pixels 256 c .. 256 c + 255 of item b.
+// The last stage's reaction at own pixel i of batch item k: u_T into u_out.
 template <int R>
-__global__ void __launch_bounds__(256) k_batched_final(BatchArgs a)
+__device__ __forceinline__ void batched_final_pixel(const BatchArgs &a, int k, int i)
 {
-    const BatchItem it = a.items[blockIdx.x];
+    const BatchItem it = a.items[k];
     const BatchImage im = a.imgs[it.image];
     const BatchModel md = a.models[im.model];
     const XTiles xt = batch_xtiles(im, a.Th, a.Tw, R);
     const int ty = it.tile / xt.nx, tx = it.tile - ty * xt.nx;
     const int y0 = ty * xt.Th, x0 = tx * xt.Tw;
     const int th = min(xt.Th, xt.H - y0), tw = min(xt.Tw, xt.W - x0);
+    if (i >= th * tw) return;
     const int T = a.T;
     const float *up = T == 1 ? im.f : batch_plane(im, T, T - 1);
     const float *xs = ((T - 1) & 1) ? im.xs[1] : im.xs[0];
-    const float l = md.lam[T - 1];
-    const int i = blockIdx.y * 256 + threadIdx.x;
-    if (i < th * tw) {
-        const int y = y0 + i / tw, x = x0 + i % tw;
-        const size_t q = (size_t)y * xt.W + x;
-        im.u_out[q] = reaction_step(md.react, up[q], pixel_force<R>(xs, xt, y, x), im.f[q], l, md.proj_c);
+    const int y = y0 + i / tw, x = x0 + i % tw;
+    const size_t q = (size_t)y * xt.W + x;
+    im.u_out[q] = reaction_step(md.react, up[q], pixel_force<R>(xs, xt, y, x), im.f[q], md.lam[T - 1],
+                                md.proj_c);
+}
+
+template <int KS, int NMB, int NB, int NW, int RBFM>
+__global__ void __launch_bounds__(64 * NW) k_batched_stage(BatchArgs a, int t)
+{
+    extern __shared__ float lds[];
+    batched_stage_item<KS, NMB, NB, NW, RBFM>(a, t, blockIdx.x, lds);
+}
+
+// The last stage's reaction of every image: u_T into u_out, one pixel per
+// thread; workgroup (b, c) covers pixels 256 c .. 256 c + 255 of item b.
+template <int R>
+__global__ void __launch_bounds__(256) k_batched_final(BatchArgs a)
+{
+    batched_final_pixel<R>(a, blockIdx.x, blockIdx.y * 256 + threadIdx.x);
+}
+
+// Platform of the persistent launch's scheduling loop (tnrd_persist.hpp) on
+// the GPU: workgroup barriers, device-scope atomics on the workspace's
+// counter and flags, the broadcast word in the workgroup's LDS.
+template <int KS, int NMB, int NB, int NW, int RBFM>
+struct BatchPersist {
+    const BatchArgs *a;
+    float *lds;
+    int *sh;
+    __device__ int tid() const { return threadIdx.x; }
+    __device__ void barrier() { __syncthreads(); }
+    __device__ int fetch_next(int *p)
+    {
+        return __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __device__ void set_shared(int v) { *sh = v; }
+    __device__ int get_shared() { return *sh; }
+    __device__ int poll(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+    __device__ void store_release(int *p, int v)
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // every counter to zero: the wave's stores have been acknowledged by the L2
+    __device__ void stores_done() { __builtin_amdgcn_s_waitcnt(0); }
+    __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
+    __device__ long long now() { return (long long)wall_clock64(); }
+    __device__ void neighbours(int k, int *nb)
+    {
+        const BatchItem it = a->items[k];
+        const BatchImage im = a->imgs[it.image];
+        persist_neighbours(k - it.tile, it.tile, im.tiles_x, im.tiles / im.tiles_x, nb);
+    }
+    __device__ void work(int t, int k)
+    {
+        if (t < a->T) {
+            batched_stage_item<KS, NMB, NB, NW, RBFM>(*a, t, k, lds);
+        } else {
+            for (int i = threadIdx.x; i < a->Th * a->Tw; i += 64 * NW) batched_final_pixel<KS / 2>(*a, k, i);
+        }
+    }
+};
+
+// Every stage of every tile of the batch in one launch: workgroups take
+// (stage, item) pairs in stage-major order and wait for the item's
+// neighbourhood to finish the stage before (persist_loop).  The broadcast
+// word sits in the LDS's reduction slot, which the forward never uses.
+template <int KS, int NMB, int NB, int NW, int RBFM>
+__global__ void __launch_bounds__(64 * NW) k_batched_persist(BatchArgs a)
+{
+    extern __shared__ float lds[];
+    const FusedLds L = fused_lds(KS, NMB, NB, a.Th, a.Tw, a.Nrbf, NW, MODE_FWD, RBFM);
+    BatchPersist<KS, NMB, NB, NW, RBFM> p{&a, lds, reinterpret_cast<int *>(lds + L.red_off)};
+    persist_loop(p, a.ctl);
+}
+
+// p[0 .. n) = 0 (a kernel, not a memset: the launch sequence is recorded in graphs)
+static __global__ void __launch_bounds__(256) k_clear_ints(int *__restrict__ p, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 template <int KS, int NMB, int NB, int NW, int MODE, int PREC, int RBFM>
@@ -994,6 +1068,33 @@ inline hipError_t launch_batched_t(const BatchArgs &a, hipStream_t stream)
     const size_t lds_bytes = (size_t)L.total * sizeof(float);
     raise_lds_limit((const void *)k_batched_stage<KS, NMB, NB, NW, RBFM>);
     if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    if (a.persistent) {
+        // counter, abort flag and flags are contiguous: [next][abort][flags...]
+        const int nctl = 2 + a.items_per_stage;
+        hipLaunchKernelGGL(k_clear_ints, dim3((nctl + 255) / 256), dim3(256), 0, stream, a.ctl.next, nctl);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const void *kp = (const void *)k_batched_persist<KS, NMB, NB, NW, RBFM>;
+        raise_lds_limit(kp);
+        int per_cu = 0, dev = 0, cus = 0, khz = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp, 64 * NW, lds_bytes) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        // the clock wall_clock64() reads (kHz)
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz < 1)
+            khz = 100000;
+        (void)hipGetLastError();
+        long grid = (long)per_cu * cus;
+        if (grid > a.ctl.n_items) grid = a.ctl.n_items;
+        BatchArgs b = a;
+        b.ctl.budget = (long long)(a.budget_s * 1e3 * khz);
+        hipLaunchKernelGGL((k_batched_persist<KS, NMB, NB, NW, RBFM>), dim3((int)grid), dim3(64 * NW),
+                           lds_bytes, stream, b);
+        return hipGetLastError();
+    }
     for (int t = 0; t < a.T; ++t) {
         hipLaunchKernelGGL((k_batched_stage<KS, NMB, NB, NW, RBFM>), dim3(a.items_per_stage),
                            dim3(64 * NW), lds_bytes, stream, a, t);

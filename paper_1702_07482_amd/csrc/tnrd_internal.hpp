@@ -10,6 +10,12 @@
 #include "tnrd_device.hpp"
 #include "tnrd_fused_common.hpp"
 
+// the scheduling loop of the persistent batched launch, plain C++ shared with
+// its host model: every function in it becomes host and device
+#pragma clang force_cuda_host_device begin
+#include "tnrd_persist.hpp"
+#pragma clang force_cuda_host_device end
+
 namespace tnrd {
 
 // Raises a kernel's dynamic LDS limit to the compute unit's 160 KB, once per
@@ -106,9 +112,14 @@ struct BatchArgs {
     size_t prep_stage;  // floats per prepared stage block
     int n_models;
     FusedRbf rb;
+    int persistent;   // one persistent launch for every stage (else one launch per stage)
+    PersistCtl ctl;   // persistent: counter, flags, abort flag (in the workspace)
+    double budget_s;  // persistent: ctl.budget in seconds (converted at launch)
 };
 
-// Runs the T stages of a batch: one launch per stage over all (image, tile) items.
+// Runs the T stages of a batch: one persistent launch over every (stage, item)
+// (a.persistent), or one launch per stage over all (image, tile) items and a
+// last-reaction launch.
 hipError_t batched_launch(const BatchArgs &a, int ks, int nw, hipStream_t stream);
 bool batched_config_ok(int ks, int nk, int nrbf, int th, int tw, int nw);
 

@@ -28,6 +28,7 @@ TNRD_ERR_WORKSPACE = -3
 TNRD_ERR_HIP = -4
 TNRD_ERR_UNSUPPORTED = -5
 TNRD_ERR_CAPACITY = -6
+TNRD_ERR_TIMEOUT = -7
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
@@ -51,7 +52,7 @@ class TnrdOpts(ctypes.Structure):
         ("prec", ctypes.c_int32), ("impl", ctypes.c_int32), ("rbf_window", ctypes.c_int32),
         ("recompute_every", ctypes.c_int32), ("validate", ctypes.c_int32),
         ("tile_h", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
-        ("use_graph", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("persistent", ctypes.c_int32),
     ]
 
 

@@ -48,7 +48,8 @@ def _fwd(m, N=1, H=32, W=32, L=1, f=FAKE_F, u=FAKE_U, ws=None, nb=0, **opt):
 
 def test_default_opts():
     o = tnrd.default_opts()
-    assert (o.prec, o.impl, o.rbf_window, o.recompute_every, o.validate, o.use_graph) == (0, 0, -1, 1, 0, 1)
+    assert (o.prec, o.impl, o.rbf_window, o.recompute_every, o.validate, o.use_graph, o.persistent) == \
+        (0, 0, -1, 1, 0, 1, 0)
 
 
 @pytest.mark.parametrize("kw,bad", [
@@ -130,7 +131,7 @@ def test_num_checkpoints():
 
 
 def test_status_strings():
-    for st in [0, -1, -2, -3, -4, -5, -6]:
+    for st in [0, -1, -2, -3, -4, -5, -6, -7]:
         assert tnrd.status_str(st) and tnrd.status_str(st) != "unknown status"
     assert tnrd.status_str(12) == "unknown status"
 

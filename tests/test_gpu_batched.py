@@ -1,6 +1,7 @@
 """Batched uneven forward (tnrd_forward_batched: one launch per stage over the
-tiles of every image, replayed from a HIP graph) against per-image
-tnrd_forward and the FP64 oracle."""
+tiles of every image, or one persistent launch over every (stage, tile),
+replayed from a HIP graph) against per-image tnrd_forward and the FP64
+oracle."""
 import numpy as np
 import pytest
 import torch
@@ -163,9 +164,57 @@ def test_graph_signature_covers_the_reaction():
     assert outs[0].min().item() >= 1.0  # the last call was the projected one
 
 
-@pytest.mark.skip(reason="The single persistent launch over all stages (work items handed out "
-                         "by an atomic counter, per-tile stage flags) hung twice on the GPU, the "
-                         "second time with a wall-clock-bounded wait; its cause is not found, so "
-                         "that variant is switched off and batches run one launch per stage.")
-def test_persistent_single_launch_variant():
-    pass
+def _persistent_vs_per_stage(fd, looks, dms, th, tw, nw, graph):
+    """Outputs of the single persistent launch and of one launch per stage
+    (same tile), the persistent one checked for give-ups (validate)."""
+    base = dict(tile_h=th, tile_w=tw, wg_waves=nw, use_graph=graph)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ref, _ = tnrd.forward_batched(fd, looks, dms, opts=tnrd.default_opts(persistent=0, **base))
+        ref = [u.clone() for u in ref]
+        po = tnrd.default_opts(persistent=1, validate=0 if graph else 1, **base)
+        outs, ws = tnrd.forward_batched(fd, looks, dms, opts=po)
+        if graph:  # records, then replays into the same buffers
+            outs, ws = tnrd.forward_batched(fd, looks, dms, opts=po, outs=outs, ws=ws)
+    s.synchronize()
+    return [u.cpu().numpy() for u in outs], [u.cpu().numpy() for u in ref]
+
+
+def test_persistent_launch_small_uneven_batch():
+    """One persistent launch over every (stage, tile) of an uneven batch with
+    per-look models (Sec. 4.5), tiles from 1 x 1 to 4 x 3 per image: bit for bit
+    the per-stage launches, and the oracle at whole images."""
+    sizes = [(40, 52), (96, 64), (33, 90), (64, 64), (120, 75), (7, 7)]
+    looks = [1, 4, 1, 2, 4, 2]
+    ms = _models(looks)
+    fs = [synth.make_pair(h, w, L, config_id=4, index=i)[1] for i, ((h, w), L) in enumerate(zip(sizes, looks))]
+    dms = [tnrd.DeviceModel.from_numpy(ms[L], L=L) for L in sorted(ms)]
+    print("[persistent: small uneven batch, 32x32x8, direct launch]", flush=True)
+    got, ref = _persistent_vs_per_stage([_dev(f) for f in fs], looks, dms, 32, 32, 8, 0)
+    for b in range(len(fs)):
+        np.testing.assert_array_equal(got[b], ref[b], err_msg=f"image {b}")
+    for b in (2, 4, 5):
+        assert rel_inf(got[b], oracle.forward(fs[b], ms[looks[b]])) <= TOL
+
+
+def test_persistent_launch_c4_batch():
+    """The 64-image batch of 256x256 .. 1024x768 images, L in {1, 2, 4, 8}: the
+    persistent launch at the autotuned tile and at 96 x 32 x 8 waves, directly
+    and as a graph replay, equals the per-stage launches on every image bit for
+    bit, and the oracle at sampled pixels."""
+    sizes, looks, ms, dms, fs = _c4_inputs()
+    fd = [_dev(f) for f in fs]
+    tuned = tuple(autotune.tune_batched(fd, looks, dms))
+    radius = 8 * 6
+    for th, tw, nw in sorted({tuned, (96, 32, 8)}):
+        for graph in (0, 1):
+            print(f"[persistent c4: tile {th}x{tw}x{nw} graph {graph}]", flush=True)
+            got, ref = _persistent_vs_per_stage(fd, looks, dms, th, tw, nw, graph)
+            for b in range(len(fs)):
+                np.testing.assert_array_equal(got[b], ref[b], err_msg=f"image {b} tile {th}x{tw}x{nw}")
+        for b in (9, 50):
+            h, w = sizes[b]
+            pts = [(0, w - 1), (h - 1, 0), (h // 2, w // 2)]
+            want = oracle_uT_at(fs[b], ms[looks[b]], pts, radius)
+            have = np.array([got[b][p] for p in pts])
+            assert np.abs(have - want).max() <= TOL * np.abs(want).max(), (th, tw, nw, b, have, want)
