@@ -217,7 +217,8 @@ int run_stages(const float *f, int N, int H, int W, const tnrd_model *m, const t
     if (use_prep) {
         if (!prep) return TNRD_ERR_WORKSPACE;
         if (fused_prep(m->filters + (size_t)t_begin * m->Nk * kk, m->rbf_w + (size_t)t_begin * m->Nk * m->Nrbf,
-                       t_end - t_begin, m->ksize, m->Nk, s.grid, 0, prep, stream) != hipSuccess)
+                       t_end - t_begin, m->ksize, m->Nk, s.grid, fused_prep_form(s), prep, stream) !=
+            hipSuccess)
             return TNRD_ERR_HIP;
     }
     if (impl == TNRD_IMPL_SPLIT) {

@@ -1128,7 +1128,8 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     // the input-gradient stages' d phi / ds tables and filter operands, all stages at once
     const bool use_prep = fused_uses_prep(ia);
     const size_t prep_sf = use_prep ? fused_prep_floats(m->ksize, m->Nk, m->Nrbf) : 0;
-    if (use_prep && fused_prep(m->filters, m->rbf_w, T, m->ksize, m->Nk, ia.grid, 1, w.prep_b, stream) !=
+    if (use_prep && fused_prep(m->filters, m->rbf_w, T, m->ksize, m->Nk, ia.grid, 1 | fused_prep_form(ia),
+                               w.prep_b, stream) !=
                         hipSuccess)
         return TNRD_ERR_HIP;
 

@@ -49,6 +49,49 @@ static void poly_gauss_coeffs(double rho, bool deriv, double M[POLY_NC][POLY_MW 
     }
 }
 
+// Monomial coefficients P[k][m + POLY_MW] (k = 0..3, |m| <= POLY_MW) of the
+// cubic interpolant at the Chebyshev points of e in [-1/2, 1/2] of
+// g(x) = exp(-rho x^2 / 2) (deriv = false) or -rho x exp(-rho x^2 / 2)
+// (deriv = true) at x = e / 2 + off - m: the Gaussian of centre j0 + m seen from
+// the half interval centred at j0 + off (off = -1/4 or +1/4), in FP64.
+static void poly3_gauss_coeffs(double rho, bool deriv, double off, double P[POLY3_NC][POLY3_NM])
+{
+    const double pi = 3.14159265358979323846;
+    double e[POLY3_NC];
+    for (int n = 0; n < POLY3_NC; ++n) e[n] = 0.5 * cos((2 * n + 1) * pi / (2 * POLY3_NC));
+    for (int mi = 0; mi < POLY3_NM; ++mi) {
+        const double m = mi - POLY_MW;
+        double A[POLY3_NC][POLY3_NC + 1];
+        for (int n = 0; n < POLY3_NC; ++n) {
+            double p = 1.0;
+            for (int k = 0; k < POLY3_NC; ++k) {
+                A[n][k] = p;
+                p *= e[n];
+            }
+            const double x = 0.5 * e[n] + off - m;
+            const double g = exp(-rho * x * x / 2.0);
+            A[n][POLY3_NC] = deriv ? -rho * x * g : g;
+        }
+        for (int col = 0; col < POLY3_NC; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < POLY3_NC; ++r)
+                if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+            if (piv != col)
+                for (int k = 0; k <= POLY3_NC; ++k) {
+                    double t = A[col][k];
+                    A[col][k] = A[piv][k];
+                    A[piv][k] = t;
+                }
+            for (int r = 0; r < POLY3_NC; ++r) {
+                if (r == col) continue;
+                const double fct = A[r][col] / A[col][col];
+                for (int k = col; k <= POLY3_NC; ++k) A[r][k] -= fct * A[col][k];
+            }
+        }
+        for (int k = 0; k < POLY3_NC; ++k) P[k][mi] = A[k][POLY3_NC] / A[k][k];
+    }
+}
+
 static FusedRbf make_fused_rbf_uncached(const RbfGrid &grid);
 
 // The constants depend on the grid only; the two 8 x 8 solves per centre
@@ -95,6 +138,16 @@ static FusedRbf make_fused_rbf_uncached(const RbfGrid &grid)
             rb.pm[k][m] = (float)M[k][m];
             rb.pmd[k][m] = (float)Md[k][m];
         }
+    for (int h = 0; h < 2; ++h) {
+        double P[POLY3_NC][POLY3_NM], Pd[POLY3_NC][POLY3_NM];
+        poly3_gauss_coeffs(rho, false, h ? 0.25 : -0.25, P);
+        poly3_gauss_coeffs(rho, true, h ? 0.25 : -0.25, Pd);
+        for (int k = 0; k < POLY3_NC; ++k)
+            for (int m = 0; m < POLY3_NM; ++m) {
+                rb.p3[h][k][m] = (float)P[k][m];
+                rb.p3d[h][k][m] = (float)Pd[k][m];
+            }
+    }
     return rb;
 }
 
@@ -246,9 +299,11 @@ static hipError_t fused_dispatch(const StageArgs &s, hipStream_t stream)
     const TilePlan p = plan_tile_cached(s.ks, s.Nk, s.grid.nrbf, s.N, s.H, s.W, s.tile_h, s.tile_w,
                                         s.waves, MODE, poly);
     if (!p.ok) return hipErrorInvalidValue;
-    if (MODE == MODE_BWD_INPUT) return fused_launch_bwd(s, p.th, p.tw, p.nb, p.nw, p.rbfm, stream);
+    // BF16 operands read the cubic half-interval table (fused_prep_form)
+    const int rbfm = p.rbfm == RBF_POLY && fused_prep_form(s) ? RBF_POLY3 : p.rbfm;
+    if (MODE == MODE_BWD_INPUT) return fused_launch_bwd(s, p.th, p.tw, p.nb, p.nw, rbfm, stream);
     if (s.prec == PREC_BF16 || s.prec == PREC_F16)
-        return fused_launch_fwd_mixed(s, p.th, p.tw, p.nb, p.nw, p.rbfm, stream);
+        return fused_launch_fwd_mixed(s, p.th, p.tw, p.nb, p.nw, rbfm, stream);
     return fused_launch_fwd_f32(s, p.th, p.tw, p.nb, p.nw, p.rbfm, stream);
 }
 

@@ -106,8 +106,19 @@ constexpr int POLY_TFP = POLY_NC * POLY_NI + ((4 - POLY_NC * POLY_NI % 16) + 16)
 // table, so it clamps to the zero interval at the top end with d = 0.
 constexpr float POLY_OFF_MASKED = 1048576.f;
 
+// Cubic half-interval form (BF16 operands only): each unit interval's table row
+// of 8 floats holds instead two cubics, one per half.  Half h (0: s below the
+// centre j0, 1: above) is centred at j0 - 1/4 + h/2; with e = 2 (s - centre) in
+// [-1/2, 1/2], phi ~ sum_{k<4} c_k e^k, the degree-3 interpolant at the
+// Chebyshev points of e, c_k = sum_{|m| <= POLY_MW} P3[h][k][m + POLY_MW] w_{j0+m}
+// (P3d for d phi / ds).  Summed over the centres its error stays below 2.6e-4
+// (phi) and 6.7e-4 (d phi / ds) of the largest weight for rho < 1.4, a tenth of
+// the BF16 rounding (2^-8) that the influence values get for the K^T GEMM.
+constexpr int POLY3_NC = 4;
+constexpr int POLY3_NM = 2 * POLY_MW + 1;
+
 // Influence evaluation of the fused stage kernel.
-enum RbfMethod { RBF_HORNER = 0, RBF_POLY = 1 };
+enum RbfMethod { RBF_HORNER = 0, RBF_POLY = 1, RBF_POLY3 = 2 };
 
 // Constants of the windowed Horner evaluation of phi.
 //   s = (z - mu0) / step = j0 + d, j0 the nearest centre, |d| <= 1/2,
@@ -124,6 +135,8 @@ struct FusedRbf {
     float c[RBF_TERMS];
     float pm[POLY_NC][POLY_MW + 1];   // M[k][m] of the polynomial form of phi
     float pmd[POLY_NC][POLY_MW + 1];  // the same for d phi / ds (input-gradient mode)
+    float p3[2][POLY3_NC][POLY3_NM];  // P3[h][k][m + POLY_MW] of the cubic half-interval form
+    float p3d[2][POLY3_NC][POLY3_NM]; // the same for d phi / ds
 };
 
 // Forward stage in exchange form.  A tile computes z, phi and K^T v from its

@@ -96,7 +96,8 @@ __host__ __device__ inline FusedLds fused_lds(int ks, int nmb, int nb, int th, i
     l.t_pitch = nrbf + 4 * RBF_WIN + 1;
     l.ni = POLY_NI;
     l.tf_pitch = POLY_TFP;
-    l.t_size = rbfm == RBF_POLY ? 16 * nmb * l.tf_pitch : ((16 * nmb * l.t_pitch + 3) & ~3);
+    l.t_size = rbfm == RBF_POLY || rbfm == RBF_POLY3 ? 16 * nmb * l.tf_pitch
+                                                     : ((16 * nmb * l.t_pitch + 3) & ~3);
     l.p_off = l.t_off + l.t_size;
     l.pw = 16 * nb + 2 * R;
     l.ring = fused_ring(ks, nw);
@@ -120,7 +121,9 @@ __device__ __forceinline__ void fused_tile(
     const FusedRbf &rb, const float *__restrict__ lam_t, float *lds)
 {
     constexpr bool BWD = MODE == MODE_BWD_INPUT;
-    constexpr bool POLY = RBFM == RBF_POLY;
+    constexpr bool POLY = RBFM == RBF_POLY || RBFM == RBF_POLY3;
+    constexpr bool CUBIC = RBFM == RBF_POLY3;  // cubic half-interval table (BF16 operands)
+    static_assert(!CUBIC || PREC == PREC_BF16, "the cubic half-interval form is for BF16 operands");
     // Polynomial form: the coefficient table comes ready-made from io.prep
     // (k_prep_stage); with FP32 operands the per-lane filter operands too
     constexpr bool PREP_TAB = POLY;
@@ -482,7 +485,10 @@ __device__ __forceinline__ void fused_tile(
     // accumulator register quad) into one of two buffers.  The interval index is
     // s = z / step - mu0 / step + W + 1 rounded; a lane whose pixel is masked off
     // takes scale 0 and offset POLY_OFF_MASKED instead, which selects the all-zero
-    // last interval, so its influence comes out exactly 0 with no select.
+    // last interval, so its influence comes out exactly 0 with no select.  The
+    // cubic half-interval form indexes halves with 2 s + 1/2 (the caller's scale
+    // and offset): half 2q + h of interval q, e = 2 s + 1/2 - (2q + h), one
+    // 4-float read.
     float dq[2][4];
     floatx4 lo[2][4], hi[2][4];
     auto fetch = [&](const floatx4 *acc1, int mb, int slot, float sscale, float soff) {
@@ -491,10 +497,10 @@ __device__ __forceinline__ void fused_tile(
             const float s = fmaf(acc1[mb][r], sscale, soff);
             const float jr = rintf(s);
             dq[slot][r] = s - jr;
-            const int q = (int)__builtin_amdgcn_fmed3f(jr, 0.f, (float)(POLY_NI - 1));
+            const int q = (int)__builtin_amdgcn_fmed3f(jr, 0.f, (float)((CUBIC ? 2 : 1) * POLY_NI - 1));
             const float *cp = stab + (16 * mb + r) * POLY_TFP + tab_g + 4 * q;
             lo[slot][r] = *reinterpret_cast<const floatx4 *>(cp);
-            hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * POLY_NI);
+            if (!CUBIC) hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * POLY_NI);
         }
     };
     // influence of filter group mb, in place: v = phi(z) (times phi' and a in
@@ -505,12 +511,18 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float d = dq[cur][r];
-                const floatx4 l = lo[cur][r], h = hi[cur][r];
-                float p = fmaf(h[3], d, h[2]);
-                p = fmaf(p, d, h[1]);
-                p = fmaf(p, d, h[0]);
-                p = fmaf(p, d, l[3]);
-                p = fmaf(p, d, l[2]);
+                const floatx4 l = lo[cur][r];
+                float p;
+                if (CUBIC) {
+                    p = fmaf(l[3], d, l[2]);
+                } else {
+                    const floatx4 h = hi[cur][r];
+                    p = fmaf(h[3], d, h[2]);
+                    p = fmaf(p, d, h[1]);
+                    p = fmaf(p, d, h[0]);
+                    p = fmaf(p, d, l[3]);
+                    p = fmaf(p, d, l[2]);
+                }
                 p = fmaf(p, d, l[1]);
                 p = fmaf(p, d, l[0]);
                 // input-gradient mode: p = d phi / ds, so phi'(z) a = p a / step
@@ -597,8 +609,10 @@ __device__ __forceinline__ void fused_tile(
         for (int mb2 = 0; mb2 < MB2; ++mb2) acc2[mb2] = floatx4{0.f, 0.f, 0.f, 0.f};
         // polynomial form: interval coordinate of this lane's pixel, or the
         // masked-off coordinate
-        const float sscale = valid ? rb.inv_step : 0.f;
-        const float soff = valid ? (float)(RBF_WIN + 1) - rb.mu0_over_step : POLY_OFF_MASKED;
+        const float sscale = valid ? (CUBIC ? 2.f : 1.f) * rb.inv_step : 0.f;
+        const float soff = valid ? (CUBIC ? 2.f * ((float)(RBF_WIN + 1) - rb.mu0_over_step) + 0.5f
+                                          : (float)(RBF_WIN + 1) - rb.mu0_over_step)
+                                 : POLY_OFF_MASKED;
         gemm1_load(en, cbn);
         if (POLY) fetch(c1, 0, 0, sscale, soff);
         gemm1_steps(0, K1 / NMB, n1, na);
@@ -959,7 +973,7 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     io.react = s.react;
     io.proj_c = s.proj_c;
     io.prep = s.prep;
-    if (RBFM == RBF_POLY && !s.prep) return hipErrorInvalidValue;
+    if ((RBFM == RBF_POLY || RBFM == RBF_POLY3) && !s.prep) return hipErrorInvalidValue;
     const int tiles_x = (s.W + tw - 1) / tw, tiles_y = (s.H + th - 1) / th;
     const int tiles = tiles_x * tiles_y;
     if (!s.x_out) return hipErrorInvalidValue;
@@ -1057,6 +1071,8 @@ template <int KS, int NMB, int MODE, int PREC>
 inline hipError_t fused_form(const StageArgs &s, int th, int tw, int nb, int nw, int rbfm,
                              hipStream_t stream)
 {
+    if constexpr (PREC == PREC_BF16)
+        if (rbfm == RBF_POLY3) return fused_nw<KS, NMB, MODE, PREC, RBF_POLY3>(s, th, tw, nb, nw, stream);
     if (rbfm == RBF_POLY) return fused_nw<KS, NMB, MODE, PREC, RBF_POLY>(s, th, tw, nb, nw, stream);
     return fused_nw<KS, NMB, MODE, PREC, RBF_HORNER>(s, th, tw, nb, nw, stream);
 }

@@ -128,8 +128,12 @@ bool batched_config_ok(int ks, int nk, int nrbf, int th, int tw, int nw);
 // prep + t * fused_prep_floats) from [T][Nk][ks*ks] filters and [T][Nk][Nrbf]
 // weights; deriv selects the d phi / ds table of the input-gradient mode.
 size_t fused_prep_floats(int ks, int nk, int nrbf);
+// form: bit 0 = tables of d phi / ds (input-gradient mode), bit 1 = the cubic
+// half-interval form (the BF16 kernels, fused_prep_form)
 hipError_t fused_prep(const float *filt, const float *rbfw, int T, int ks, int nk, const RbfGrid &grid,
-                      int deriv, float *prep, hipStream_t stream);
+                      int form, float *prep, hipStream_t stream);
+// The table form bit of the kernels that read stage s's prepared blocks.
+inline int fused_prep_form(const StageArgs &s) { return s.prec == PREC_BF16 ? 2 : 0; }
 // The same for stage 0 .. T-1 of every model of a batch (into BatchModel::prep).
 hipError_t batched_prep(const BatchArgs &a, int ks, int n_models, hipStream_t stream);
 // Whether a stage with these options runs the fused kernel's prepared form.

@@ -40,11 +40,15 @@ static size_t prep_stage_floats_t(int nrbf)
 
 // Thread idx of stage t: table interval (fi, q) for idx < 16 NMB ni (its 8
 // coefficients, plus the row's zero padding), then operand quad (k4, lane).
+// form: bit 0 = d phi / ds instead of phi, bit 1 = the cubic half-interval
+// form (two cubics per interval, floats 8 q .. 8 q + 7 of the row).
 template <int KS, int NMB>
 __device__ void prep_stage_body(const float *__restrict__ filt, const float *__restrict__ rbfw, int Nk,
-                                int Nrbf, const FusedRbf &rb, int deriv, float *__restrict__ out,
+                                int Nrbf, const FusedRbf &rb, int form, float *__restrict__ out,
                                 int idx)
 {
+    const int deriv = form & 1;
+    const bool cubic = (form & 2) != 0;
     using G = Geo<KS>;
     using G2 = Geo2<KS>;
     using P = PrepGeo<KS, NMB>;
@@ -56,6 +60,30 @@ __device__ void prep_stage_body(const float *__restrict__ filt, const float *__r
         // c_k = M[k][0] w_j0 + sum_{m>=1} M[k][m] (w_{j0+m} +- w_{j0-m}), j0 = q - 1 - W,
         // weights outside [0, Nrbf) taken as 0
         const int fi = idx / ni, q = idx - fi * ni;
+        if (cubic) {
+            // c_k of half h = sum_m P3[h][k][m + MW] w_{j0+m}, j0 = q - 1 - W
+            floatx4 c[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+            if (fi < Nk && q >= 1 && q <= ni_used - 2) {
+                const int j0 = q - 1 - RBF_WIN;
+#pragma unroll
+                for (int mi = 0; mi < POLY3_NM; ++mi) {
+                    const int jj = j0 + mi - POLY_MW;
+                    const float w = (jj >= 0 && jj < Nrbf) ? rbfw[fi * Nrbf + jj] : 0.f;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int k = 0; k < POLY3_NC; ++k)
+                            c[h][k] = fmaf(deriv ? rb.p3d[h][k][mi] : rb.p3[h][k][mi], w, c[h][k]);
+                }
+            }
+            float *dst = out + fi * L.tf_pitch + 8 * q;
+            *reinterpret_cast<floatx4 *>(dst) = c[0];
+            *reinterpret_cast<floatx4 *>(dst + 4) = c[1];
+            if (4 * q < L.tf_pitch - POLY_NC * ni)
+                *reinterpret_cast<floatx4 *>(out + fi * L.tf_pitch + POLY_NC * ni + 4 * q) =
+                    floatx4{0.f, 0.f, 0.f, 0.f};
+            return;
+        }
         const float(*pm)[POLY_MW + 1] = deriv ? rb.pmd : rb.pm;
         const int par = deriv ? 1 : 0;  // parity of k whose terms are sums
         float c[POLY_NC];
@@ -118,12 +146,12 @@ __device__ void prep_stage_body(const float *__restrict__ filt, const float *__r
 
 template <int KS, int NMB>
 __global__ void __launch_bounds__(256) k_prep_stage(const float *filt, const float *rbfw, int Nk,
-                                                    int Nrbf, FusedRbf rb, int deriv, float *prep,
+                                                    int Nrbf, FusedRbf rb, int form, float *prep,
                                                     size_t stage_floats)
 {
     const int t = blockIdx.y;
     prep_stage_body<KS, NMB>(filt + (size_t)t * Nk * KS * KS, rbfw + (size_t)t * Nk * Nrbf, Nk, Nrbf,
-                             rb, deriv, prep + (size_t)t * stage_floats,
+                             rb, form, prep + (size_t)t * stage_floats,
                              blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -155,7 +183,7 @@ size_t fused_prep_floats(int ks, int nk, int nrbf)
 }
 
 hipError_t fused_prep(const float *filt, const float *rbfw, int T, int ks, int nk, const RbfGrid &grid,
-                      int deriv, float *prep, hipStream_t stream)
+                      int form, float *prep, hipStream_t stream)
 {
     if (T <= 0) return hipSuccess;
     const int nmb = prep_nmb(nk);
@@ -163,7 +191,7 @@ hipError_t fused_prep(const float *filt, const float *rbfw, int T, int ks, int n
     const FusedRbf rb = make_fused_rbf(grid);
     auto go = [&](auto kern, int threads) {
         dim3 gridd((threads + 255) / 256, T);
-        hipLaunchKernelGGL(kern, gridd, dim3(256), 0, stream, filt, rbfw, nk, grid.nrbf, rb, deriv,
+        hipLaunchKernelGGL(kern, gridd, dim3(256), 0, stream, filt, rbfw, nk, grid.nrbf, rb, form,
                            prep, sf);
         return hipGetLastError();
     };
