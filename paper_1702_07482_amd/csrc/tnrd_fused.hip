@@ -50,15 +50,16 @@ static void poly_gauss_coeffs(double rho, bool deriv, double M[POLY_NC][POLY_MW 
 }
 
 // Monomial coefficients P[k][m + POLY_MW] (k = 0..3, |m| <= POLY_MW) of the
-// cubic interpolant at the Chebyshev points of e in [-1/2, 1/2] of
+// cubic interpolant at the Chebyshev points of e in [0, 1] of
 // g(x) = exp(-rho x^2 / 2) (deriv = false) or -rho x exp(-rho x^2 / 2)
-// (deriv = true) at x = e / 2 + off - m: the Gaussian of centre j0 + m seen from
-// the half interval centred at j0 + off (off = -1/4 or +1/4), in FP64.
+// (deriv = true) at x = (e - 1/2) / 2 + off - m: the Gaussian of centre j0 + m
+// seen from the half interval centred at j0 + off (off = -1/4 or +1/4), whose
+// points are j0 + off + (e - 1/2) / 2, in FP64.
 static void poly3_gauss_coeffs(double rho, bool deriv, double off, double P[POLY3_NC][POLY3_NM])
 {
     const double pi = 3.14159265358979323846;
     double e[POLY3_NC];
-    for (int n = 0; n < POLY3_NC; ++n) e[n] = 0.5 * cos((2 * n + 1) * pi / (2 * POLY3_NC));
+    for (int n = 0; n < POLY3_NC; ++n) e[n] = 0.5 + 0.5 * cos((2 * n + 1) * pi / (2 * POLY3_NC));
     for (int mi = 0; mi < POLY3_NM; ++mi) {
         const double m = mi - POLY_MW;
         double A[POLY3_NC][POLY3_NC + 1];
@@ -68,7 +69,7 @@ static void poly3_gauss_coeffs(double rho, bool deriv, double off, double P[POLY
                 A[n][k] = p;
                 p *= e[n];
             }
-            const double x = 0.5 * e[n] + off - m;
+            const double x = 0.5 * (e[n] - 0.5) + off - m;
             const double g = exp(-rho * x * x / 2.0);
             A[n][POLY3_NC] = deriv ? -rho * x * g : g;
         }

@@ -108,8 +108,8 @@ constexpr float POLY_OFF_MASKED = 1048576.f;
 
 // Cubic half-interval form (BF16 operands only): each unit interval's table row
 // of 8 floats holds instead two cubics, one per half.  Half h (0: s below the
-// centre j0, 1: above) is centred at j0 - 1/4 + h/2; with e = 2 (s - centre) in
-// [-1/2, 1/2], phi ~ sum_{k<4} c_k e^k, the degree-3 interpolant at the
+// centre j0, 1: above) is [j0 - 1/2 + h/2, j0 + h/2); with e = 2 (s - its left
+// end) in [0, 1), phi ~ sum_{k<4} c_k e^k, the degree-3 interpolant at the
 // Chebyshev points of e, c_k = sum_{|m| <= POLY_MW} P3[h][k][m + POLY_MW] w_{j0+m}
 // (P3d for d phi / ds).  Summed over the centres its error stays below 2.6e-4
 // (phi) and 6.7e-4 (d phi / ds) of the largest weight for rho < 1.4, a tenth of

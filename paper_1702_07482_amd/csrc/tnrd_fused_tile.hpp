@@ -206,6 +206,8 @@ __device__ __forceinline__ void fused_tile(
                 }
             }
         }
+        // the padding word of each row (read by the mixed kernels' pad k-slots)
+        for (int ly = tid; ly < luh; ly += THREADS) se[ly * L.ldw + luw] = 0.f;
     }
     // (3) Gaussian form: the RBF weights are the table itself, rows zero padded
     // by 2W on both sides
@@ -296,6 +298,8 @@ __device__ __forceinline__ void fused_tile(
                 }
             }
         }
+        // the padding word of each row (read by the mixed kernels' pad k-slots)
+        for (int ly = tid; ly < luh; ly += THREADS) su[ly * L.ldw + luw] = 0.f;
     }
     // (2c) polynomial form: the prepared coefficient table straight into LDS in
     // 256-float chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk)
@@ -378,7 +382,12 @@ __device__ __forceinline__ void fused_tile(
     constexpr int KSH = (KK + 15) / 16;  // GEMM1 k-steps of 16 taps
     MV a1m[NMB][MIXED ? KSH : 1];
     MV a2m[MB2][MIXED ? NMB : 1];
-    int offm[MIXED ? KSH : 1][4];
+    // GEMM1 k-slots (mixed): the 7 x 7 taps in a 7 x 8 grid with a pad column in
+    // front, slot 16 s + 4 g + i = tap row 2 s + (g >> 1), column 4 (g & 1) + i - 1,
+    // so a lane's four taps of a k-step are adjacent in one row and its B
+    // operand reads take compile-time offsets from one per-lane base.  Pad
+    // slots and row 7 carry zero weight.
+    static_assert(!MIXED || (KS == 7 && KSH == 4), "the mixed tap grid is laid out for 7 x 7 filters");
     if (MIXED) {
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb)
@@ -386,8 +395,9 @@ __device__ __forceinline__ void fused_tile(
             for (int s = 0; s < KSH; ++s)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    int fi = 16 * mb + j, t = 16 * s + 4 * g + i;
-                    a1m[mb][s][i] = MX::cvt((fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f);
+                    const int fi = 16 * mb + j, ta = 2 * s + (g >> 1), tb = 4 * (g & 1) + i - 1;
+                    const bool ok = fi < Nk && ta < KS && tb >= 0 && tb < KS;
+                    a1m[mb][s][i] = MX::cvt(ok ? sf[fi * KK + ta * KS + tb] : 0.f);
                 }
 #pragma unroll
         for (int mb2 = 0; mb2 < MB2; ++mb2)
@@ -411,15 +421,13 @@ __device__ __forceinline__ void fused_tile(
         int t = 4 * s + g;
         off1[s] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
     }
-    if (MIXED) {
-#pragma unroll
-        for (int s = 0; s < KSH; ++s)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int t = 16 * s + 4 * g + i;
-                offm[s][i] = t < KK ? (t / KS) * L.ldw + (t % KS) : 0;
-            }
-    }
+    // mixed GEMM1 B operands: lane group g's taps of k-step s sit at compile-time
+    // offsets 2 s ldw + i below the per-lane base ub - gofs; in the last k-step
+    // the rows past KS - 1 (zero weights) read row KS - 1 instead (gofs_last),
+    // so no read leaves the tile.  Column -1 (the pad slot) is the tile row's
+    // padding word past the last column, which holds a finite value.
+    const int gofs = (g >> 1) * L.ldw + 4 * (g & 1) - 1;
+    const int gofs_last = (min(2 * (KSH - 1) + (g >> 1), KS - 1) - 2 * (KSH - 1)) * L.ldw + 4 * (g & 1) - 1;
 
     const float lam = lam_t[0];
     // per-lane part of the polynomial table address: filter 16 mb + 4 g + r
@@ -437,13 +445,17 @@ __device__ __forceinline__ void fused_tile(
         const float *ub = su + (e + 2 * R) * L.ldw + cc + 2 * R;
         const float *eb = se + (e + 2 * R) * L.ldw + cc + 2 * R;
         if (MIXED) {
+            const float *ubg = ub - gofs, *ubl = ub - gofs_last;
+            const float *ebg = eb - gofs, *ebl = eb - gofs_last;
 #pragma unroll
             for (int s = 0; s < KSH; ++s) {
+                const float *up = s == KSH - 1 ? ubl : ubg;
+                const float *ep = s == KSH - 1 ? ebl : ebg;
                 floatx4 xu, xe;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    xu[i] = ub[-offm[s][i]];
-                    xe[i] = BWD ? escale * eb[-offm[s][i]] : 0.f;
+                    xu[i] = up[-(2 * s * L.ldw + i)];
+                    xe[i] = BWD ? escale * ep[-(2 * s * L.ldw + i)] : 0.f;
                 }
                 bum[s] = MX::cvt4(xu);
                 if (BWD) bem[s] = MX::cvt4(xe);
@@ -486,18 +498,26 @@ __device__ __forceinline__ void fused_tile(
     // s = z / step - mu0 / step + W + 1 rounded; a lane whose pixel is masked off
     // takes scale 0 and offset POLY_OFF_MASKED instead, which selects the all-zero
     // last interval, so its influence comes out exactly 0 with no select.  The
-    // cubic half-interval form indexes halves with 2 s + 1/2 (the caller's scale
-    // and offset): half 2q + h of interval q, e = 2 s + 1/2 - (2q + h), one
-    // 4-float read.
+    // cubic half-interval form indexes halves with 2 s + 1 (the caller's scale
+    // and offset): half 2q + h = floor(2 s + 1) of interval q, e = the fraction
+    // in [0, 1), one 4-float read.
     float dq[2][4];
     floatx4 lo[2][4], hi[2][4];
     auto fetch = [&](const floatx4 *acc1, int mb, int slot, float sscale, float soff) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float s = fmaf(acc1[mb][r], sscale, soff);
-            const float jr = rintf(s);
-            dq[slot][r] = s - jr;
-            const int q = (int)__builtin_amdgcn_fmed3f(jr, 0.f, (float)((CUBIC ? 2 : 1) * POLY_NI - 1));
+            int q;
+            if (CUBIC) {
+                // s = 2 (interval coordinate) + 1: half q = floor(s), e = its fraction
+                const float sc = __builtin_amdgcn_fmed3f(s, 0.f, (float)(2 * POLY_NI) - 0.5f);
+                q = (int)sc;
+                dq[slot][r] = __builtin_amdgcn_fractf(sc);
+            } else {
+                const float jr = rintf(s);
+                dq[slot][r] = s - jr;
+                q = (int)__builtin_amdgcn_fmed3f(jr, 0.f, (float)(POLY_NI - 1));
+            }
             const float *cp = stab + (16 * mb + r) * POLY_TFP + tab_g + 4 * q;
             lo[slot][r] = *reinterpret_cast<const floatx4 *>(cp);
             if (!CUBIC) hi[slot][r] = *reinterpret_cast<const floatx4 *>(cp + 4 * POLY_NI);
@@ -610,7 +630,7 @@ __device__ __forceinline__ void fused_tile(
         // polynomial form: interval coordinate of this lane's pixel, or the
         // masked-off coordinate
         const float sscale = valid ? (CUBIC ? 2.f : 1.f) * rb.inv_step : 0.f;
-        const float soff = valid ? (CUBIC ? 2.f * ((float)(RBF_WIN + 1) - rb.mu0_over_step) + 0.5f
+        const float soff = valid ? (CUBIC ? 2.f * ((float)(RBF_WIN + 1) - rb.mu0_over_step) + 1.f
                                           : (float)(RBF_WIN + 1) - rb.mu0_over_step)
                                  : POLY_OFF_MASKED;
         gemm1_load(en, cbn);
