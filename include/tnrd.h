@@ -116,7 +116,10 @@ typedef struct tnrd_opts {
                                  0: every RBF term, w > 0: the 2w+1 centres nearest to z */
     int32_t recompute_every; /* backward checkpointing, see tnrd_forward(states) */
     int32_t validate;     /* nonzero: check f > 0 and finite on the device first (synchronises
-                             `stream`; TNRD_ERR_DOMAIN on failure) */
+                             `stream`; TNRD_ERR_DOMAIN on failure); with FP16 operands also that
+                             f < 2^15 (the states enter the FP16 GEMMs unscaled and stay near the
+                             data's range, so this keeps them below FP16's 65504;
+                             TNRD_ERR_UNSUPPORTED otherwise) */
     int32_t tile_h, tile_w; /* 0 = automatic; otherwise the fused kernel's output tile */
     int32_t wg_waves;     /* fused kernel: wavefronts per workgroup, 4 or 8; 0 = automatic */
     int32_t use_graph;    /* tnrd_forward_batched: 1 (default) records the launch sequence in a HIP

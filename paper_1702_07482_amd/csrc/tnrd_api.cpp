@@ -19,16 +19,18 @@ constexpr size_t WS_ALIGN = 256;
 size_t align_up(size_t x) { return (x + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
 
 // Domain check of f: flag[0] |= 1 if any f <= 0 or not finite.
-__global__ void k_check_domain(const float *__restrict__ f, size_t n, int *flag)
+// flag bit 0: some f <= 0 or not finite; bit 1: some f >= fmax
+__global__ void k_check_domain(const float *__restrict__ f, size_t n, float fmax, int *flag)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     int bad = 0;
     for (; i < n; i += stride) {
         float v = f[i];
-        bad |= !(v > 0.f) || !isfinite(v);
+        bad |= (!(v > 0.f) || !isfinite(v)) ? 1 : 0;
+        bad |= v >= fmax ? 2 : 0;
     }
-    if (bad) atomicOr(flag, 1);
+    if (bad) atomicOr(flag, bad);
 }
 
 // flag[0] = 0 (a kernel rather than a memset node, safe where callers capture graphs)
@@ -163,20 +165,23 @@ size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opt
     return bytes;
 }
 
-int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream)
+int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream, int prec)
 {
     hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, stream, dflag);
     if (hipGetLastError() != hipSuccess) return TNRD_ERR_HIP;
     int blocks = (int)((n + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_check_domain, dim3(blocks), dim3(256), 0, stream, f, n, dflag);
+    // FP16 operands hold u unscaled: f below 2^15 keeps the states (which stay
+    // near the data's range) well inside FP16's largest value, 65504
+    const float fmax = prec == TNRD_PREC_FP16 ? FP16_FMAX : INFINITY;
+    hipLaunchKernelGGL(k_check_domain, dim3(blocks), dim3(256), 0, stream, f, n, fmax, dflag);
     if (hipGetLastError() != hipSuccess) return TNRD_ERR_HIP;
     int host = 0;
     if (hipMemcpyAsync(&host, dflag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess)
         return TNRD_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return TNRD_ERR_HIP;
-    return host ? TNRD_ERR_DOMAIN : TNRD_OK;
+    return (host & 1) ? TNRD_ERR_DOMAIN : (host & 2) ? TNRD_ERR_UNSUPPORTED : TNRD_OK;
 }
 
 // Runs stages [t_begin, t_end) (0-based stage index t computes u_{t+1})
@@ -310,7 +315,7 @@ int run_forward(const float *f, int N, int H, int W, const tnrd_model *m, float 
     }
 
     if (oo.validate) {
-        int st = run_domain_check(f, img, dflag, stream);
+        int st = run_domain_check(f, img, dflag, stream, oo.prec);
         if (st != TNRD_OK) return st;
     }
 

@@ -18,7 +18,11 @@ RbfGrid make_grid(const tnrd_model *m, int window);
 int choose_impl(const tnrd_model *m, const tnrd_opts &o, int window);
 int checkpoint_slot(int t, int T, int s);
 size_t forward_ws_bytes(int N, int H, int W, const tnrd_model *m, const tnrd_opts &o, int impl);
-int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream);
+// Largest f the FP16 operands accept (validate: TNRD_ERR_UNSUPPORTED from it on).
+constexpr float FP16_FMAX = 32768.f;
+// validate: TNRD_ERR_DOMAIN if some f <= 0 or is not finite, TNRD_ERR_UNSUPPORTED
+// if prec is FP16 and some f >= FP16_FMAX; synchronises `stream`.
+int run_domain_check(const float *f, size_t n, int *dflag, hipStream_t stream, int prec);
 // Runs stages [t_begin, t_end) of m.  prep: room for the prepared blocks of
 // t_end - t_begin stages (prep_region_floats), used by the fused FP32 form.
 // slabs: two regions of slab_region_floats each (the fused forward's exchange buffers).

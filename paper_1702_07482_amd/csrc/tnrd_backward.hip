@@ -1101,7 +1101,7 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
         bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, false, oo.prec));
     const size_t img = gm.img;
     if (oo.validate) {
-        st = run_domain_check(f, img, (int *)ws, stream);
+        st = run_domain_check(f, img, (int *)ws, stream, oo.prec);
         if (st != TNRD_OK) return st;
     }
 

@@ -284,7 +284,7 @@ extern "C" int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models,
     char *wsb = (char *)ws;
     if (oo.validate) {
         for (int b = 0; b < B; ++b) {
-            st = run_domain_check(imgs[b].f, (size_t)imgs[b].H * imgs[b].W, (int *)ws, stream);
+            st = run_domain_check(imgs[b].f, (size_t)imgs[b].H * imgs[b].W, (int *)ws, stream, oo.prec);
             if (st != TNRD_OK) return st;
         }
     }

@@ -142,3 +142,18 @@ def test_mixed_backward_input_gradient(prec):
     print(f"prec={prec} backward rel errors {errs} bounds {bounds}", flush=True)
     for n in names:
         assert errs[n] <= bounds[n], (n, errs, bounds)
+
+
+def test_fp16_validate_rejects_values_beyond_its_range():
+    """FP16 operands hold the states unscaled; validate refuses f >= 2^15 for
+    them (TNRD_ERR_UNSUPPORTED), and accepts the same image in BF16 and FP32,
+    whose exponent range covers it."""
+    m = synth.config_model(5)
+    f = synth.make_pair(40, 40, 1, config_id=5, index=3)[1].astype(np.float64)
+    f = f / f.max() * 1.0e5
+    dm = tnrd.DeviceModel.from_numpy(m)
+    with pytest.raises(RuntimeError, match="unsupported"):
+        tnrd.forward(_dev(f), dm, opts=tnrd.default_opts(prec=tnrd.PREC_FP16, validate=1))
+    for prec in (tnrd.PREC_BF16, tnrd.PREC_FP32):
+        out = tnrd.forward(_dev(f), dm, opts=tnrd.default_opts(prec=prec, validate=1)).cpu().numpy()
+        assert np.isfinite(out).all()
