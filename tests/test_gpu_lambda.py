@@ -98,8 +98,14 @@ def test_prox_backward_lambda_end_to_end(case):
 
     dK, dW, dl/du_0 and dl/df meet 1e-4.  dlambda^t = sum_p g_t x_l is a sum over
     pixels with cancellation whose terms depend on u_t itself, so it carries the
-    FP32 forward's state error amplified; its bar is derived from the oracle
-    alone (see the assertion)."""
+    FP32 forward's state error amplified.  Rounding each state to FP32 on its own
+    moves the oracle's dlambda little (kappa_round, printed): independent
+    per-pixel errors cancel in the sum.  A coherent deviation does not, and the
+    GPU's states carry one of about one FP32 unit (the polynomial influence form
+    is a fixed perturbation of phi; long FP32 sums round with a correlated bias).
+    The bar for dlambda is therefore derived from the oracle alone: twice
+    kappa_coh, the change of the oracle's dlambda when every state is multiplied
+    by 1 + 2^-23 before the next stage."""
     print(f"[lambda backward, end to end: {case}]", flush=True)
     m, u, f, scale = CASES[case]()
     uT, st = oracle.forward(f, m, want_states=True)
@@ -118,6 +124,10 @@ def test_prox_backward_lambda_end_to_end(case):
     # stage's state is rounded to FP32 before the next stage
     st_r = _stage_states(f, m, lambda x: x.astype(np.float32).astype(np.float64))
     kappa_round = rel_inf(oracle.backward(f, m, st_r, gT)[2], ref[2])
-    print("rel errors", errs, "state err", state_err, "kappa_round", kappa_round, flush=True)
+    st_c = _stage_states(f, m, lambda x: x * (1.0 + 2.0 ** -23))
+    kappa_coh = rel_inf(oracle.backward(f, m, st_c, gT)[2], ref[2])
+    print("rel errors", errs, "state err", state_err, "kappa_round", kappa_round, "kappa_coh", kappa_coh,
+          flush=True)
     for n in ["dK", "dW", "g0", "gf"]:
         assert errs[n] <= TOL, (n, errs)
+    assert errs["dlam"] <= 2.0 * kappa_coh, (errs["dlam"], kappa_coh)
