@@ -137,7 +137,7 @@ __device__ __forceinline__ void rbf_phi_dphi_horner(float z, const float *__rest
 // The one computing them is held to 256 (2 waves per SIMD); it reads a filter
 // block's GEMM operands from the LDS copy of the bank when it starts the block.
 template <int KS, int NMB, int NBW, int NW, bool LOADZA, int PREC>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LOADZA ? 4 : 2, 8)))
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(LOADZA ? 3 : 2, 8)))
 k_bwd_params(
     BwdParamsIO io, int H, int W, int Th, int tiles_x, int tiles_per_img,
     const float *__restrict__ filt, int Nk, const float *__restrict__ rbfw, int Nrbf, FusedRbf rb,
@@ -354,6 +354,8 @@ k_bwd_params(
         // pixel, and the export buffer carries ZA_PAD floats of slack for the last one.
         const float *zaimg = io.za + img * plane * zst + 8 * (j >> 2) + (j & 3);
         float zn[NMB][4], an[NMB][4];
+        // raw values; the mask of a pixel past the image row or a filter past Nk
+        // is applied when the block is used
         auto load = [&](int b) {
             const int y = wave + NW * (b / NBW), cb = b % NBW;
             const int yy = b < nblk ? ty0 + y : ty0;
@@ -362,21 +364,29 @@ k_bwd_params(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float *pp = rowp + (size_t)(min(xb + r, W - 1) * zst);
-                const bool okr = b < nblk && xb + r < W;
 #pragma unroll
                 for (int nb = 0; nb < NMB; ++nb) {
-                    const bool ok = okr && 16 * nb + j < Nk;
-                    const float zz = pp[32 * nb], aa = pp[32 * nb + 4];
-                    zn[nb][r] = ok ? zz : 0.f;
-                    an[nb][r] = ok ? aa : 0.f;
+                    zn[nb][r] = pp[32 * nb];
+                    an[nb][r] = pp[32 * nb + 4];
                 }
             }
         };
+        // one block ahead: the loads of block b + 1 are in flight while block b
+        // is computed (a block past the end loads clamped in-image addresses)
+        if (nblk > 0) load(0);
 #pragma unroll 1
         for (int b = 0; b < nblk; ++b) {
-            load(b);
-            const float(&zc)[NMB][4] = zn;
-            const float(&ac)[NMB][4] = an;
+            float zc[NMB][4], ac[NMB][4];
+            const int xb = tx0 + 16 * (b % NBW) + 4 * g;
+#pragma unroll
+            for (int nb = 0; nb < NMB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool ok = xb + r < W && 16 * nb + j < Nk;
+                    zc[nb][r] = ok ? zn[nb][r] : 0.f;
+                    ac[nb][r] = ok ? an[nb][r] : 0.f;
+                }
+            load(b + 1);
             const int y = wave + NW * (b / NBW), cb = b % NBW;
 #pragma unroll
             for (int nb = 0; nb < NMB; ++nb) {
