@@ -282,6 +282,8 @@ struct FusedIO {
     float *u_keep;        // pend: the tile's own pixels of u_{t-1} after the pending reaction
     const float *lam_prev;  // pend: lambda of the previous stage
     int pend;             // the previous stage's reaction is still to be applied
+    int keep_table;       // polynomial form: the workgroup's LDS already holds this stage's
+                          // table (a persistent workgroup's previous item), no copy
     XTiles xt;            // this image's tiling
 };
 

@@ -303,7 +303,7 @@ __device__ __forceinline__ void fused_tile(
     }
     // (2c) polynomial form: the prepared coefficient table straight into LDS in
     // 256-float chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk)
-    if (PREP_TAB) {
+    if (PREP_TAB && !io.keep_table) {
         for (int c = wave; c * 256 < L.t_size; c += NW) {
             const int k = c * 256 + 4 * lane;
             if (k < L.t_size) __builtin_amdgcn_global_load_lds(io.prep + k, stab + c * 256, 16, 0, 0);
@@ -844,9 +844,11 @@ __device__ __forceinline__ float *batch_plane(const BatchImage &im, int T, int t
     return ((T - t) & 1) == 0 ? im.u_out : im.u_tmp;
 }
 
-// Stage t (< T) of batch item k.
+// Stage t (< T) of batch item k.  keep_table: the LDS already holds this
+// stage's coefficient table for this item's model.
 template <int KS, int NMB, int NB, int NW, int RBFM>
-__device__ __forceinline__ void batched_stage_item(const BatchArgs &a, int t, int k, float *lds)
+__device__ __forceinline__ void batched_stage_item(const BatchArgs &a, int t, int k, float *lds,
+                                                   int keep_table = 0)
 {
     constexpr int KK = KS * KS, R = KS / 2;
     const BatchItem it = a.items[k];
@@ -872,6 +874,7 @@ __device__ __forceinline__ void batched_stage_item(const BatchArgs &a, int t, in
     io.react = md.react;
     io.proj_c = md.proj_c;
     io.prep = md.prep + (size_t)t * a.prep_stage;
+    io.keep_table = keep_table;
     fused_tile<KS, NMB, NB, NW, MODE_FWD, PREC_F32, RBFM>(
         io, im.H, im.W, a.Th, a.Tw, ty * a.Th, tx * a.Tw, md.filt + (size_t)t * a.Nk * KK, a.Nk,
         md.rbfw + (size_t)t * a.Nk * a.Nrbf, a.Nrbf, a.rb, md.lam + t, lds);
@@ -921,6 +924,7 @@ struct BatchPersist {
     const BatchArgs *a;
     float *lds;
     int *sh;
+    int table_key;  // (model, stage) whose coefficient table the LDS holds, -1: none
     __device__ int tid() const { return threadIdx.x; }
     __device__ void barrier() { __syncthreads(); }
     __device__ int fetch_next(int *p)
@@ -948,7 +952,12 @@ struct BatchPersist {
     __device__ void work(int t, int k)
     {
         if (t < a->T) {
-            batched_stage_item<KS, NMB, NB, NW, RBFM>(*a, t, k, lds);
+            // consecutive items mostly share the stage and the model: their table
+            // stays in LDS (every thread computes the same key)
+            const int key = a->imgs[a->items[k].image].model * (a->T + 1) + t;
+            const int keep = RBFM == RBF_POLY && key == table_key;
+            table_key = key;
+            batched_stage_item<KS, NMB, NB, NW, RBFM>(*a, t, k, lds, keep);
         } else {
             for (int i = threadIdx.x; i < a->Th * a->Tw; i += 64 * NW) batched_final_pixel<KS / 2>(*a, k, i);
         }
@@ -964,7 +973,7 @@ __global__ void __launch_bounds__(64 * NW) k_batched_persist(BatchArgs a)
 {
     extern __shared__ float lds[];
     const FusedLds L = fused_lds(KS, NMB, NB, a.Th, a.Tw, a.Nrbf, NW, MODE_FWD, RBFM);
-    BatchPersist<KS, NMB, NB, NW, RBFM> p{&a, lds, reinterpret_cast<int *>(lds + L.red_off)};
+    BatchPersist<KS, NMB, NB, NW, RBFM> p{&a, lds, reinterpret_cast<int *>(lds + L.red_off), -1};
     persist_loop(p, a.ctl);
 }
 
