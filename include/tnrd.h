@@ -68,7 +68,11 @@ typedef enum tnrd_prec {
 
 /* Which stage implementation runs the forward. */
 typedef enum tnrd_impl {
-    TNRD_IMPL_AUTO = 0,   /* fused MFMA stage kernel */
+    TNRD_IMPL_AUTO = 0,   /* the fused MFMA stage kernel where it covers the model (ksize 5 or 7,
+                             Nk <= 48, the automatic or the 11-centre RBF window); otherwise, with
+                             FP32 operands, the split path, about 10x slower (ksize 3, Nk > 48, an
+                             explicit window such as rbf_window = 0); tnrd_selected_impl reports
+                             the choice */
     TNRD_IMPL_FUSED = 1,  /* one kernel per stage: K (MFMA), phi, K^T (MFMA), prox, responses kept on chip */
     TNRD_IMPL_SPLIT = 2   /* two kernels per stage on the vector ALUs: (K, phi) -> Nk response maps in
                              the workspace, then (K^T, prox).  Reference design for comparison. */
@@ -252,6 +256,12 @@ int tnrd_forward_batched(int B, const tnrd_image *imgs, int n_models, const tnrd
 #define TNRD_NOALLOC_SCRATCH_BYTES (64u << 20)
 int tnrd_forward_noalloc(const float *f, int N, int H, int W, int L, const tnrd_model *m,
                          float *u_out, float *states, const tnrd_opts *o, void *stream);
+
+/* The implementation tnrd_forward would run for model m with options o (NULL:
+ * defaults): TNRD_IMPL_FUSED or TNRD_IMPL_SPLIT, or TNRD_ERR_ARG (NULL model,
+ * bad ksize or sizes) or TNRD_ERR_UNSUPPORTED (no implementation covers the
+ * model at o->prec).  Host-only, no device call. */
+int tnrd_selected_impl(const tnrd_model *m, const tnrd_opts *o);
 
 /* Static description of a status code. */
 const char *tnrd_status_str(int status);

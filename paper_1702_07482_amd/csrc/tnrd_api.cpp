@@ -412,6 +412,15 @@ int tnrd_forward(const float *f, int N, int H, int W, int L, const tnrd_model *m
     return run_forward(f, N, H, W, m, u_out, states, oo, p, ws, (hipStream_t)stream_);
 }
 
+int tnrd_selected_impl(const tnrd_model *m, const tnrd_opts *o)
+{
+    if (!m || m->T < 1 || m->Nk < 1 || m->Nrbf < 1 || (m->ksize != 3 && m->ksize != 5 && m->ksize != 7))
+        return TNRD_ERR_ARG;
+    tnrd_opts oo;
+    resolve_opts(o, &oo);
+    return choose_impl(m, oo, rbf_window_for(m, oo.rbf_window));
+}
+
 const char *tnrd_status_str(int status)
 {
     switch (status) {

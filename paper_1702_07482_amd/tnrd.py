@@ -91,6 +91,7 @@ SIGNATURES = [
     ("tnrd_forward_noalloc", _I, [_P, _I, _I, _I, _I, ctypes.POINTER(TnrdModel), _P, _P,
                                   ctypes.POINTER(TnrdOpts), _P]),
     ("tnrd_status_str", ctypes.c_char_p, [_I]),
+    ("tnrd_selected_impl", _I, [ctypes.POINTER(TnrdModel), ctypes.POINTER(TnrdOpts)]),
     ("tnrd_peaks_sink_floats", _SZ, []),
     ("tnrd_measure_peaks", _I, [_P, _P, _SZ, _P, ctypes.POINTER(TnrdPeaks), _P]),
 ]

@@ -152,3 +152,23 @@ def test_noalloc_forward_rejects_oversized_calls_before_any_launch():
                                     ctypes.byref(o), None) == tnrd.TNRD_ERR_ARG
     assert lib.tnrd_forward_noalloc(FAKE_F, 0, 32, 32, 1, ctypes.byref(m), FAKE_U, None,
                                     ctypes.byref(o), None) == tnrd.TNRD_OK
+
+
+@pytest.mark.parametrize("kw,opt,want", [
+    (dict(ks=7, Nk=48), {}, tnrd.IMPL_FUSED),                        # the workloads' models
+    (dict(ks=5, Nk=24), {}, tnrd.IMPL_FUSED),
+    (dict(ks=7, Nk=48), dict(rbf_window=0), tnrd.IMPL_SPLIT),       # every RBF term: split only
+    (dict(ks=3, Nk=8), {}, tnrd.IMPL_SPLIT),                          # no fused kernel for 3 x 3
+    (dict(ks=7, Nk=64), {}, tnrd.IMPL_SPLIT),                         # more filters than 3 blocks
+    (dict(ks=7, Nk=48), dict(prec=tnrd.PREC_BF16), tnrd.IMPL_FUSED),
+    (dict(ks=5, Nk=24), dict(prec=tnrd.PREC_BF16), tnrd.TNRD_ERR_UNSUPPORTED),  # mixed: 7 x 7 only
+    (dict(ks=7, Nk=48), dict(impl=tnrd.IMPL_FUSED, rbf_window=0), tnrd.TNRD_ERR_UNSUPPORTED),
+    (dict(ks=4), {}, tnrd.TNRD_ERR_ARG),
+])
+def test_selected_impl_reports_the_automatic_choice(kw, opt, want):
+    """TNRD_IMPL_AUTO takes the fused kernel where it covers the model and the
+    (slower) split path otherwise; tnrd_selected_impl says which, on the host."""
+    m = _model(**kw)
+    o = tnrd.default_opts(**opt)
+    assert tnrd.load().tnrd_selected_impl(ctypes.byref(m), ctypes.byref(o)) == want
+    assert tnrd.load().tnrd_selected_impl(None, ctypes.byref(o)) == tnrd.TNRD_ERR_ARG

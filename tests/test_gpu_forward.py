@@ -143,19 +143,20 @@ def test_zero_weights_identity(impl):
 
 @pytest.mark.parametrize("impl", IMPLS)
 def test_exact_rbf_sum_and_windows(impl):
-    """rbf_window = 0 (all 63 terms) and a narrow window both meet the bar."""
+    """rbf_window = 0 (all 63 terms) and the 11-centre window both meet the bar on
+    the split path; the fused kernel runs the 11-centre window and refuses
+    rbf_window = 0 (its influence forms are built for the window)."""
     m = synth.config_model(1)
     if impl == tnrd.IMPL_FUSED and not _fused_available(m):
         pytest.skip("fused kernel not built for this model")
     _, f = synth.make_pair(64, 64, 1, config_id=1, index=5)
     ref = oracle.forward(f, m)
     for w in (0, 5):
-        try:
-            got = _run(f, m, impl, rbf_window=w)
-        except RuntimeError as e:
-            if "unsupported" in str(e):
-                continue
-            raise
+        if impl == tnrd.IMPL_FUSED and w == 0:
+            with pytest.raises(RuntimeError, match="unsupported"):
+                _run(f, m, impl, rbf_window=w)
+            continue
+        got = _run(f, m, impl, rbf_window=w)
         assert rel_inf(got, ref) <= TOL, w
 
 
