@@ -20,6 +20,8 @@ Extra legs reported on the same JSON line (each its own workload):
            ratio image, coefficient of variation) of the model before and after
   peaks    measured copy, matrix, vector-FMA and exp2 throughput; the legs' rates
            against them ("fractions")
+  fused_vs_split  (not a default leg) the 8 x 2048 x 2048 FP32 forward with the fused
+           stage kernel and with the split path
 
 The CPU baseline times the FP64 oracle (tests' reference, not a product path)
 on a bounded strip of the same workload.
@@ -474,6 +476,35 @@ def mixed_vs_oracle(pin):
     return out
 
 
+def leg_fused_vs_split(args):
+    """8 x 2048 x 2048, 8 stages x 48 7x7, FP32: the fused stage kernel against the
+    split path (K and phi into Nk response maps in HBM, then K^T and prox).  Not a
+    default leg; its HBM counters are in profiles/fused_vs_split_c2_c5.md."""
+    import torch
+    from paper_1702_07482_amd import synth, tnrd
+
+    N, H, W, T = 8, 2048, 2048, 8
+    m = synth.config_model(5)
+    f = np.stack([synth.make_pair(H, W, 1, config_id=5, index=n)[1] for n in range(N)])
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd = torch.from_numpy(f).cuda().contiguous()
+    out = {}
+    for name, impl in (("split", tnrd.IMPL_SPLIT), ("fused", tnrd.IMPL_FUSED)):
+        o = tnrd.default_opts(impl=impl)
+        tnrd.forward(fd, dm, opts=o)  # warm-up (and workspace)
+        torch.cuda.synchronize()
+        a, b = _events()
+        a.record()
+        for _ in range(2):
+            tnrd.forward(fd, dm, opts=o)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 2
+        out[name] = {"ms_per_call": ms, "mpst_s": N * H * W * T / 1e6 / (ms / 1e3)}
+    out["workload"] = "forward 8 x 2048 x 2048, L=1, 8 stages x 48 7x7, FP32, fused vs split"
+    return out
+
+
 def leg_projected(args):
     """The paper's comparison model (eq. diffusion_backP, projection onto u >= 1)
     at the shape of its comparison experiment (5 stages of 24 5x5 filters, L = 1),
@@ -652,12 +683,15 @@ def fractions(out):
 
 def resolve_auto_impl():
     """The implementation IMPL_AUTO runs for the headline workload."""
-    import torch
+    import ctypes
     from paper_1702_07482_amd import synth, tnrd
 
     dm = tnrd.DeviceModel.from_numpy(synth.config_model(2))
-    fused = tnrd.tnrd_workspace_bytes(1, 512, 512, dm.abi(), tnrd.default_opts(impl=tnrd.IMPL_FUSED), 0)
-    return tnrd.IMPL_FUSED if fused > 0 else tnrd.IMPL_SPLIT
+    m, o = dm.abi(), tnrd.default_opts()
+    impl = tnrd.load().tnrd_selected_impl(ctypes.byref(m), ctypes.byref(o))
+    if impl not in (tnrd.IMPL_FUSED, tnrd.IMPL_SPLIT):
+        raise RuntimeError(f"no implementation for the headline model: {tnrd.status_str(impl)}")
+    return impl
 
 
 def cpu_baseline(f, m, rows):
@@ -748,6 +782,8 @@ def main():
         out["batched"] = leg_batched(args)
     if "mixed" in legs:
         out["mixed"] = leg_mixed(args)
+    if "fused_vs_split" in legs:
+        out["fused_vs_split"] = leg_fused_vs_split(args)
     if "projected" in legs:
         out["projected"] = leg_projected(args)
     if "denoise" in legs:
