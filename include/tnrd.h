@@ -59,7 +59,11 @@ typedef enum tnrd_status {
 
 /* Operand precision of the two filter-bank contractions (K and K^T, forward
  * and backward).  The influence function, the prox and all accumulation stay
- * FP32 in every mode. */
+ * FP32 in every mode.  In tnrd_backward, BF16 also keeps z = K u and a = K e
+ * of the input-gradient contraction as BF16 values for the parameter
+ * gradients (fastest; dK and dW then carry z's BF16 rounding, a few percent of
+ * their maximum), while FP16 recomputes z on FP32 operands for them (closer
+ * to FP32). */
 typedef enum tnrd_prec {
     TNRD_PREC_FP32 = 0,
     TNRD_PREC_BF16 = 1,

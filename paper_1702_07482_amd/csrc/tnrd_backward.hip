@@ -14,11 +14,12 @@
 // Three kernels per stage, then one deterministic reduction:
 //   k_fused_stage<.., MODE_BWD_INPUT>  the force sum_i K_i^T(phi_i'(z_i) a_i) of
 //                  each tile's own pixels into its slab (tnrd_fused_tile.hpp), then
-//                  k_grad_finish forms g_{t-1} from the slabs; in FP32 the first
-//                  also stores z and a of every pixel (za_index layout)
-//   k_bwd_params   dK and dl partial sums per tile, from the stored z, a (FP32),
-//                  or computing and storing them itself (BF16/FP16, and the first
-//                  stage when dl/du_0 is not asked for)
+//                  k_grad_finish forms g_{t-1} from the slabs; with FP32 or BF16
+//                  operands the first also stores z and a of every pixel
+//                  (za_index layout; BF16 words with BF16 operands)
+//   k_bwd_params   dK and dl partial sums per tile, from the stored z, a (FP32,
+//                  BF16), or computing and storing them itself (FP16, and the
+//                  first stage when dl/du_0 is not asked for)
 //   k_bwd_dw       dW partial sums from the stored z, a
 //   k_reduce_partials  fixed-order sums of the partials into the outputs (one launch)
 //
@@ -29,18 +30,20 @@
 // straight into the weight-gradient contraction without passing through LDS.
 // When it computes z and a itself, the filter-bank GEMM runs transposed
 // (rows = 16 pixels, columns = 16 filters) to leave them in that layout.
-// With BF16/FP16 operands (the mixed-precision backward), a = K e and the dK
-// contraction run on v_mfma_f32_16x16x16_{bf16,f16} with FP32 accumulation:
-// the transposed filter bank for a (k = 16 taps per step) and dK (k = the
-// block's 16 pixels in one step, whose B operand is the transposed bank's
-// accumulator quad, pixels 4g .. 4g+3 of filter j, converted once).  e enters
+// With BF16/FP16 operands (the mixed-precision backward), the dK contraction
+// runs on v_mfma_f32_16x16x16_{bf16,f16} with FP32 accumulation (k = the
+// block's 16 pixels in one step, whose B operand is the block's v or phi'a
+// quad, pixels 4g .. 4g+3 of filter j, converted once), and ubar enters the
+// second dK term as a BF16/FP16 pair ubar = hi + lo (two MFMAs).  e enters
 // scaled by a per-tile power of two (max |e| -> 2^10, FP16's normal range)
-// that is undone in FP32 on dK and on the exported a.  Two operands stay
-// accurate to about 2^-16: z = K u stays on the FP32 instruction (it feeds phi,
-// phi' and the Gaussians of dW, and u carries a large mean that 8 or 11
-// mantissa bits of u or of k would move z by several units), and ubar enters
-// the second dK term as a BF16/FP16 pair ubar = hi + lo (two MFMAs).  The
-// influence function and dlambda stay FP32.
+// that is undone in FP32 on dK and on the exported a.  With BF16, z and a are
+// the input-gradient kernel's (its BF16 GEMMs; z is then where the BF16
+// forward evaluated phi), loaded from its BF16 export.  With FP16 (and at a
+// first stage without dl/du_0), k_bwd_params computes them: a = K e on the
+// 16x16x16 instruction (the transposed bank, k = 16 taps per step) and
+// z = K u on the FP32 instruction, since u carries a large mean that 8 or 11
+// mantissa bits of u or of k would move z by several units.  The influence
+// function and dlambda stay FP32.
 //
 // k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms, each lane working
 // on one filter and owning its column (a filter has several lanes, each with a
@@ -49,6 +52,7 @@
 #include <limits.h>
 #include <math.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "tnrd.h"
@@ -148,13 +152,13 @@ k_bwd_params(
     constexpr int THREADS = 64 * NW;
     constexpr int Tw = 16 * NBW;
     constexpr bool MIXED = PREC != PREC_F32;
-    static_assert(!(MIXED && LOADZA), "the mixed-precision variant computes z and a itself");
+    static_assert(!(LOADZA && PREC == PREC_F16), "FP16 operands: z and a are computed here");
     using MX = Mix<PREC>;
     typedef typename MX::V MV;
     constexpr int KSH = (KK + 15) / 16;  // mixed: transposed filter-bank k-steps of 16 taps
 
     extern __shared__ float lds[];
-    const BpLds L = bp_lds(KS, NMB, Th, Tw, Nrbf, NW, MIXED);
+    const BpLds L = bp_lds(KS, NMB, Th, Tw, Nrbf, NW, MIXED && !LOADZA);
     float *su = lds + L.u_off;
     float *se = lds + L.e_off;
     float *stab = lds + L.t_off;
@@ -352,18 +356,20 @@ k_bwd_params(
         // address of a pixel past the image row or of a row past the tile is clamped into
         // the image (its values are dropped); a filter block past Nk may read into the next
         // pixel, and the export buffer carries ZA_PAD floats of slack for the last one.
-        const float *zaimg = io.za + img * plane * zst + 8 * (j >> 2) + (j & 3);
-        float zn[NMB][4], an[NMB][4];
+        // FP32 words, or BF16 words with BF16 operands
+        using ZT = typename std::conditional<MIXED, unsigned short, float>::type;
+        const ZT *zaimg = reinterpret_cast<const ZT *>(io.za) + img * plane * zst + 8 * (j >> 2) + (j & 3);
+        ZT zn[NMB][4], an[NMB][4];
         // raw values; the mask of a pixel past the image row or a filter past Nk
         // is applied when the block is used
         auto load = [&](int b) {
             const int y = wave + NW * (b / NBW), cb = b % NBW;
             const int yy = b < nblk ? ty0 + y : ty0;
-            const float *rowp = zaimg + (size_t)yy * W * zst;
+            const ZT *rowp = zaimg + (size_t)yy * W * zst;
             const int xb = tx0 + 16 * cb + 4 * g;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float *pp = rowp + (size_t)(min(xb + r, W - 1) * zst);
+                const ZT *pp = rowp + (size_t)(min(xb + r, W - 1) * zst);
 #pragma unroll
                 for (int nb = 0; nb < NMB; ++nb) {
                     zn[nb][r] = pp[32 * nb];
@@ -383,28 +389,78 @@ k_bwd_params(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const bool ok = xb + r < W && 16 * nb + j < Nk;
-                    zc[nb][r] = ok ? zn[nb][r] : 0.f;
-                    ac[nb][r] = ok ? an[nb][r] : 0.f;
+                    zc[nb][r] = ok ? za_value(zn[nb][r]) : 0.f;
+                    ac[nb][r] = ok ? escale * za_value(an[nb][r]) : 0.f;
                 }
             load(b + 1);
             const int y = wave + NW * (b / NBW), cb = b % NBW;
+            if constexpr (MIXED) {
+                // BF16: the dK contraction on the 16x16x16 instruction, as in the
+                // computing variant below (A = scaled ebar, and ubar as hi + lo)
+                MV de[MB2], duh[MB2], dul[MB2];
 #pragma unroll
-            for (int nb = 0; nb < NMB; ++nb) {
-                const float *row = stab + nb * 16 * L.t_pitch + j;
-                floatx4 vz, vh;
+                for (int mt = 0; mt < MB2; ++mt) {
+                    floatx4 xe, xu, xl;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const bool valid = tx0 + 16 * cb + 4 * g + r < W;
-                    float ph, dph;
-                    rbf_phi_dphi_horner(zc[nb][r], row, rb, ph, dph);
-                    vz[r] = valid ? ph : 0.f;
-                    vh[r] = valid ? dph * ac[nb][r] : 0.f;
+                    for (int i = 0; i < 4; ++i) {
+                        const int b2 = (y + 2 * R) * L.ldw + 16 * cb + 4 * g + i + 2 * R;
+                        xe[i] = tapok[mt] ? escale * se[b2 - offt[mt]] : 0.f;
+                        xu[i] = tapok[mt] ? su[b2 - offt[mt]] : 0.f;
+                    }
+                    de[mt] = MX::cvt4(xe);
+                    duh[mt] = MX::cvt4(xu);
+                    const floatx4 hi = MX::widen4(duh[mt]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xl[i] = xu[i] - hi[i];
+                    dul[mt] = MX::cvt4(xl);
                 }
-                dk_block(y, cb, nb, vz, vh);
+#pragma unroll
+                for (int nb = 0; nb < NMB; ++nb) {
+                    const float *row = stab + nb * 16 * L.t_pitch + j;
+                    floatx4 vz, vh;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bool valid = tx0 + 16 * cb + 4 * g + r < W;
+                        float ph, dph;
+                        rbf_phi_dphi_horner(zc[nb][r], row, rb, ph, dph);
+                        vz[r] = valid ? ph : 0.f;
+                        vh[r] = valid ? dph * ac[nb][r] : 0.f;
+                    }
+                    const MV vb = MX::cvt4(vz), hb = MX::cvt4(vh);
+#pragma unroll
+                    for (int mt = 0; mt < MB2; ++mt) {
+                        dkt[mt][nb] = MX::mfma(de[mt], vb, dkt[mt][nb]);
+                        dkt[mt][nb] = MX::mfma(duh[mt], hb, dkt[mt][nb]);
+                        dkt[mt][nb] = MX::mfma(dul[mt], hb, dkt[mt][nb]);
+                    }
+                    if (G::VTAP) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int b2 = (y + 2 * R) * L.ldw + 16 * cb + 4 * g + r + 2 * R;
+                            const float ev = escale * se[b2 - offv], uvv = su[b2 - offv];
+                            acc48[nb] = fmaf(vz[r], ev, fmaf(vh[r], uvv, acc48[nb]));
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int nb = 0; nb < NMB; ++nb) {
+                    const float *row = stab + nb * 16 * L.t_pitch + j;
+                    floatx4 vz, vh;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bool valid = tx0 + 16 * cb + 4 * g + r < W;
+                        float ph, dph;
+                        rbf_phi_dphi_horner(zc[nb][r], row, rb, ph, dph);
+                        vz[r] = valid ? ph : 0.f;
+                        vh[r] = valid ? dph * ac[nb][r] : 0.f;
+                    }
+                    dk_block(y, cb, nb, vz, vh);
+                }
             }
         }
     }
-    if constexpr (MIXED) {
+    if constexpr (MIXED && !LOADZA) {
         // transposed filter bank of a = K e as the B operand, converted once into
         // LDS, [nb][s][lane]: lane (g, j) holds taps 16 s + 4 g + i (i = 0..3) of
         // filter 16 nb + j
@@ -489,9 +545,15 @@ k_bwd_params(
                         float ph, dph;
                         rbf_phi_dphi_horner(z, row, rb, ph, dph);
                         if (valid && fi < Nk) {
-                            const size_t pix = img * plane + (size_t)yi * W + xi;
-                            io.za[za_index(pix, Nk, fi)] = z;
-                            io.za[za_index(pix, Nk, fi) + 4] = a * einv;
+                            const size_t zi = za_index(img * plane + (size_t)yi * W + xi, Nk, fi);
+                            if constexpr (PREC == PREC_BF16) {
+                                unsigned short *zq = reinterpret_cast<unsigned short *>(io.za);
+                                zq[zi] = (unsigned short)MX::cvt(z);
+                                zq[zi + 4] = (unsigned short)MX::cvt(a * einv);
+                            } else {
+                                io.za[zi] = z;
+                                io.za[zi + 4] = a * einv;
+                            }
                         }
                         accz[r] = valid ? ph : 0.f;
                         acca[r] = valid ? dph * a : 0.f;
@@ -514,6 +576,8 @@ k_bwd_params(
                 }
             }
         }
+    }
+    if constexpr (MIXED) {
         // back to the gradient's own scale
 #pragma unroll
         for (int nb = 0; nb < NMB; ++nb) {
@@ -629,10 +693,10 @@ __host__ __device__ inline int dw_bins(int nrbf) { return nrbf + 4 * RBF_WIN; }
 __host__ __device__ inline size_t dw_wave_bytes(int nrbf) { return (size_t)dw_bins(nrbf) * 64 * sizeof(float); }
 
 // dW partial sums: each wave its own histogram, each lane one filter and a share
-// of the workgroup's pixels.
-template <int NW>
+// of the workgroup's pixels.  ZT: the export's words (float, or BF16 bits).
+template <int NW, typename ZT>
 __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
-    const float *__restrict__ za, long long P, long long per_wg,
+    const ZT *__restrict__ za, long long P, long long per_wg,
     int Nk, int Nrbf, FusedRbf rb, float *__restrict__ dw_part)
 {
     extern __shared__ float lds[];
@@ -656,18 +720,18 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
         // this step's are binned.  Both loads always run (a pixel past p1 reads
         // pixel p0 instead), and its a is replaced by 0, so it adds 0.
         constexpr int U = DW_U;
-        float zn[U], an[U];
-        const float *zl = za + za_index((size_t)p0, Nk, fi);
+        ZT zn[U], an[U];
+        const ZT *zl = za + za_index((size_t)p0, Nk, fi);
         const unsigned zst = (unsigned)za_stride(Nk);
         auto load = [&](int kb) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int pl = sub + ns * (kb + u);
                 const bool in = pl < npix;
-                const float *qp = zl + (size_t)((unsigned)(in ? pl : 0) * zst);
-                const float zz = qp[0], aa = qp[4];
+                const ZT *qp = zl + (size_t)((unsigned)(in ? pl : 0) * zst);
+                const ZT zz = qp[0], aa = qp[4];
                 zn[u] = zz;
-                an[u] = in ? aa : 0.f;
+                an[u] = in ? aa : ZT(0);
             }
         };
         load(0);
@@ -675,8 +739,8 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
             float zc[U], ac[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                zc[u] = zn[u];
-                ac[u] = an[u];
+                zc[u] = za_value(zn[u]);
+                ac[u] = za_value(an[u]);
             }
             load(kb + U);
 #pragma unroll
@@ -817,6 +881,7 @@ BwdGeom bwd_geom(int N, int H, int W, int th)
 template <int KS, int NMB>
 static const void *bp_kernel_t(bool loadza, int prec)
 {
+    if (loadza && KS == 7 && prec == PREC_BF16) return (const void *)k_bwd_params<7, NMB, BP_NBW, BP_NW, true, PREC_BF16>;
     if (loadza) return (const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, true, PREC_F32>;
     if (KS == 7 && prec == PREC_BF16) return (const void *)k_bwd_params<7, NMB, BP_NBW, BP_NW, false, PREC_BF16>;
     if (KS == 7 && prec == PREC_F16) return (const void *)k_bwd_params<7, NMB, BP_NBW, BP_NW, false, PREC_F16>;
@@ -839,10 +904,10 @@ static int bp_per_cu(int ks, int nk, int nrbf, bool loadza, int prec, int th)
     const int nmb = (nk + 15) / 16 <= 2 ? 2 : 3;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    static thread_local int key[4][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1},
+    static thread_local int key[5][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1},
                                          {-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};
-    static thread_local int cached[4][BP_TH_MAX + 1];
-    const int v = loadza ? 3 : (prec >= 0 && prec <= 2 ? prec : 0);
+    static thread_local int cached[5][BP_TH_MAX + 1];
+    const int v = loadza ? (prec == PREC_BF16 ? 4 : 3) : (prec >= 0 && prec <= 2 ? prec : 0);
     th = th < BP_TH_MIN ? BP_TH_MIN : (th > BP_TH_MAX ? BP_TH_MAX : th);
     if (!(key[v][0] == ks && key[v][1] == nmb && key[v][2] == nrbf && key[v][3] == dev && key[v][4] == prec)) {
         for (int i = 0; i <= BP_TH_MAX; ++i) cached[v][i] = 0;
@@ -936,7 +1001,7 @@ hipError_t launch_bwd_params(const BwdParamsIO &io, const BwdGeom &gm, int H, in
                              int Nk, const float *rbfw, const RbfGrid &grid, const float *lam,
                              hipStream_t stream)
 {
-    BpLds L = bp_lds(KS, NMB, gm.th, 16 * BP_NBW, grid.nrbf, BP_NW, PREC != PREC_F32);
+    BpLds L = bp_lds(KS, NMB, gm.th, 16 * BP_NBW, grid.nrbf, BP_NW, PREC != PREC_F32 && !LOADZA);
     size_t lds_bytes = (size_t)L.total * sizeof(float);
     raise_lds_limit((const void *)k_bwd_params<KS, NMB, BP_NBW, BP_NW, LOADZA, PREC>);
     const int per_img = gm.tiles_x * gm.tiles_y;
@@ -952,6 +1017,8 @@ hipError_t launch_bwd_params_mode(bool loadza, int prec, const BwdParamsIO &io, 
                                   int W, const float *filt, int Nk, const float *rbfw,
                                   const RbfGrid &grid, const float *lam, hipStream_t stream)
 {
+    if (loadza && KS == 7 && prec == PREC_BF16)
+        return launch_bwd_params<7, NMB, true, PREC_BF16>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     if (loadza) return launch_bwd_params<KS, NMB, true, PREC_F32>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
     if (KS == 7 && prec == PREC_BF16)
         return launch_bwd_params<7, NMB, false, PREC_BF16>(io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
@@ -961,14 +1028,15 @@ hipError_t launch_bwd_params_mode(bool loadza, int prec, const BwdParamsIO &io, 
 }
 
 // Parameter-gradient partials of one stage.  loadza: z = K u and a = K e come
-// from the input-gradient kernel's export (FP32 path); otherwise they are
-// computed here, with the operand precision prec, and exported for k_bwd_dw.
+// from the input-gradient kernel's export (FP32 or BF16 operands, the export's
+// words); otherwise they are computed here, with the operand precision prec,
+// and exported for k_bwd_dw.
 hipError_t bwd_params(bool loadza, int prec, const BwdParamsIO &io, const BwdGeom &gm, int H, int W,
                       int ks, const float *filt, int Nk, const float *rbfw, const RbfGrid &grid,
                       const float *lam, hipStream_t stream)
 {
     const int nmb = (Nk + 15) / 16;
-    if (prec != PREC_F32 && (ks != 7 || loadza)) return hipErrorInvalidValue;
+    if (prec != PREC_F32 && (ks != 7 || (loadza && prec != PREC_BF16))) return hipErrorInvalidValue;
     if (ks == 7)
         return nmb <= 2 ? launch_bwd_params_mode<7, 2>(loadza, prec, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream)
                         : launch_bwd_params_mode<7, 3>(loadza, prec, io, gm, H, W, filt, Nk, rbfw, grid, lam, stream);
@@ -978,32 +1046,42 @@ hipError_t bwd_params(bool loadza, int prec, const BwdParamsIO &io, const BwdGeo
     return hipErrorInvalidValue;
 }
 
-template <int NW>
-hipError_t launch_bwd_dw(const float *za, const BwdGeom &gm, int Nk,
+template <int NW, typename ZT>
+hipError_t launch_bwd_dw(const ZT *za, const BwdGeom &gm, int Nk,
                          const RbfGrid &grid, float *dw_part, hipStream_t stream)
 {
     const size_t lds_bytes = NW * dw_wave_bytes(grid.nrbf);
-    raise_lds_limit((const void *)k_bwd_dw<NW>);
+    raise_lds_limit((const void *)k_bwd_dw<NW, ZT>);
     // the kernel indexes a workgroup's pixels with 32-bit offsets and gives
     // every filter at least one of its 64 NW lanes
     if (gm.dw_per_wg >= (1LL << 30) || (long long)gm.dw_per_wg * za_stride(Nk) >= (1LL << 32) ||
         Nk < 1 || Nk > 64 * NW)
         return hipErrorInvalidValue;
     FusedRbf rb = make_fused_rbf(grid);
-    hipLaunchKernelGGL((k_bwd_dw<NW>), dim3(gm.dw_grid), dim3(64 * NW), lds_bytes, stream,
+    hipLaunchKernelGGL((k_bwd_dw<NW, ZT>), dim3(gm.dw_grid), dim3(64 * NW), lds_bytes, stream,
                        za, (long long)gm.img, gm.dw_per_wg, Nk, grid.nrbf, rb, dw_part);
     return hipGetLastError();
 }
 
 // As many waves (histograms) per workgroup as fit the LDS: 7 for 63 RBFs.
-hipError_t bwd_dw(const float *za, const BwdGeom &gm, int Nk,
-                  const RbfGrid &grid, float *dw_part, hipStream_t stream)
+template <typename ZT>
+hipError_t bwd_dw_t(const ZT *za, const BwdGeom &gm, int Nk, const RbfGrid &grid, float *dw_part,
+                    hipStream_t stream)
 {
     const size_t per_wave = dw_wave_bytes(grid.nrbf), cap = 160 * 1024;
     if (7 * per_wave <= cap) return launch_bwd_dw<7>(za, gm, Nk, grid, dw_part, stream);
     if (4 * per_wave <= cap) return launch_bwd_dw<4>(za, gm, Nk, grid, dw_part, stream);
     if (2 * per_wave <= cap) return launch_bwd_dw<2>(za, gm, Nk, grid, dw_part, stream);
     return launch_bwd_dw<1>(za, gm, Nk, grid, dw_part, stream);
+}
+
+// za: the export in the words of operand precision prec (za_is_bf16)
+hipError_t bwd_dw(const float *za, int prec, const BwdGeom &gm, int Nk, const RbfGrid &grid,
+                  float *dw_part, hipStream_t stream)
+{
+    if (za_is_bf16(prec))
+        return bwd_dw_t(reinterpret_cast<const unsigned short *>(za), gm, Nk, grid, dw_part, stream);
+    return bwd_dw_t(za, gm, Nk, grid, dw_part, stream);
 }
 
 // acc += x over n floats.
@@ -1106,7 +1184,9 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
     BwdWs w = bwd_ws_layout((char *)ws, N, H, W, m, s, prep, slab, slab_b);
     // the two variants of k_bwd_params hold different numbers of workgroups per
     // compute unit, so each gets its own tile height (gm: loading z and a)
-    BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, true, TNRD_PREC_FP32));
+    // B2 geometries: loading the export (FP32 or BF16 operands), and computing z and a
+    const int prec_load = oo.prec == TNRD_PREC_BF16 ? TNRD_PREC_BF16 : TNRD_PREC_FP32;
+    BwdGeom gm = bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, true, prec_load));
     const BwdGeom gm_own =
         bwd_geom(N, H, W, bwd_tile_h(N, H, W, m->ksize, m->Nk, m->Nrbf, false, oo.prec));
     const size_t img = gm.img;
@@ -1179,11 +1259,12 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
             io.proj_c = m->proj_c;
             io.dk_part = w.dk_part;
             io.dl_part = w.dl_part;
-            // The input-gradient kernel (FP32) computes z = K u and a = K e at
-            // every pixel anyway and exports them, so it runs first and the
-            // parameter-gradient kernels load them instead of recomputing.
+            // The input-gradient kernel (FP32 or BF16 operands) computes z = K u
+            // and a = K e at every pixel anyway and exports them, so it runs first
+            // and the parameter-gradient kernels load them instead of recomputing.
             const bool need_g = t > 1 || grad_u0 || grad_f;
-            const bool loadza = need_g && oo.prec == TNRD_PREC_FP32 && (long long)H * W <= INT_MAX;
+            const bool loadza = need_g && (oo.prec == TNRD_PREC_FP32 || oo.prec == TNRD_PREC_BF16) &&
+                                (long long)H * W <= INT_MAX;
             float *g_next = (t == 1 && grad_u0) ? grad_u0 : w.g[ping];
             if (need_g) {
                 // the input-gradient kernel leaves the force of e in its slabs; the
@@ -1205,11 +1286,11 @@ extern "C" int tnrd_backward(const float *f, int N, int H, int W, int L, const t
                 if (fused_grad_finish(fa, stream) != hipSuccess) return TNRD_ERR_HIP;
             }
             const BwdGeom &gp = loadza ? gm : gm_own;
-            if (bwd_params(loadza, loadza ? TNRD_PREC_FP32 : oo.prec, io, gp, H, W, m->ksize, filt, m->Nk,
+            if (bwd_params(loadza, oo.prec, io, gp, H, W, m->ksize, filt, m->Nk,
                            rbfw, ia.grid, lam, stream) !=
                 hipSuccess)
                 return TNRD_ERR_HIP;
-            if (bwd_dw(w.za, gm, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
+            if (bwd_dw(w.za, oo.prec, gm, m->Nk, ia.grid, w.dw_part, stream) != hipSuccess)
                 return TNRD_ERR_HIP;
             const RedJob jobs[RED_JOBS] = {
                 {w.dk_part, grad_filters + (size_t)ts * m->Nk * kk, gp.tiles, (int)(m->Nk * kk), -1.f, 0},

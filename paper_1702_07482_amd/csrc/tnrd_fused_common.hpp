@@ -14,6 +14,7 @@ typedef short short4v __attribute__((ext_vector_type(4)));
 typedef _Float16 half4v __attribute__((ext_vector_type(4)));
 typedef float float2v __attribute__((ext_vector_type(2)));
 typedef int int2v __attribute__((ext_vector_type(2)));
+typedef int int4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 // Operand types of the 16x16x16 MFMAs used by the mixed-precision path
@@ -271,7 +272,7 @@ struct FusedIO {
     const float *u_cur;   // input gradient: u_t
     const float *g_cur;   // input gradient: g_t = dl/du_t
     float *za;            // input gradient, optional: z = K u and a = K e at the tile's own
-                          // pixels, layout of za_index()
+                          // pixels, layout of za_index() (BF16 words with BF16 operands)
     int react;            // tnrd_reaction of the stage
     float proj_c;         // projected reaction: threshold c
     const float *prep;    // polynomial form: the stage's prepared table (and FP32 operands),
@@ -294,6 +295,16 @@ __host__ __device__ inline int za_stride(int nk) { return 8 * ((nk + 3) / 4); }
 __host__ __device__ inline size_t za_index(size_t pix, int nk, int f)  // z; a at + 4
 {
     return pix * za_stride(nk) + 8 * (f >> 2) + (f & 3);
+}
+// With BF16 operands the export holds BF16 words (rounded to nearest even) at
+// the same positions counted in 2-byte words: z and a as the BF16 filter-bank
+// GEMMs produce them, in half the bytes.  Every other precision exports FP32
+// (FP16's exponent range would not hold z).
+__host__ __device__ inline bool za_is_bf16(int prec) { return prec == PREC_BF16; }
+__device__ __forceinline__ float za_value(float x) { return x; }
+__device__ __forceinline__ float za_value(unsigned short h)
+{
+    return __builtin_bit_cast(float, (unsigned)h << 16);
 }
 
 enum FusedMode { MODE_FWD = 0, MODE_BWD_INPUT = 1 };

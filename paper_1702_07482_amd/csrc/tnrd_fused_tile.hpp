@@ -611,13 +611,30 @@ __device__ __forceinline__ void fused_tile(
         // pixel is own to exactly one tile), stored before anything else of the
         // block, when the fewest registers are live
         if (BWD && io.za && valid) {
-            float *q = io.za + za_index((size_t)(ty0 + e) * W + xi, Nk, 4 * g);
+            const size_t zi = za_index((size_t)(ty0 + e) * W + xi, Nk, 4 * g);
+            if constexpr (PREC == PREC_BF16) {
+                // BF16 words: the quad's four z and four a (unscaled) in one 16-byte store
+                unsigned short *q = reinterpret_cast<unsigned short *>(io.za) + zi;
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
-                if (16 * mb + 4 * g < Nk) {
-                    *reinterpret_cast<floatx4 *>(q + 8 * 4 * mb) = c1[mb];
-                    *reinterpret_cast<floatx4 *>(q + 8 * 4 * mb + 4) = ca[mb];
-                }
+                for (int mb = 0; mb < NMB; ++mb)
+                    if (16 * mb + 4 * g < Nk) {
+                        floatx4 av = ca[mb];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) av[i] *= einv;
+                        const MV zb = MX::cvt4(c1[mb]), ab = MX::cvt4(av);
+                        *reinterpret_cast<int4v *>(q + 32 * mb) =
+                            int4v{__builtin_bit_cast(int2v, zb)[0], __builtin_bit_cast(int2v, zb)[1],
+                                  __builtin_bit_cast(int2v, ab)[0], __builtin_bit_cast(int2v, ab)[1]};
+                    }
+            } else {
+                float *q = io.za + zi;
+#pragma unroll
+                for (int mb = 0; mb < NMB; ++mb)
+                    if (16 * mb + 4 * g < Nk) {
+                        *reinterpret_cast<floatx4 *>(q + 8 * 4 * mb) = c1[mb];
+                        *reinterpret_cast<floatx4 *>(q + 8 * 4 * mb + 4) = ca[mb];
+                    }
+            }
         }
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) {
@@ -786,7 +803,10 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     ii.out = io.out ? io.out + img * plane : nullptr;
     ii.u_cur = io.u_cur ? io.u_cur + img * plane : nullptr;
     ii.g_cur = io.g_cur ? io.g_cur + img * plane : nullptr;
-    ii.za = io.za ? io.za + img * plane * za_stride(Nk) : nullptr;
+    ii.za = !io.za ? nullptr
+            : PREC == PREC_BF16
+                ? reinterpret_cast<float *>(reinterpret_cast<unsigned short *>(io.za) + img * plane * za_stride(Nk))
+                : io.za + img * plane * za_stride(Nk);
     const size_t sl = (size_t)io.xt.sl;
     ii.x_out = io.x_out + ((size_t)img * tiles_per_img + trem) * sl;
     ii.x_prev = io.x_prev ? io.x_prev + (size_t)img * tiles_per_img * sl : nullptr;
@@ -998,7 +1018,7 @@ inline hipError_t launch_fused(const StageArgs &s, int th, int tw, hipStream_t s
     io.out = s.u_next;
     io.u_cur = s.u_cur;
     io.g_cur = s.g_cur;
-    io.za = MODE == MODE_BWD_INPUT && PREC == PREC_F32 ? s.za : nullptr;
+    io.za = MODE == MODE_BWD_INPUT && (PREC == PREC_F32 || PREC == PREC_BF16) ? s.za : nullptr;
     io.react = s.react;
     io.proj_c = s.proj_c;
     io.prep = s.prep;

@@ -68,8 +68,9 @@ struct StageArgs {
     int poly;             // fused kernel: the polynomial influence form may be used
     int react = 0;        // tnrd_reaction of the model
     float proj_c = 1.f;   // projected reaction: threshold c
-    float *za = nullptr;  // input-gradient mode, FP32: if set, z = K u and a = K e at every
-                          // pixel (za_index layout), the parameter-gradient kernels' input
+    float *za = nullptr;  // input-gradient mode, FP32 or BF16 operands: if set, z = K u and
+                          // a = K e at every pixel (za_index layout; BF16 words with BF16
+                          // operands), the parameter-gradient kernels' input
     const float *prep = nullptr;  // polynomial form: this stage's block written by fused_prep
                                   // (phi table in the forward, d phi / ds in the input-gradient
                                   // mode; FP32 operands use its filter block too); required there
