@@ -38,12 +38,13 @@
 // scaled by a per-tile power of two (max |e| -> 2^10, FP16's normal range)
 // that is undone in FP32 on dK and on the exported a.  With BF16, z and a are
 // the input-gradient kernel's (its BF16 GEMMs; z is then where the BF16
-// forward evaluated phi), loaded from its BF16 export.  With FP16 (and at a
-// first stage without dl/du_0), k_bwd_params computes them: a = K e on the
-// 16x16x16 instruction (the transposed bank, k = 16 taps per step) and
-// z = K u on the FP32 instruction, since u carries a large mean that 8 or 11
-// mantissa bits of u or of k would move z by several units.  The influence
-// function and dlambda stay FP32.
+// forward evaluated phi), loaded from its BF16 export.  With FP16, and at a
+// first stage without dl/du_0, k_bwd_params computes them: a = K e on the
+// 16x16x16 instruction (the transposed bank, k = 16 taps per step), and z = K u
+// on the same BF16 instruction with BF16 operands, or on the FP32 instruction
+// with FP16 operands, since u carries a large mean that 11 mantissa bits of u
+// or of k would move z by several units.  The influence function and dlambda
+// stay FP32.
 //
 // k_bwd_dw scatters a_i G_j(z_i) into per-wave histograms, each lane working
 // on one filter and owning its column (a filter has several lanes, each with a
@@ -490,20 +491,28 @@ k_bwd_params(
             if (yi >= H) break;
 #pragma unroll 1
             for (int cb = 0; cb < NBW; ++cb) {
-                // A operands of K u (FP32, 4 taps per k-step) and of K e (scaled, 16
-                // taps per k-step) at pixel j of the block
+                // A operands of K u (FP16 operands: FP32, 4 taps per k-step; BF16:
+                // BF16, 16 taps per k-step, as the input-gradient kernel's z of the
+                // other stages) and of K e (scaled, 16 taps per k-step) at pixel j
                 const float *ubase = su + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
                 const float *ebase = se + (y + 2 * R) * L.ldw + 16 * cb + j + 2 * R;
-                float bu[KS1];
+                constexpr bool ZB = PREC == PREC_BF16;
+                float bu[ZB ? 1 : KS1];
+                if constexpr (!ZB) {
 #pragma unroll
-                for (int s = 0; s < KS1; ++s) bu[s] = ubase[-off1[s]];
-                MV ae[KSH];
+                    for (int s = 0; s < KS1; ++s) bu[s] = ubase[-off1[s]];
+                }
+                MV ae[KSH], au[ZB ? KSH : 1];
 #pragma unroll
                 for (int s = 0; s < KSH; ++s) {
-                    floatx4 xe;
+                    floatx4 xe, xu;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) xe[i] = escale * ebase[-offm[s][i]];
+                    for (int i = 0; i < 4; ++i) {
+                        xe[i] = escale * ebase[-offm[s][i]];
+                        if constexpr (ZB) xu[i] = ubase[-offm[s][i]];
+                    }
                     ae[s] = MX::cvt4(xe);
+                    if constexpr (ZB) au[s] = MX::cvt4(xu);
                 }
                 // A operands of the dK contraction: rows = taps 16 mt + j, k = the
                 // block's pixels 4 g + i: scaled ebar, and ubar as hi + lo
@@ -527,13 +536,19 @@ k_bwd_params(
 #pragma unroll
                 for (int nb = 0; nb < NMB; ++nb) {
                     floatx4 accz = floatx4{0.f, 0.f, 0.f, 0.f}, acca = floatx4{0.f, 0.f, 0.f, 0.f};
-                    float bf[KS1];
-                    load_bf(nb, bf);
+                    if constexpr (!ZB) {
+                        float bf[KS1];
+                        load_bf(nb, bf);
 #pragma unroll
-                    for (int s = 0; s < KS1; ++s)
-                        accz = __builtin_amdgcn_mfma_f32_16x16x4f32(bu[s], bf[s], accz, 0, 0, 0);
+                        for (int s = 0; s < KS1; ++s)
+                            accz = __builtin_amdgcn_mfma_f32_16x16x4f32(bu[s], bf[s], accz, 0, 0, 0);
+                    }
 #pragma unroll
-                    for (int s = 0; s < KSH; ++s) acca = MX::mfma(ae[s], smb[(nb * KSH + s) * 64 + lane], acca);
+                    for (int s = 0; s < KSH; ++s) {
+                        const MV kb = smb[(nb * KSH + s) * 64 + lane];
+                        if constexpr (ZB) accz = MX::mfma(au[s], kb, accz);
+                        acca = MX::mfma(ae[s], kb, acca);
+                    }
                     // influence, export (a unscaled), and the dK operands v, h (scaled) in place
                     const float *row = stab + nb * 16 * L.t_pitch + j;
                     const int fi = 16 * nb + j;
@@ -723,15 +738,14 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
         ZT zn[U], an[U];
         const ZT *zl = za + za_index((size_t)p0, Nk, fi);
         const unsigned zst = (unsigned)za_stride(Nk);
+        // raw words; a pixel past p1 is masked when its step is binned
         auto load = [&](int kb) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int pl = sub + ns * (kb + u);
-                const bool in = pl < npix;
-                const ZT *qp = zl + (size_t)((unsigned)(in ? pl : 0) * zst);
-                const ZT zz = qp[0], aa = qp[4];
-                zn[u] = zz;
-                an[u] = in ? aa : ZT(0);
+                const ZT *qp = zl + (size_t)((unsigned)(pl < npix ? pl : 0) * zst);
+                zn[u] = qp[0];
+                an[u] = qp[4];
             }
         };
         load(0);
@@ -740,7 +754,7 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 zc[u] = za_value(zn[u]);
-                ac[u] = za_value(an[u]);
+                ac[u] = sub + ns * (kb + u) < npix ? za_value(an[u]) : 0.f;
             }
             load(kb + U);
 #pragma unroll
@@ -756,15 +770,23 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
                 float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
                 float qi = __builtin_amdgcn_exp2f(-rb.rho_log2e * d);
                 float *hrow = hist + (int)jr * 64;
+                // the pixel's 2W + 1 bins are read together (one wait for all of them)
+                // while its Gaussians are formed, then written back
+                float hv[2 * RBF_WIN + 1];
+#pragma unroll
+                for (int m = -RBF_WIN; m <= RBF_WIN; ++m) hv[m + RBF_WIN] = hrow[64 * m];
+                __builtin_amdgcn_sched_barrier(0);
                 float up = a * E0, dn = a * E0;
-                hrow[0] += up * rb.c[RBF_WIN];
+                hv[RBF_WIN] = fmaf(up, rb.c[RBF_WIN], hv[RBF_WIN]);
 #pragma unroll
                 for (int m = 1; m <= RBF_WIN; ++m) {
                     up *= q;
                     dn *= qi;
-                    hrow[64 * m] += up * rb.c[RBF_WIN + m];
-                    hrow[-64 * m] += dn * rb.c[RBF_WIN - m];
+                    hv[RBF_WIN + m] = fmaf(up, rb.c[RBF_WIN + m], hv[RBF_WIN + m]);
+                    hv[RBF_WIN - m] = fmaf(dn, rb.c[RBF_WIN - m], hv[RBF_WIN - m]);
                 }
+#pragma unroll
+                for (int m = -RBF_WIN; m <= RBF_WIN; ++m) hrow[64 * m] = hv[m + RBF_WIN];
             }
         }
     }
