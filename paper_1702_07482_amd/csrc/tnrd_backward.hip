@@ -765,10 +765,10 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
                 float d = s - jr;
                 // beyond every centre by more than W spacings: nothing to add
                 const float a = fabsf(d) <= 0.5f ? ac[u] : 0.f;
-                // G_{jr+m} = E0 q^m c_m,  E0 = exp(-rho d^2/2),  q = exp(rho d)
-                float E0 = __builtin_amdgcn_exp2f(-0.5f * rb.rho_log2e * d * d);
-                float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
-                float qi = __builtin_amdgcn_exp2f(-rb.rho_log2e * d);
+                // G_{jr+m} = E q^(m+W) c_m,  E = exp(-rho d (d/2 + W)),  q = exp(rho d):
+                // one product chain from the lowest bin up, two exponentials
+                const float E = __builtin_amdgcn_exp2f(-rb.rho_log2e * d * fmaf(0.5f, d, (float)RBF_WIN));
+                const float q = __builtin_amdgcn_exp2f(rb.rho_log2e * d);
                 float *hrow = hist + (int)jr * 64;
                 // the pixel's 2W + 1 bins are read together (one wait for all of them)
                 // while its Gaussians are formed, then written back
@@ -776,14 +776,11 @@ __global__ void __launch_bounds__(64 * NW) k_bwd_dw(
 #pragma unroll
                 for (int m = -RBF_WIN; m <= RBF_WIN; ++m) hv[m + RBF_WIN] = hrow[64 * m];
                 __builtin_amdgcn_sched_barrier(0);
-                float up = a * E0, dn = a * E0;
-                hv[RBF_WIN] = fmaf(up, rb.c[RBF_WIN], hv[RBF_WIN]);
+                float gm = a * E;
 #pragma unroll
-                for (int m = 1; m <= RBF_WIN; ++m) {
-                    up *= q;
-                    dn *= qi;
-                    hv[RBF_WIN + m] = fmaf(up, rb.c[RBF_WIN + m], hv[RBF_WIN + m]);
-                    hv[RBF_WIN - m] = fmaf(dn, rb.c[RBF_WIN - m], hv[RBF_WIN - m]);
+                for (int k = 0; k <= 2 * RBF_WIN; ++k) {
+                    hv[k] = fmaf(gm, rb.c[k], hv[k]);
+                    if (k < 2 * RBF_WIN) gm *= q;
                 }
 #pragma unroll
                 for (int m = -RBF_WIN; m <= RBF_WIN; ++m) hrow[64 * m] = hv[m + RBF_WIN];
