@@ -1,8 +1,9 @@
 """Mixed precision: the filter-bank contractions (K u and the K^T GEMM of the
 forward and of the input-gradient pass; K e and the dK contraction of the
 parameter-gradient pass) with BF16 or FP16 operands and FP32 accumulation; the
-influence function, the prox and z = K u of the parameter-gradient pass stay
-FP32 (with BF16 operands the influence comes from cubics on half intervals,
+influence function and the prox stay FP32.  The parameter gradients take z = K u
+on FP32 operands with FP16, and with BF16 the input-gradient pass's BF16 z, kept
+as BF16 words (with BF16 operands the influence comes from cubics on half intervals,
 whose interpolation error, below 2.6e-4 of the largest RBF weight for phi and
 6.7e-4 for d phi / ds, is a tenth of the BF16 rounding its values get for the
 K^T GEMM).  Errors against the FP64 oracle are bounded per output, and the
@@ -143,6 +144,30 @@ def test_mixed_backward_input_gradient(prec, want_u0):
             zip(names, out, (rK, rW, rl, rg))}
     bounds = dict(zip(names, bound))
     print(f"prec={prec} want_u0={want_u0} backward rel errors {errs} bounds {bounds}", flush=True)
+    for n in names:
+        assert errs[n] <= bounds[n], (n, errs, bounds)
+
+
+@pytest.mark.parametrize("nk", [13, 40])
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_backward_uneven_filter_counts(prec, nk):
+    """Filter counts that fill neither a 16-filter block nor the last 4-filter
+    quad of the z/a export (BF16 words with BF16 operands), within the derived
+    bound of the FP64 oracle."""
+    print(f"[mixed bwd prec {prec} nk {nk}]", flush=True)
+    g = np.random.default_rng(4400 + nk)
+    m = synth.make_model(3, nk, 7, g)
+    u, f = synth.make_pair(37, 45, 1, config_id=5, index=nk)
+    (rK, rW, rl, rg), gT, bound = _backward_bound(f, u, m, prec)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(prec=prec)
+    fd = _dev(f)
+    _, states = tnrd.forward(fd, dm, want_states=True, opts=o)
+    out = tnrd.backward(fd, dm, states, _dev(gT), opts=o, want_u0=True)
+    names = ["dK", "dW", "dlam", "g0"]
+    errs = {n: rel_inf(a.cpu().numpy(), b) for n, a, b in zip(names, out, (rK, rW, rl, rg))}
+    bounds = dict(zip(names, bound))
+    print(f"rel errors {errs} bounds {bounds}", flush=True)
     for n in names:
         assert errs[n] <= bounds[n], (n, errs, bounds)
 
