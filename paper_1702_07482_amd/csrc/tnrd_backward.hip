@@ -34,9 +34,9 @@
 // runs on v_mfma_f32_16x16x16_{bf16,f16} with FP32 accumulation (k = the
 // block's 16 pixels in one step, whose B operand is the block's v or phi'a
 // quad, pixels 4g .. 4g+3 of filter j, converted once), and ubar enters the
-// second dK term as a BF16/FP16 pair ubar = hi + lo (two MFMAs).  e enters
-// scaled by a per-tile power of two (max |e| -> 2^10, FP16's normal range)
-// that is undone in FP32 on dK and on the exported a.  With BF16, z and a are
+// second dK term as a BF16/FP16 pair ubar = hi + lo (two MFMAs).  With FP16, e
+// enters scaled by a per-tile power of two (max |e| -> 2^10, FP16's normal
+// range) that is undone in FP32 on dK and on the exported a.  With BF16, z and a are
 // the input-gradient kernel's (its BF16 GEMMs; z is then where the BF16
 // forward evaluated phi), loaded from its BF16 export.  With FP16, and at a
 // first stage without dl/du_0, k_bwd_params computes them: a = K e on the
@@ -268,16 +268,18 @@ k_bwd_params(
                 if (base + k * THREADS + tid < n) stab[base + k * THREADS + tid] = v[k];
         }
     }
-    // mixed: e is scaled by 2^(10 - ilogb(max |e|)) before its conversion (FP16's
-    // normal range is 2^-14 .. 65504; |K e| <= 7 max|e| for unit-norm 7x7 filters)
+    // FP16 operands: e is scaled by 2^(10 - ilogb(max |e|)) before its conversion
+    // (FP16's normal range is 2^-14 .. 65504; |K e| <= 7 max|e| for unit-norm 7x7
+    // filters).  BF16 has FP32's exponent range and needs no scale.
+    constexpr bool ESCALE = PREC == PREC_F16;
     float escale = 1.f, einv = 1.f;
-    if (MIXED) {
+    if (ESCALE) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) emax = fmaxf(emax, __shfl_xor(emax, o));
         if (lane == 0) sdl[wave] = emax;
     }
     __syncthreads();
-    if (MIXED) {
+    if (ESCALE) {
         float mx = 0.f;
         for (int w = 0; w < NW; ++w) mx = fmaxf(mx, sdl[w]);
         if (mx > 0.f && isfinite(mx)) {

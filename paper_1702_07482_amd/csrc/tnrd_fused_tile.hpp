@@ -312,11 +312,12 @@ __device__ __forceinline__ void fused_tile(
     if (!PREP_OPS) __syncthreads();  // the staged filters (and Gaussian table)
 
     // Mixed-precision input gradient: e, a = K e and phi' a go through BF16/FP16
-    // operands with a power-of-two tile scale that puts max|e| at 2^10 (FP16's
+    // operands.  With FP16 a power-of-two tile scale puts max|e| at 2^10 (FP16's
     // normal range starts at 2^-14 and ends below 2^16; |K e| <= 7 max|e| for
-    // unit-norm 7x7 filters), undone in FP32 when g_{t-1} is formed.
+    // unit-norm 7x7 filters), undone in FP32 when g_{t-1} is formed; BF16 has
+    // FP32's exponent range and needs none.
     float escale = 1.f, einv = 1.f;
-    if (BWD && PREC != PREC_F32) {
+    if (BWD && PREC == PREC_F16) {
         float wmax = emax;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, o));
@@ -708,7 +709,7 @@ __device__ __forceinline__ void fused_tile(
     // row e feeds ring row e - a with its tap row a) is slab row o + 2R; slab
     // column dx is P column dx.  Tap rows written by source rows outside
     // [0, e_hi) count as zero.  The input-gradient mode's slab holds the force
-    // in the gradient's own scale (BF16/FP16: einv undoes the tile's e scale).
+    // in the gradient's own scale (FP16: einv undoes the tile's e scale).
     const int sw = Tw + 2 * R;
     const int sw_own = min(Tw, W - tx0) + 2 * R;
     auto export_rows = [&](int o0, int o1) {
