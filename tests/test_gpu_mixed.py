@@ -64,6 +64,25 @@ def test_mixed_forward_against_oracle(prec):
     assert dpsnr <= 1e-2
 
 
+@pytest.mark.parametrize("tile", [(32, 32, 4), (64, 32, 8), (32, 48, 4), (128, 32, 4)])
+def test_bf16_forward_tiles(tile):
+    """The BF16 forward on requested tiles and wave counts (4 and 8 waves, 2 and 3
+    sixteen-pixel blocks per row), ragged at both edges, against the oracle
+    within the BF16 bound."""
+    th, tw, nw = tile
+    print(f"[bf16 forward tile {tile}]", flush=True)
+    m = synth.config_model(5)
+    u, f = synth.make_pair(150, 137, 1, config_id=5, index=7)
+    ref = oracle.forward(f, m)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(prec=tnrd.PREC_BF16)
+    o.tile_h, o.tile_w, o.wg_waves = th, tw, nw
+    got = tnrd.forward(_dev(f), dm, opts=o).cpu().numpy()[0]
+    err = rel_inf(got, ref)
+    print(f"rel_inf={err:.2e}", flush=True)
+    assert err <= BOUND[tnrd.PREC_BF16]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_mixed_full_size_sampled(prec):
     """8 x 2048 x 2048 (the mixed workload): sampled pixels against the oracle on
