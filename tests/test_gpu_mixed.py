@@ -191,6 +191,45 @@ def test_mixed_backward_uneven_filter_counts(prec, nk):
         assert errs[n] <= bounds[n], (n, errs, bounds)
 
 
+def _reaction_case(reaction):
+    """(model, clean, noisy) of the projected (Sec. 3.1, c = 1) or quadratic
+    (Sec. 2.2.1) reaction with 7x7 filters, the size the mixed kernels take."""
+    if reaction == "l2":
+        m = synth.config_model(7)  # 5 stages x 48 7x7, lambda 0.1
+        u, f = synth.make_gaussian_pair(44, 52, 25.0, config_id=7, index=61)
+        return m, u, f
+    g = np.random.default_rng(6210)
+    m = synth.make_model(3, 24, 7, g)
+    m["reaction"], m["proj_c"] = "projected", 1.0
+    u, f = synth.make_pair(44, 52, 1, config_id=2, index=62, peak=12.0)
+    return m, u, f
+
+
+@pytest.mark.parametrize("reaction", ["projected", "l2"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_other_reactions(prec, reaction):
+    """The projected and quadratic reactions with BF16/FP16 filter-bank operands:
+    the forward within the forward bound, and dK, dW, dlambda and dl/du_0 within
+    the derived bound D_k + D_s of the FP64 oracle."""
+    print(f"[mixed {reaction} prec {prec}]", flush=True)
+    m, u, f = _reaction_case(reaction)
+    ref = oracle.forward(f, m)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(prec=prec)
+    fd = _dev(f)
+    got, states = tnrd.forward(fd, dm, want_states=True, opts=o)
+    ferr = rel_inf(got.cpu().numpy()[0], ref)
+    (rK, rW, rl, rg), gT, bound = _backward_bound(f, u, m, prec)
+    out = tnrd.backward(fd, dm, states, _dev(gT), opts=o, want_u0=True)
+    names = ["dK", "dW", "dlam", "g0"]
+    errs = {n: rel_inf(a.cpu().numpy(), b) for n, a, b in zip(names, out, (rK, rW, rl, rg))}
+    bounds = dict(zip(names, bound))
+    print(f"forward rel_inf={ferr:.2e}; backward rel errors {errs} bounds {bounds}", flush=True)
+    assert ferr <= BOUND[prec]
+    for n in names:
+        assert errs[n] <= bounds[n], (n, errs, bounds)
+
+
 def test_fp16_validate_rejects_values_beyond_its_range():
     """FP16 operands hold the states unscaled; validate refuses f >= 2^15 for
     them (TNRD_ERR_UNSUPPORTED), and accepts the same image in BF16 and FP32,
