@@ -31,7 +31,7 @@ import torch
 
 import oracle
 from paper_1702_07482_amd import synth, tnrd
-from tests.helpers import oracle_uT_at, rel_inf
+from tests.helpers import crop_window, oracle_uT_at, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -140,6 +140,63 @@ def _backward_bound(f, u, m, prec):
         outs = oracle.backward(f, m, sts, gs)
         ds = [max(d, rel_inf(a, b)) for d, a, b in zip(ds, outs, ref)]
     return ref, gT, [a + b for a, b in zip(dk, ds)]
+
+
+def _bound_given_g(f, m, gT, prec):
+    """The oracle's gradients for dl/du_T = gT and the derived bound D_k + D_s
+    (as _backward_bound, with gT given)."""
+    _, st = oracle.forward(f, m, want_states=True)
+    ref = oracle.backward(f, m, st, gT)
+    mk = dict(m)
+    mk["filters"] = _round_to(m["filters"], prec)
+    _, stk = oracle.forward(f, mk, want_states=True)
+    dk = [rel_inf(a, b) for a, b in zip(oracle.backward(f, mk, stk, gT), ref)]
+    up = UNIT_ROUNDOFF[prec]
+    rng = np.random.default_rng(1703)
+    ds = [0.0] * 4
+    for _ in range(2):
+        sts = st * (1.0 + up * rng.uniform(-1.0, 1.0, size=st.shape))
+        sts[0] = st[0]
+        gs = gT * (1.0 + up * rng.uniform(-1.0, 1.0, size=gT.shape))
+        ds = [max(d, rel_inf(a, b)) for d, a, b in zip(ds, oracle.backward(f, m, sts, gs), ref)]
+    return ref, [a + b for a, b in zip(dk, ds)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_backward_full_size_localized(prec):
+    """8 x 2048 x 2048 (the mixed workload) with the loss gradient on one pixel:
+    every gradient comes from that pixel's receptive field, which the oracle
+    covers with a crop of radius T (k - 1); dK, dW, dlambda and dl/du_0 on the
+    crop within the derived bound computed there, and dl/du_0 exactly zero
+    outside it."""
+    m = synth.config_model(5)
+    pairs = [synth.make_pair(2048, 2048, 1, config_id=5, index=n) for n in range(8)]
+    f = np.stack([p[1] for p in pairs])
+    del pairs
+    n, y, x = 5, 1500, 700
+    print(f"[mixed full-size localized prec {prec} n={n} y={y} x={x}]", flush=True)
+    gT = np.zeros(f.shape, dtype=np.float32)
+    gT[n, y, x] = 1.0
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(prec=prec)
+    fd = _dev(f)
+    _, states = tnrd.forward(fd, dm, want_states=True, opts=o)
+    dK, dW, dl, g0 = tnrd.backward(fd, dm, states, _dev(gT), opts=o, want_u0=True)
+    g0 = g0.cpu().numpy()
+    radius = m["T"] * (m["ks"] - 1)
+    y0, y1 = crop_window(y, 2048, radius)
+    x0, x1 = crop_window(x, 2048, radius)
+    (rK, rW, rl, rg), bound = _bound_given_g(f[n, y0:y1, x0:x1], m, gT[n, y0:y1, x0:x1], prec)
+    names = ["dK", "dW", "dlam", "g0"]
+    got = [dK.cpu().numpy(), dW.cpu().numpy(), dl.cpu().numpy(), g0[n, y0:y1, x0:x1]]
+    errs = {k: rel_inf(a, b) for k, a, b in zip(names, got, (rK, rW, rl, rg))}
+    bounds = dict(zip(names, bound))
+    print(f"rel errors {errs} bounds {bounds}", flush=True)
+    outside = g0.copy()
+    outside[n, y0:y1, x0:x1] = 0.0
+    assert not outside.any()
+    for k in names:
+        assert errs[k] <= bounds[k], (k, errs, bounds)
 
 
 @pytest.mark.parametrize("want_u0", [True, False])
