@@ -739,7 +739,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the filter shards by image with no exchange; see the design notes)",
+              "(images are independent: several GPUs would each run a share of them with no "
+              "exchange in the forward and one small all-reduce of the parameter gradients)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -28,7 +28,7 @@
  *   psi = l (u - f): the Gaussian-denoising reaction of the TNRD framework):
  *     u_t = u_{t-1} - ( x + l (u_{t-1} - f) )
  *
- * Readings of points the paper leaves open (listed with reasons in the design notes):
+ * Readings of points the paper leaves open, each with its reason:
  *   - u_0 = f (the paper leaves the initial state I_0 open);
  *   - K_i is a true convolution: the kernel is flipped (the paper defines k*u as
  *     2-D convolution and bar k as k rotated by 180 degrees);

@@ -29,7 +29,7 @@ def _cuda(a):
 def test_driver_gradients_match_oracle():
     """dl/dK, dl/dW and dl/dbeta = lambda dl/dlambda of the loss 1/2 ||u_T - u_gt||^2
     against the oracle, and dl/dbeta against lambda times the C ABI's dl/dlambda on
-    the same inputs (the driver's chain rule)."""
+    the same inputs (the training driver's chain rule)."""
     print("[train grads]", flush=True)
     m, u, f = _problem(seed=31)
     m["lam"] = np.array([1.0, 1.0], dtype=np.float32)
