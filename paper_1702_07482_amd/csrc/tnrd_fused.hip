@@ -301,7 +301,7 @@ static hipError_t fused_dispatch(const StageArgs &s, hipStream_t stream)
                                         s.waves, MODE, poly);
     if (!p.ok) return hipErrorInvalidValue;
     // BF16 operands read the cubic half-interval table (fused_prep_form)
-    const int rbfm = p.rbfm == RBF_POLY && fused_prep_form(s) ? RBF_POLY3 : p.rbfm;
+    const int rbfm = p.rbfm == RBF_POLY && (fused_prep_form(s) & 2) ? RBF_POLY3 : p.rbfm;
     if (MODE == MODE_BWD_INPUT) return fused_launch_bwd(s, p.th, p.tw, p.nb, p.nw, rbfm, stream);
     if (s.prec == PREC_BF16 || s.prec == PREC_F16)
         return fused_launch_fwd_mixed(s, p.th, p.tw, p.nb, p.nw, rbfm, stream);

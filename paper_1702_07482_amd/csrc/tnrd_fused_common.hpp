@@ -118,6 +118,12 @@ constexpr float POLY_OFF_MASKED = 1048576.f;
 constexpr int POLY3_NC = 4;
 constexpr int POLY3_NM = 2 * POLY_MW + 1;
 
+// Prepared-block form bits (beside bit 0, d phi / ds, and bit 1, the cubic
+// half-interval table): the operand part holds the mixed kernels' filter
+// operands converted to BF16 or FP16 instead of the FP32 kernels' ones.
+constexpr int PREP_MIXED_BF16 = 8;
+constexpr int PREP_MIXED_F16 = 16;
+
 // Influence evaluation of the fused stage kernel.
 enum RbfMethod { RBF_HORNER = 0, RBF_POLY = 1, RBF_POLY3 = 2 };
 

@@ -128,6 +128,8 @@ __device__ __forceinline__ void fused_tile(
     // (k_prep_stage); with FP32 operands the per-lane filter operands too
     constexpr bool PREP_TAB = POLY;
     constexpr bool PREP_OPS = POLY && PREC == PREC_F32;
+    // the mixed kernels' BF16/FP16 filter operands come prepared as well
+    constexpr bool PREP_MOPS = POLY && PREC != PREC_F32;
     const float *__restrict__ u_prev = io.u_prev;
     const float *__restrict__ f = io.f;
     using G = Geo<KS>;
@@ -161,7 +163,7 @@ __device__ __forceinline__ void fused_tile(
     // (1) the stage's filters, staged in the P area (free until the first
     // block's partials), unless the operands come prepared
     float *sf = sp;
-    if (!PREP_OPS) {
+    if (!PREP_OPS && !PREP_MOPS) {
         const int nf = Nk * KK;
         for (int base = 0; base < nf; base += 8 * THREADS) {
             float v[8];
@@ -309,7 +311,7 @@ __device__ __forceinline__ void fused_tile(
             if (k < L.t_size) __builtin_amdgcn_global_load_lds(io.prep + k, stab + c * 256, 16, 0, 0);
         }
     }
-    if (!PREP_OPS) __syncthreads();  // the staged filters (and Gaussian table)
+    if (!PREP_OPS && !PREP_MOPS) __syncthreads();  // the staged filters (and Gaussian table)
 
     // Mixed-precision input gradient: e, a = K e and phi' a go through BF16/FP16
     // operands.  With FP16 a power-of-two tile scale puts max|e| at 2^10 (FP16's
@@ -355,7 +357,7 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
         for (int s = 0; s < KS1; ++s) {
             int fi = 16 * mb + j, t = 4 * s + g;
-            if (!PREP_OPS) a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
+            if (!PREP_OPS && PREC == PREC_F32) a1[mb][s] = (fi < Nk && t < KK) ? sf[fi * KK + t] : 0.f;
         }
     // GEMM2 A operand: lane (g, j) supplies slot row j of block mb2, i.e.
     // register R' = 4 mb2 + (j & 3) in lane group j >> 2, and k-row g of k-step s,
@@ -373,7 +375,8 @@ __device__ __forceinline__ void fused_tile(
         for (int s = 0; s < KS2; ++s) {
             int fi = 16 * (s >> 2) + 4 * g + (s & 3);
             const int ta = slot_a[mb2], tb = slot_b[mb2];
-            if (!PREP_OPS) a2[mb2][s] = (fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f;
+            if (!PREP_OPS && PREC == PREC_F32)
+                a2[mb2][s] = (fi < Nk && ta < KS && tb < KS) ? sf[fi * KK + ta * KS + tb] : 0.f;
         }
 
     // mixed precision: 16-wide k-steps, operands converted once to BF16/FP16
@@ -389,7 +392,20 @@ __device__ __forceinline__ void fused_tile(
     // operand reads take compile-time offsets from one per-lane base.  Pad
     // slots and row 7 carry zero weight.
     static_assert(!MIXED || (KS == 7 && KSH == 4), "the mixed tap grid is laid out for 7 x 7 filters");
-    if (MIXED) {
+    if constexpr (PREP_MOPS) {
+        // prepared (k_prep_stage): operand v = 2 k4 + h of lane l in quad k4, a1m first
+        constexpr int NV = NMB * KSH + MB2 * NMB, NQM = (NV + 1) / 2;
+        const int4v *opq = reinterpret_cast<const int4v *>(io.prep + L.t_size) + lane;
+        int4v q[NQM];
+#pragma unroll
+        for (int k4 = 0; k4 < NQM; ++k4) q[k4] = opq[64 * k4];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const MV op = __builtin_bit_cast(MV, int2v{q[v >> 1][2 * (v & 1)], q[v >> 1][2 * (v & 1) + 1]});
+            if (v < NMB * KSH) a1m[v / KSH][v % KSH] = op;
+            else a2m[(v - NMB * KSH) / NMB][(v - NMB * KSH) % NMB] = op;
+        }
+    } else if (MIXED) {
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll

@@ -133,8 +133,12 @@ size_t fused_prep_floats(int ks, int nk, int nrbf);
 // half-interval form (the BF16 kernels, fused_prep_form)
 hipError_t fused_prep(const float *filt, const float *rbfw, int T, int ks, int nk, const RbfGrid &grid,
                       int form, float *prep, hipStream_t stream);
-// The table form bit of the kernels that read stage s's prepared blocks.
-inline int fused_prep_form(const StageArgs &s) { return s.prec == PREC_BF16 ? 2 : 0; }
+// The table form bit of the kernels that read stage s's prepared blocks, and the
+// operand format of the mixed kernels (their filter operands come prepared too).
+inline int fused_prep_form(const StageArgs &s)
+{
+    return s.prec == PREC_BF16 ? 2 | PREP_MIXED_BF16 : s.prec == PREC_F16 ? PREP_MIXED_F16 : 0;
+}
 // The same for stage 0 .. T-1 of every model of a batch (into BatchModel::prep).
 hipError_t batched_prep(const BatchArgs &a, int ks, int n_models, hipStream_t stream);
 // Whether a stage with these options runs the fused kernel's prepared form.

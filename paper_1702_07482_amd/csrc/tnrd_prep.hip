@@ -41,7 +41,9 @@ static size_t prep_stage_floats_t(int nrbf)
 // Thread idx of stage t: table interval (fi, q) for idx < 16 NMB ni (its 8
 // coefficients, plus the row's zero padding), then operand quad (k4, lane).
 // form: bit 0 = d phi / ds instead of phi, bit 1 = the cubic half-interval
-// form (two cubics per interval, floats 8 q .. 8 q + 7 of the row).
+// form (two cubics per interval, floats 8 q .. 8 q + 7 of the row); the
+// operand part holds the FP32 operands, or with PREP_MIXED_BF16/F16 the
+// mixed kernels' BF16/FP16 ones.
 template <int KS, int NMB>
 __device__ void prep_stage_body(const float *__restrict__ filt, const float *__restrict__ rbfw, int Nk,
                                 int Nrbf, const FusedRbf &rb, int form, float *__restrict__ out,
@@ -117,6 +119,49 @@ __device__ void prep_stage_body(const float *__restrict__ filt, const float *__r
     if (idx >= P::NQ * 64) return;
     const int k4 = idx >> 6, lane = idx & 63;
     const int g = lane >> 4, j = lane & 15;
+    if (form & (PREP_MIXED_BF16 | PREP_MIXED_F16)) {
+        // BF16/FP16 operands of the mixed kernels, lane-ordered: operand v = 2 k4 + h
+        // of lane l (four 16-bit words, element i in word i): GEMM1's a1m[mb][s]
+        // first (v < NMB KSH), then the K^T GEMM's a2m[mb2][mb]
+        constexpr int KSH = (KK + 15) / 16, NV = NMB * KSH + G2::MB2 * NMB;
+        if (KS != 7 || 2 * k4 >= NV) return;
+        unsigned wd[4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int v = 2 * k4 + h;
+            float x[4] = {0.f, 0.f, 0.f, 0.f};
+            if (v < NMB * KSH) {
+                // the 7 x 7 taps in a 7 x 8 grid with a pad column in front: slot
+                // 16 s + 4 g + i = tap row 2 s + (g >> 1), column 4 (g & 1) + i - 1
+                const int mb = v / KSH, s = v - mb * KSH;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int fi = 16 * mb + j, ta = 2 * s + (g >> 1), tb = 4 * (g & 1) + i - 1;
+                    if (fi < Nk && ta < KS && tb >= 0 && tb < KS) x[i] = filt[fi * KK + ta * KS + tb];
+                }
+            } else if (v < NV) {
+                // slot row j of block mb2 (as below), k-row g of k-step mb: filter 16 mb + 4 g + i
+                const int vv = v - NMB * KSH, mb2 = vv / NMB, mb = vv - mb2 * NMB;
+                const int Rr = 4 * mb2 + (j & 3);
+                const int tb = Rr < NREG ? Rr / HB : KS;
+                const int ta = 4 * (Rr % HB) + (j >> 2);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int fi = 16 * mb + 4 * g + i;
+                    if (fi < Nk && ta < KS && tb < KS) x[i] = filt[fi * KK + ta * KS + tb];
+                }
+            }
+            unsigned short hw[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                hw[i] = (form & PREP_MIXED_BF16) ? __builtin_bit_cast(unsigned short, (__bf16)x[i])
+                                                  : __builtin_bit_cast(unsigned short, (_Float16)x[i]);
+            wd[2 * h] = (unsigned)hw[0] | ((unsigned)hw[1] << 16);
+            wd[2 * h + 1] = (unsigned)hw[2] | ((unsigned)hw[3] << 16);
+        }
+        *reinterpret_cast<uint4 *>(out + L.t_size + 4 * (64 * k4 + lane)) = uint4{wd[0], wd[1], wd[2], wd[3]};
+        return;
+    }
     float v[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
