@@ -132,6 +132,37 @@ def test_c3_full_size_localized_gradient():
         _check(got, (dK, dW, dl, g0))
 
 
+@pytest.mark.parametrize("ks,nk,shape,N", [(7, 48, (45, 37), 1), (5, 24, (7, 9), 2), (7, 40, (96, 130), 1)])
+def test_input_gradient_is_a_symmetric_operator(ks, nk, shape, N):
+    """Adjoint identity of the GPU's own K and K^T (eq. derv1-1).  With the
+    quadratic reaction at lambda = 1 one stage maps u_0 to u_1 = f - sum_i K_i^T
+    phi_i(K_i u_0), whose Jacobian -sum_i K_i^T D_i K_i (D_i = diag phi_i'(K_i u_0))
+    is symmetric exactly when the kernels' K^T, the border fold included, is the
+    adjoint of their K.  The input gradient applies it: <J^T a, b> = <a, J^T b>
+    for random a, b, and the operator's size is checked so that the identity is
+    not carried by a vanishing term."""
+    print(f"[adjoint ks {ks} nk {nk} shape {shape} N {N}]", flush=True)
+    g = np.random.default_rng(9100 + ks + nk)
+    m = synth.make_model(1, nk, ks, g, w_std=2.0)
+    m["reaction"], m["proj_c"] = "l2", 1.0
+    f = np.stack([synth.make_gaussian_pair(*shape, 25.0, config_id=7, index=90 + n)[1] for n in range(N)])
+    dm = tnrd.DeviceModel.from_numpy(m)
+    fd = _dev(f)
+    _, states = tnrd.forward(fd, dm, want_states=True)
+    a = g.standard_normal(f.shape)
+    b = g.standard_normal(f.shape)
+    ja = tnrd.backward(fd, dm, states, _dev(a), want_u0=True)[3].cpu().numpy().astype(np.float64)
+    jb = tnrd.backward(fd, dm, states, _dev(b), want_u0=True)[3].cpu().numpy().astype(np.float64)
+    a = a.astype(np.float32).astype(np.float64)
+    b = b.astype(np.float32).astype(np.float64)
+    s1, s2 = float((ja * b).sum()), float((a * jb).sum())
+    scale = 0.5 * (np.abs(ja * b).sum() + np.abs(a * jb).sum())
+    print(f"<J^T a, b> = {s1:.6e}, <a, J^T b> = {s2:.6e}, rel {abs(s1 - s2) / scale:.2e}, "
+          f"|J^T a| / |a| = {np.linalg.norm(ja) / np.linalg.norm(a):.3f}", flush=True)
+    assert np.linalg.norm(ja) >= 0.05 * np.linalg.norm(a)
+    assert abs(s1 - s2) <= 1e-5 * scale
+
+
 def test_autograd_function_matches_backward():
     """TNRDFunction: loss.backward() fills filters/rbf_w/lam grads equal to the
     C-ABI backward with dl/du_T = 2 (u_T - u_gt) / n."""
