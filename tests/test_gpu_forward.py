@@ -264,3 +264,67 @@ def test_concurrent_calls_from_two_threads_on_two_streams():
             ref_t = tnrd.forward(fs[i], dm, opts=tnrd.default_opts(tile_h=24 + 8 * rep, tile_w=26))
             torch.testing.assert_close(u, ref_t.cpu(), rtol=0, atol=0)
             assert rel_inf(u.numpy(), ref[i].numpy()) <= 2e-5
+
+
+def _linear_influence_model(ks, nk, g, slope_std):
+    """One stage whose influence functions are linear: with weights w_ij = c_i mu_j on
+    the uniform Gaussian grid, phi_i(z) = sum_j c_i mu_j exp(-(z - mu_j)^2 / (2 sigma^2))
+    equals c_i sqrt(2 pi) sigma / step * z up to a relative 2 exp(-2 pi^2 sigma^2 /
+    step^2) (Poisson summation; about 5e-9 at sigma = step) while |z| stays well inside
+    the centres' span."""
+    m = synth.make_model(1, nk, ks, g)
+    mu = m["mu0"] + m["step"] * np.arange(m["Nrbf"])
+    c = g.normal(0.0, slope_std, size=nk)
+    m["rbf_w"] = (c[:, None] * mu[None, :])[None].astype(np.float32)
+    m["reaction"], m["proj_c"] = "l2", 1.0
+    return m
+
+
+ADJ_CASES = [(7, 48, (45, 37), 1), (5, 24, (7, 9), 2), (7, 40, (96, 130), 1)]
+ADJ_PATHS = [(tnrd.IMPL_SPLIT, tnrd.PREC_FP32), (tnrd.IMPL_FUSED, tnrd.PREC_FP32),
+             (tnrd.IMPL_FUSED, tnrd.PREC_BF16), (tnrd.IMPL_FUSED, tnrd.PREC_FP16)]
+ADJ_ROUNDOFF = {tnrd.PREC_FP32: 0.0, tnrd.PREC_BF16: 2.0 ** -8, tnrd.PREC_FP16: 2.0 ** -11}
+
+
+@pytest.mark.parametrize("impl,prec", ADJ_PATHS)
+@pytest.mark.parametrize("ks,nk,shape,N", ADJ_CASES)
+def test_forward_diffusion_is_a_symmetric_operator(ks, nk, shape, N, impl, prec):
+    """Adjoint identity of the forward kernels' own K and K^T (eq. the diffusion step).
+    With linear influences phi_i(z) = s_i z and the quadratic reaction (which vanishes
+    at u_0 = f), one stage maps f to u_1 = f - sum_i s_i K_i^T K_i f, so A f = f - u_1 is
+    symmetric exactly when the K^T applied to the influences (the per-tile transpose,
+    the exchange across tiles and the border fold) is the adjoint of K: <A a, b> =
+    <a, A b> for random a, b.  An unflipped K^T breaks it by about 0.2 relative.  FP32
+    paths: 1e-5 relative.  BF16/FP16 operands round the influences once per element
+    (relative u, 2^-8 and 2^-11 taken with margin) while K and K^T share one rounded
+    filter, so the asymmetry stays below 2 u sum_i |s_i| sum_p |(K_i a)_p (K_i b)_p|
+    plus the FP32 term; the input's hi + lo split (relative 2^-18) sits inside the
+    factor-two margin on u."""
+    if prec != tnrd.PREC_FP32 and ks != 7:
+        pytest.skip("BF16/FP16 operands are built for 7x7 filters")
+    print(f"[fwd adjoint ks {ks} nk {nk} shape {shape} N {N} impl {impl} prec {prec}]", flush=True)
+    g = np.random.default_rng(9300 + ks + nk)
+    m = _linear_influence_model(ks, nk, g, 1e-2)
+    if impl == tnrd.IMPL_FUSED and not _fused_available(m):
+        pytest.skip("fused kernel not built for this model")
+    slope = np.array([oracle.dphi(0.0, m["rbf_w"][0, i].astype(np.float64), m["mu0"], m["step"],
+                                  m["sigma"]) for i in range(nk)], dtype=np.float64).ravel()
+    a = (20.0 * g.standard_normal((N,) + shape)).astype(np.float32)
+    b = (20.0 * g.standard_normal((N,) + shape)).astype(np.float32)
+    dm = tnrd.DeviceModel.from_numpy(m)
+    o = tnrd.default_opts(impl=impl, prec=prec)
+    Aa = a.astype(np.float64) - tnrd.forward(_dev(a), dm, opts=o).cpu().numpy().astype(np.float64)
+    Ab = b.astype(np.float64) - tnrd.forward(_dev(b), dm, opts=o).cpu().numpy().astype(np.float64)
+    s1, s2 = float((Aa * b).sum()), float((a * Ab).sum())
+    scale = 0.5 * (np.abs(Aa * b).sum() + np.abs(a * Ab).sum())
+    S = 0.0
+    if prec != tnrd.PREC_FP32:
+        for n in range(N):
+            for i in range(nk):
+                k = m["filters"][0, i].astype(np.float64)
+                S += abs(slope[i]) * np.abs(oracle.conv(a[n], k) * oracle.conv(b[n], k)).sum()
+    bound = 1e-5 * scale + 2.0 * ADJ_ROUNDOFF[prec] * S
+    print(f"<A a, b> = {s1:.6e}, <a, A b> = {s2:.6e}, |diff| {abs(s1 - s2):.3e}, bound {bound:.3e}, "
+          f"|A a| / |a| = {np.linalg.norm(Aa) / np.linalg.norm(a):.3f}", flush=True)
+    assert np.linalg.norm(Aa) >= 0.05 * np.linalg.norm(a)
+    assert abs(s1 - s2) <= bound
