@@ -280,7 +280,7 @@ def _linear_influence_model(ks, nk, g, slope_std):
     return m
 
 
-ADJ_CASES = [(7, 48, (45, 37), 1), (5, 24, (7, 9), 2), (7, 40, (96, 130), 1)]
+ADJ_CASES = [(7, 48, (45, 37), 1), (5, 24, (7, 9), 2), (7, 40, (96, 130), 1), (7, 48, (512, 512), 1)]
 ADJ_PATHS = [(tnrd.IMPL_SPLIT, tnrd.PREC_FP32), (tnrd.IMPL_FUSED, tnrd.PREC_FP32),
              (tnrd.IMPL_FUSED, tnrd.PREC_BF16), (tnrd.IMPL_FUSED, tnrd.PREC_FP16)]
 ADJ_ROUNDOFF = {tnrd.PREC_FP32: 0.0, tnrd.PREC_BF16: 2.0 ** -8, tnrd.PREC_FP16: 2.0 ** -11}
@@ -289,17 +289,18 @@ ADJ_ROUNDOFF = {tnrd.PREC_FP32: 0.0, tnrd.PREC_BF16: 2.0 ** -8, tnrd.PREC_FP16: 
 @pytest.mark.parametrize("impl,prec", ADJ_PATHS)
 @pytest.mark.parametrize("ks,nk,shape,N", ADJ_CASES)
 def test_forward_diffusion_is_a_symmetric_operator(ks, nk, shape, N, impl, prec):
-    """Adjoint identity of the forward kernels' own K and K^T (eq. the diffusion step).
-    With linear influences phi_i(z) = s_i z and the quadratic reaction (which vanishes
-    at u_0 = f), one stage maps f to u_1 = f - sum_i s_i K_i^T K_i f, so A f = f - u_1 is
-    symmetric exactly when the K^T applied to the influences (the per-tile transpose,
-    the exchange across tiles and the border fold) is the adjoint of K: <A a, b> =
-    <a, A b> for random a, b.  An unflipped K^T breaks it by about 0.2 relative.  FP32
-    paths: 1e-5 relative.  BF16/FP16 operands round the influences once per element
-    (relative u, 2^-8 and 2^-11 taken with margin) while K and K^T share one rounded
-    filter, so the asymmetry stays below 2 u sum_i |s_i| sum_p |(K_i a)_p (K_i b)_p|
-    plus the FP32 term; the input's hi + lo split (relative 2^-18) sits inside the
-    factor-two margin on u."""
+    """Adjoint identity of the forward kernels' own K and K^T (Sec. 3.1, eq.
+    diffusionprocessfinal).  With linear influences phi_i(z) = s_i z and the quadratic
+    reaction (zero at u_0 = f), one stage maps f to u_1 = f - sum_i s_i K_i^T K_i f, so
+    A f = f - u_1 is symmetric exactly when the K^T applied to the influences (the
+    per-tile transpose, the exchange across tiles and the border fold) is the adjoint of
+    K: <A a, b> = <a, A b> for random a, b, also on one 512 x 512 image with 48 filters
+    in the launch configuration the forward picks there.  An unflipped K^T breaks it by
+    about 0.2 relative.  FP32 paths: 1e-5 relative.  BF16/FP16 operands round the
+    influences once per element (relative u, 2^-8 and 2^-11 taken with margin) while K
+    and K^T share one rounded filter, so the asymmetry stays below
+    2 u sum_i |s_i| sum_p |(K_i a)_p (K_i b)_p| plus the FP32 term; the input's hi + lo
+    split (relative 2^-18) sits inside the factor-two margin on u."""
     if prec != tnrd.PREC_FP32 and ks != 7:
         pytest.skip("BF16/FP16 operands are built for 7x7 filters")
     print(f"[fwd adjoint ks {ks} nk {nk} shape {shape} N {N} impl {impl} prec {prec}]", flush=True)
