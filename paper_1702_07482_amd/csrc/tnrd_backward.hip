@@ -169,8 +169,9 @@ k_bwd_params(
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const int img = blockIdx.x / tiles_per_img;
-    const int trem = blockIdx.x - img * tiles_per_img;
+    const int bid = xcd_tile_order((int)blockIdx.x, (int)gridDim.x);  // tile and partial slot
+    const int img = bid / tiles_per_img;
+    const int trem = bid - img * tiles_per_img;
     const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
     const int ty0 = ty * Th, tx0 = tx * Tw;
     const size_t plane = (size_t)H * W;
@@ -690,12 +691,12 @@ k_bwd_params(
     for (int o = 32; o >= 1; o >>= 1) dl_acc += __shfl_xor(dl_acc, o);
     if (lane == 0) sdl[wave] = dl_acc;
     __syncthreads();
-    float *dkp = io.dk_part + (size_t)blockIdx.x * Nk * KK;
+    float *dkp = io.dk_part + (size_t)bid * Nk * KK;
     for (int i = tid; i < Nk * KK; i += THREADS) dkp[i] = red[i];
     if (tid == 0) {
         float sum = 0.f;
         for (int w = 0; w < NW; ++w) sum += sdl[w];
-        io.dl_part[blockIdx.x] = sum;
+        io.dl_part[bid] = sum;
     }
 }
 

@@ -168,6 +168,17 @@ struct XTiles {
     int sw, sl;    // slab row pitch and floats per slab
 };
 
+// Tile of workgroup b in a 1-D grid of n tile workgroups.  The dispatcher deals
+// consecutive workgroups to the eight XCDs in turn (b on XCD b mod 8), each XCD with
+// its own L2; XCD x takes the contiguous run of tiles from x q + min(x, r) on
+// (q = n / 8, r = n mod 8), so that a tile's neighbours, whose slabs and halo
+// rows it reads, mostly run on its XCD.  A bijection of [0, n).
+__host__ __device__ inline int xcd_tile_order(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 __host__ __device__ inline XTiles make_xtiles(int H, int W, int th, int tw, int R)
 {
     XTiles x;

@@ -810,8 +810,9 @@ __global__ void __launch_bounds__(64 * NW) k_fused_stage(
     FusedRbf rb, const float *__restrict__ lam_t)
 {
     extern __shared__ float lds[];
-    const int img = blockIdx.x / tiles_per_img;
-    const int trem = blockIdx.x - img * tiles_per_img;
+    const int bid = xcd_tile_order((int)blockIdx.x, (int)gridDim.x);
+    const int img = bid / tiles_per_img;
+    const int trem = bid - img * tiles_per_img;
     const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
     const size_t plane = (size_t)H * W;
     FusedIO ii = io;  // per-image pointers below; every other field as launched
