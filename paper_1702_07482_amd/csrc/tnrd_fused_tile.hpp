@@ -54,6 +54,8 @@
 // X(o, x) = sum_a P[o][a][x + 2R] over the tap rows written by rows of the tile.
 #pragma once
 
+#include <type_traits>
+
 #include "tnrd_device.hpp"
 #include "tnrd_fused_common.hpp"
 #include "tnrd_internal.hpp"
@@ -618,9 +620,11 @@ __device__ __forceinline__ void fused_tile(
     //   P[(e - a) mod RING][a][qx + 2R] = sum_b Y_(a,b)[qx + b]   (qx relative to the row)
     // The scheduling fences split the work into NMB + 1 segments; in each, the
     // table reads of the next filter group and a third of the next GEMM1 are
-    // in flight while the current group's influence and GEMM2 run.
-    auto process = [&](int e, int cb, floatx4 *c1, const floatx4 *ca, float *xa, int en, int cbn,
-                       floatx4 *n1, floatx4 *na) {
+    // in flight while the current group's influence and GEMM2 run.  The wave's
+    // last block has no next block (next_c false): its instance leaves GEMM1 out.
+    auto process = [&](auto next_c, int e, int cb, floatx4 *c1, const floatx4 *ca, float *xa, int en,
+                       int cbn, floatx4 *n1, floatx4 *na) {
+        constexpr bool NEXT = decltype(next_c)::value;
         const int c = 16 * cb + j;
         const int xi = tx0 + c;
         const bool valid = (c < Ew) && (xi < W);
@@ -667,16 +671,16 @@ __device__ __forceinline__ void fused_tile(
         const float soff = valid ? (CUBIC ? 2.f * ((float)(RBF_WIN + 1) - rb.mu0_over_step) + 1.f
                                           : (float)(RBF_WIN + 1) - rb.mu0_over_step)
                                  : POLY_OFF_MASKED;
-        gemm1_load(en, cbn);
+        if constexpr (NEXT) gemm1_load(en, cbn);
         if (POLY) fetch(c1, 0, 0, sscale, soff);
-        gemm1_steps(0, K1 / NMB, n1, na);
+        if constexpr (NEXT) gemm1_steps(0, K1 / NMB, n1, na);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int m = 1; m <= NMB; ++m) {
             if (POLY && m < NMB) fetch(c1, m, m & 1, sscale, soff);
             influence(c1, ca, m - 1, valid);
             gemm2_group(c1, m - 1, acc2);
-            if (m < NMB) gemm1_steps(m * K1 / NMB, (m + 1) * K1 / NMB, n1, na);
+            if (NEXT && m < NMB) gemm1_steps(m * K1 / NMB, (m + 1) * K1 / NMB, n1, na);
             __builtin_amdgcn_sched_barrier(0);
         }
 
@@ -775,14 +779,26 @@ __device__ __forceinline__ void fused_tile(
             float xa[HB];
 #pragma unroll
             for (int h = 0; h < HB; ++h) xa[h] = 0.f;
-            // one basic block per row: the GEMM1 after the row's last block is
-            // that of the wave's next row (or a repeat of a row of this tile
-            // when there is none, whose result is dropped)
+            // the GEMM1 after the row's last block is that of the wave's next
+            // row.  After the wave's last block there is none.  The FP32 forward
+            // on two-block rows leaves it out there (a second instance of the
+            // block code), which pays where a wave has few blocks (8 on 32 x 32
+            // tiles); elsewhere the saving does not pay for the larger code, or
+            // the input-gradient mode lacks the registers, and a row of this
+            // tile is repeated there and its result dropped.
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) {
                 floatx4 n1[NMB], na[NMB];
                 const int en = cb + 1 < NB ? e : min(e + NW, e_hi - 1);
-                process(e, cb, c1, ca, xa, en, cb + 1 < NB ? cb + 1 : 0, n1, na);
+                const int cbn = cb + 1 < NB ? cb + 1 : 0;
+                if constexpr (MODE == MODE_FWD && PREC == PREC_F32 && NB == 2) {
+                    if (cb + 1 < NB || e + NW < e_hi)
+                        process(std::true_type{}, e, cb, c1, ca, xa, en, cbn, n1, na);
+                    else
+                        process(std::false_type{}, e, cb, c1, ca, xa, en, cbn, n1, na);
+                } else {
+                    process(std::true_type{}, e, cb, c1, ca, xa, en, cbn, n1, na);
+                }
 #pragma unroll
                 for (int mb = 0; mb < NMB; ++mb) {
                     c1[mb] = n1[mb];
