@@ -780,18 +780,19 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
             for (int h = 0; h < HB; ++h) xa[h] = 0.f;
             // the GEMM1 after the row's last block is that of the wave's next
-            // row.  After the wave's last block there is none.  The FP32 forward
-            // on two-block rows leaves it out there (a second instance of the
-            // block code), which pays where a wave has few blocks (8 on 32 x 32
-            // tiles); elsewhere the saving does not pay for the larger code, or
-            // the input-gradient mode lacks the registers, and a row of this
+            // row.  After the wave's last block there is none.  With FP32
+            // operands the forward on two-block rows and the input-gradient
+            // mode (two GEMM1s per block) on rows of up to three blocks leave it
+            // out there (a second instance of the block code), which pays where
+            // a wave has few blocks; elsewhere the saving does not pay for the
+            // larger code, or the registers are not there, and a row of this
             // tile is repeated there and its result dropped.
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) {
                 floatx4 n1[NMB], na[NMB];
                 const int en = cb + 1 < NB ? e : min(e + NW, e_hi - 1);
                 const int cbn = cb + 1 < NB ? cb + 1 : 0;
-                if constexpr (MODE == MODE_FWD && PREC == PREC_F32 && NB == 2) {
+                if constexpr (PREC == PREC_F32 && (MODE == MODE_FWD ? NB == 2 : NB <= 3)) {
                     if (cb + 1 < NB || e + NW < e_hi)
                         process(std::true_type{}, e, cb, c1, ca, xa, en, cbn, n1, na);
                     else
