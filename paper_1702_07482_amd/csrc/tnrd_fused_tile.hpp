@@ -236,10 +236,24 @@ __device__ __forceinline__ void fused_tile(
                 if (base + k * THREADS + tid < n) dst[base + k * THREADS + tid] = v[k];
         }
     }
+    // (2c) polynomial form: the prepared coefficient table straight into LDS in
+    // 256-float chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk).
+    // With FP32 operands it is issued first, so that it lands while the u tile
+    // is formed; the mixed kernels issue it after the u tile (measured faster).
+    constexpr bool TAB_FIRST = PREC == PREC_F32;
+    auto load_table = [&]() {
+        if (PREP_TAB && !io.keep_table) {
+            for (int c = wave; c * 256 < L.t_size; c += NW) {
+                const int k = c * 256 + 4 * lane;
+                if (k < L.t_size) __builtin_amdgcn_global_load_lds(io.prep + k, stab + c * 256, 16, 0, 0);
+            }
+        }
+    };
+    if (TAB_FIRST) load_table();
     // (2) the u tile (rows ty0-UO .. ty0+Th+UO-1, reflected at the border),
     // loaded straight into LDS in 64-word chunks (lane l of a wave fills word
     // l of its chunk).  The loads stay in flight while the filter registers
-    // and the coefficient table are set up; padding words get an in-image value.
+    // are set up; padding words get an in-image value.
     // Forward with the previous stage's reaction pending: u_{t-1} =
     // reaction(u_{t-2}, force gathered from the slabs, f) at every position of
     // the tile (own pixels also written back to io.u_keep for later stages).
@@ -268,7 +282,9 @@ __device__ __forceinline__ void fused_tile(
             xcol[c] = reflect_clamp(tx0 - UO + lx, W);
             xt[c] = col_terms<R>(io.xt, xcol[c]);
         }
-        constexpr int RU = 2;  // rows in flight per wave
+        // rows in flight per wave: a 32-row tile's 38 rows in one pass with FP32
+        // operands and the polynomial form; the others keep the registers
+        constexpr int RU = PREC == PREC_F32 && POLY ? 5 : 2;
         for (int ly0 = wave_u; ly0 < luh; ly0 += RU * NW) {
             float up[RU][NCX], ff[RU][NCX], xf[RU][NCX];
 #pragma unroll
@@ -305,14 +321,7 @@ __device__ __forceinline__ void fused_tile(
         // the padding word of each row (read by the mixed kernels' pad k-slots)
         for (int ly = tid; ly < luh; ly += THREADS) su[ly * L.ldw + luw] = 0.f;
     }
-    // (2c) polynomial form: the prepared coefficient table straight into LDS in
-    // 256-float chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk)
-    if (PREP_TAB && !io.keep_table) {
-        for (int c = wave; c * 256 < L.t_size; c += NW) {
-            const int k = c * 256 + 4 * lane;
-            if (k < L.t_size) __builtin_amdgcn_global_load_lds(io.prep + k, stab + c * 256, 16, 0, 0);
-        }
-    }
+    if (!TAB_FIRST) load_table();
     if (!PREP_OPS && !PREP_MOPS) __syncthreads();  // the staged filters (and Gaussian table)
 
     // Mixed-precision input gradient: e, a = K e and phi' a go through BF16/FP16
