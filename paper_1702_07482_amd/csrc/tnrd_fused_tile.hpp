@@ -238,9 +238,10 @@ __device__ __forceinline__ void fused_tile(
     }
     // (2c) polynomial form: the prepared coefficient table straight into LDS in
     // 256-float chunks (lane l fills floats 4l .. 4l+3 of its wave's chunk).
-    // With FP32 operands it is issued first, so that it lands while the u tile
-    // is formed; the mixed kernels issue it after the u tile (measured faster).
-    constexpr bool TAB_FIRST = PREC == PREC_F32;
+    // With FP32 operands and 7x7 filters it is issued first, so that it lands
+    // while the u tile is formed; the other instances issue it after the u tile
+    // (measured faster for them).
+    constexpr bool TAB_FIRST = PREC == PREC_F32 && KS == 7;
     auto load_table = [&]() {
         if (PREP_TAB && !io.keep_table) {
             for (int c = wave; c * 256 < L.t_size; c += NW) {
@@ -283,8 +284,9 @@ __device__ __forceinline__ void fused_tile(
             xt[c] = col_terms<R>(io.xt, xcol[c]);
         }
         // rows in flight per wave: a 32-row tile's 38 rows in one pass with FP32
-        // operands and the polynomial form; the others keep the registers
-        constexpr int RU = PREC == PREC_F32 && POLY ? 5 : 2;
+        // operands, 7x7 filters and the polynomial form; the others keep the
+        // registers
+        constexpr int RU = PREC == PREC_F32 && KS == 7 && POLY ? 5 : 2;
         for (int ly0 = wave_u; ly0 < luh; ly0 += RU * NW) {
             float up[RU][NCX], ff[RU][NCX], xf[RU][NCX];
 #pragma unroll
